@@ -1,0 +1,338 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each checks a closed form from
+the paper's model equations, a value the paper prints, an exact invariant, a
+special case with a known answer, or an independent brute-force computation.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import berry as orc
+from tests.phase_metrics import phase_set_error
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+S0 = np.eye(2)
+S1 = np.array([[0, 1], [1, 0]], dtype=complex)
+S2 = np.array([[0, -1j], [1j, 0]])
+S3 = np.diag([1.0, -1.0]).astype(complex)
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- Bloch H
+def _rand_k(rng, n, dim=3):
+    return rng.uniform(-1, 1, size=(n, dim))
+
+
+def test_bloch_h_matches_eq4_eq7_closed_forms():
+    rng = np.random.default_rng(1)
+    for kap in _rand_k(rng, 20):
+        kx, ky, kz = 2 * np.pi * kap
+        # eq. 4 with a general mass
+        for m in (1.5, -1.0):
+            Hc = np.sin(kx) * S1 + np.sin(ky) * S2 + (np.cos(kx) + np.cos(ky) + m) * S3
+            assert np.max(np.abs(orc.bloch_hamiltonian(syn.qwz(m), kap) - Hc)) < 1e-15
+        # eq. 7
+        Hb = (np.sin(kx) * np.kron(S1, S1) + np.sin(ky) * np.kron(S1, S2)
+              + (np.cos(kx) + np.cos(ky) + 1.5) * np.kron(S3, S0))
+        assert np.max(np.abs(orc.bloch_hamiltonian(syn.bhz(), kap) - Hb)) < 1e-15
+        # eq. 9
+        Hh = (np.sin(kx) * np.kron(S1, S1) + np.sin(ky) * np.kron(S1, S2) + np.sin(kz) * np.kron(S1, S3)
+              + (np.cos(kx) + np.cos(ky) + np.cos(kz) - 1.5) * np.kron(S3, S0)
+              + 1.0 * (np.cos(kx) - np.cos(ky)) * np.kron(S2, S0))
+        assert np.max(np.abs(orc.bloch_hamiltonian(syn.choti(1.0), kap) - Hh)) < 1e-15
+
+
+def test_bloch_h_bbh_closed_form():
+    g, l = 0.5, 1.0
+    G1, G2, G3, G4 = syn.models.bbh_gammas()
+    # Gamma matrices anticommute pairwise and square to one (Clifford algebra)
+    Gs = [G1, G2, G3, G4]
+    for a in range(4):
+        for b in range(4):
+            ac = Gs[a] @ Gs[b] + Gs[b] @ Gs[a]
+            assert np.allclose(ac, 2 * np.eye(4) * (a == b))
+    rng = np.random.default_rng(2)
+    for kap in _rand_k(rng, 10, 2):
+        kx, ky = 2 * np.pi * kap
+        Hc = ((g + l * np.cos(kx)) * G4 + l * np.sin(kx) * G3
+              + (g + l * np.cos(ky)) * G2 + l * np.sin(ky) * G1)
+        assert np.max(np.abs(orc.bloch_hamiltonian(syn.bbh(g, l), kap) - Hc)) < 1e-15
+
+
+def test_bloch_h_hermitian_bruteforce_all_models():
+    rng = np.random.default_rng(3)
+    models = [syn.qwz(-1), syn.bhz(), syn.bbh(), syn.bhz_disordered(3, 2.0, [9, 9]),
+              syn.bhz_vacancies(4, 0.1, [9, 1]), syn.wannier_like(8, [9, 2])]
+    for hl in models:
+        for kap in _rand_k(rng, 3):
+            H = orc.bloch_hamiltonian(hl, kap)
+            assert np.max(np.abs(H - H.conj().T)) <= 1e-14 * np.sum(np.abs(hl.t))
+
+
+def test_supercell_band_folding():
+    """Eigenvalues of the clean L x L supercell are the unit-cell bands at folded k."""
+    L = 3
+    cell = syn.bhz()
+    sc = syn.supercell(cell, L)
+    rng = np.random.default_rng(4)
+    for kap in _rand_k(rng, 4, 2):
+        ev_sc = np.linalg.eigvalsh(orc.bloch_hamiltonian(sc, kap))
+        ev_cell = []
+        for a in range(L):
+            for b in range(L):
+                ev_cell.append(np.linalg.eigvalsh(orc.bloch_hamiltonian(cell, (kap + np.array([a, b])) / L)))
+        ev_cell = np.sort(np.concatenate(ev_cell))
+        assert np.max(np.abs(ev_sc - ev_cell)) < 1e-13
+
+
+def test_vacancy_and_disorder_counts():
+    hl = syn.bhz_vacancies(10, 0.02, [4, 1, 0])
+    assert hl.N == 4 * (100 - 2)
+    hl = syn.bhz_disordered(10, 3.0, [3, 3, 0])
+    assert hl.N == 400
+    wl = syn.wannier_like(6, [5, 2, 0])
+    assert wl.meta["n_R"] == 29
+
+
+# ---------------------------------------------------------------- eigensolver
+def test_jacobi_matches_lapack_small():
+    rng = np.random.default_rng(5)
+    mats = []
+    for n in (1, 2, 3, 5, 8, 16):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        mats.append(A + A.conj().T)
+    mats.append(orc.bloch_hamiltonian(syn.supercell(syn.bhz(), 2), [0.13, 0.31]))
+    for H in mats:
+        wj, Vj = orc.jacobi_eigh(H)
+        w, V = np.linalg.eigh(H)
+        assert np.max(np.abs(wj - w)) < 1e-13 * max(1, np.max(np.abs(w)))
+        assert np.max(np.abs(H @ Vj - Vj * wj)) < 1e-12 * max(1, np.max(np.abs(w)))
+
+
+def test_qwz_eigenvalues_closed_form_and_residual():
+    rng = np.random.default_rng(6)
+    for kap in _rand_k(rng, 10, 2):
+        kx, ky = 2 * np.pi * kap
+        d = np.array([np.sin(kx), np.sin(ky), 1.5 + np.cos(kx) + np.cos(ky)])
+        H = orc.bloch_hamiltonian(syn.qwz(1.5), kap)
+        w, U, st = orc.eigh_bands(H, 0, 1)
+        assert abs(w[0] + np.linalg.norm(d)) < 1e-14 and abs(w[1] - np.linalg.norm(d)) < 1e-14
+        assert np.max(np.abs(H @ U - U * w[0])) < 1e-14
+        assert abs(np.trace(U @ U.conj().T).real - 1) < 1e-14
+
+
+def test_gap_closed_flag():
+    H = orc.bloch_hamiltonian(syn.atomic([0.0, 0.0, 1.0]), [0, 0])
+    _, _, st = orc.eigh_bands(H, 0, 1)
+    assert st & orc.GAP_CLOSED
+
+
+# ---------------------------------------------------------------- Wilson loop
+def test_chern_number_of_eq4_matches_paper():
+    g = golden()["qwz_m1p5_chern"]
+    kg = syn.kplane(48, 48, e_par=(1, 0, 0), e_perp=(0, 1, 0))
+    out = orc.wilson_surface(syn.qwz(1.5), kg, 0, 1)
+    assert out["status"] == 0
+    assert out["winding"] == g["value"]
+
+
+@pytest.mark.parametrize("m,axis,expect", [
+    (2.5, "x", 0),      # |m| > 2: trivial
+    (-1.0, "x", -1),    # H(k + (pi, pi); m) = -H(k; -m): C(-m) = -C(m)
+    (-1.0, "y", +1),    # exchanging loop and transverse axes flips the orientation
+    (1.5, "y", -1),
+])
+def test_qwz_windings_from_symmetry(m, axis, expect):
+    ex, ey = (1, 0, 0), (0, 1, 0)
+    e_par, e_perp = (ex, ey) if axis == "x" else (ey, ex)
+    kg = syn.kplane(40, 40, e_par=e_par, e_perp=e_perp)
+    out = orc.wilson_surface(syn.qwz(m), kg, 0, 1)
+    assert out["status"] == 0 and out["winding"] == expect
+
+
+def test_ssh_berry_phase_is_pi_or_zero():
+    for (v, w, expect) in [(0.3, 1.0, np.pi), (1.0, 0.3, 0.0)]:
+        kg = syn.kplane(64, 1, e_par=(1, 0, 0), e_perp=(0, 0, 0))
+        out = orc.wilson_surface(syn.ssh(v, w), kg, 0, 1)
+        assert phase_set_error(out["theta"], np.full((1, 1), expect)) < 1e-12
+
+
+def test_bond_shift_raw_modulus_closed_form():
+    """Lower state (1, e^{ik})/sqrt2: raw product = prod (1 + e^{-i dk})/2 = -cos^n(pi/n)."""
+    n = 16
+    kg = syn.kplane(n, 1, e_par=(1, 0, 0), e_perp=(0, 0, 0))
+    _, U, _ = orc.eigh_grid(syn.bond_shift_1d(), kg, 0, 1)
+    Wr, _ = orc.wilson_matrix(U[0], "raw")
+    assert abs(Wr[0, 0] - (-np.cos(np.pi / n) ** n)) < 1e-14
+    Wp, _ = orc.wilson_matrix(U[0], "polar")
+    assert abs(Wp[0, 0] - (-1.0)) < 1e-14
+
+
+def test_atomic_limit_trivial():
+    kg = syn.kplane(8, 8)
+    out = orc.wilson_surface(syn.atomic([-1.0, -0.5, 2.0]), kg, 0, 2)
+    assert np.max(np.abs(out["theta"])) < 1e-14 and out["winding"] == 0
+
+
+def test_unitarity_trace_and_gauge_invariance():
+    hl = syn.bhz_disordered(2, 1.0, [1, 2, 3])
+    kg = syn.kplane(10, 6)
+    ev, U, st = orc.eigh_grid(hl, kg, 0, hl.N // 2)
+    m = hl.N // 2
+    for i in range(kg.shape[0]):
+        W, _ = orc.wilson_matrix(U[i])
+        assert np.max(np.abs(W.conj().T @ W - np.eye(m))) < 1e-12
+    P = U[0, 0] @ U[0, 0].conj().T
+    assert abs(np.trace(P).real - m) < 1e-12
+    th0, _, C0, _ = orc.wilson_loop_grid(U)
+    rng = np.random.default_rng(7)
+    Ug = U.copy()
+    for i in range(U.shape[0]):
+        for j in range(U.shape[1]):
+            G, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+            Ug[i, j] = U[i, j] @ G
+    th1, _, C1, _ = orc.wilson_loop_grid(Ug)
+    assert phase_set_error(th0, th1) < 1e-12 and C0 == C1
+
+
+def test_raw_vs_polar_det_identity():
+    hl = syn.bhz_disordered(2, 2.0, [2, 2, 2])
+    kg = syn.kplane(8, 4)
+    _, U, _ = orc.eigh_grid(hl, kg, 0, hl.N // 2)
+    tp, php, _, _ = orc.wilson_loop_grid(U, "polar")
+    tr, phr, _, _ = orc.wilson_loop_grid(U, "raw")
+    d = np.mod(php - phr + np.pi, 2 * np.pi) - np.pi
+    assert np.max(np.abs(d)) < 1e-13
+    # m = 1: the polar factor of a 1x1 overlap is its phase, so theta agrees exactly
+    _, U1, _ = orc.eigh_grid(syn.qwz(1.5), syn.kplane(12, 5), 0, 1)
+    assert phase_set_error(orc.wilson_loop_grid(U1, "raw")[0], orc.wilson_loop_grid(U1, "polar")[0]) < 1e-13
+
+
+def test_eigphases_two_by_two_closed_form():
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        Q, _ = np.linalg.qr(rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2)))
+        tr, det = np.trace(Q), np.linalg.det(Q)
+        disc = np.sqrt(tr * tr - 4 * det)
+        lam = np.array([(tr + disc) / 2, (tr - disc) / 2])
+        expect = np.sort(np.angle(lam))
+        assert phase_set_error(orc.eigphases(Q)[None], expect[None]) < 1e-13
+
+
+def test_uniform_grid_shift_preserves_winding():
+    kg = syn.kplane(40, 40, k0=(0.013, 0.021, 0))
+    assert orc.wilson_surface(syn.qwz(1.5), kg, 0, 1)["winding"] == 1
+
+
+def test_bhz_wcc_spectrum_gapless():
+    assert golden()["bhz_wcc_gapless"]["value"] is True
+    kg = syn.kplane(40, 40)
+    out = orc.wilson_surface(syn.bhz(), kg, 0, 2)
+    x = np.sort(np.mod(out["theta"].ravel() / (2 * np.pi), 1.0))
+    gaps = np.diff(np.concatenate([x, [x[0] + 1]]))
+    assert gaps.max() < 0.1   # the centres sweep the whole unit interval
+
+
+# ---------------------------------------------------------------- nested loop
+def test_bbh_nested_polarization_half():
+    kg = syn.kplane(40, 40)
+    out = orc.nested_wilson(syn.bbh(0.5, 1.0), kg, 0, 2)
+    assert out["status"] == 0 and out["s"] == 1
+    assert np.max(np.abs(np.abs(out["p"]) - 0.5)) < 1e-12
+    assert abs(out["p_mean"] - 0.5) < 1e-12
+    # Wannier bands of the first loop come in +-nu pairs
+    th = orc.wilson_surface(syn.bbh(0.5, 1.0), kg, 0, 2)["theta"]
+    assert np.max(np.abs(th[:, 0] + th[:, 1])) < 1e-12
+
+
+def test_bbh_trivial_control_zero():
+    kg = syn.kplane(24, 24)
+    out = orc.nested_wilson(syn.bbh(1.5, 1.0), kg, 0, 2)
+    assert out["status"] == 0
+    assert np.max(np.abs(out["p"])) < 1e-12 and min(out["p_mean"], 1 - out["p_mean"]) < 1e-12
+
+
+def test_nested_sector_selection_two_sectors():
+    """Direct sum of two rank-one product models with centres near +0.3 and -0.3.
+
+    The (0, 1/2) sector is the first model, whose y Berry phase is pi (p = 1/2);
+    the (-1/2, 0) sector is the second, with no y dependence (p = 0).
+    """
+    hl = syn.concat_hops([syn.product_state_2d(0.7, 0.5), syn.product_state_2d(0.3, 0.0)])
+    kg = syn.kplane(16, 12)
+    out = orc.nested_wilson(hl, kg, 0, 2, window=(0.0, 0.5))
+    assert out["status"] == 0 and out["s"] == 1
+    assert abs(out["p_mean"] - 0.5) < 1e-12
+    out = orc.nested_wilson(hl, kg, 0, 2, window=(-0.5, 0.0))
+    assert out["status"] == 0 and out["s"] == 1
+    assert min(out["p_mean"], 1 - out["p_mean"]) < 1e-12
+
+
+# ---------------------------------------------------------------- spin-resolved
+def test_bhz_spin_chern():
+    conv = golden()["spin_chern_sign_convention"]["value"]
+    kg = syn.kplane(32, 32)
+    out = orc.spin_resolved_wilson(syn.bhz(), np.array([1.0, -1, -1, 1]), kg, 0, 2)
+    assert out["status"] == 0
+    assert np.max(np.abs(np.abs(out["mu"]) - 1)) < 1e-13
+    assert out["C_dn"] == conv["C_dn"] and out["C_s"] == conv["C_s"] and out["C_up"] == 1
+    assert orc.wilson_surface(syn.bhz(), kg, 0, 2)["winding"] == 0
+
+
+def test_spin_block_reduction_clean_and_disordered():
+    """With [H, S_z] = 0 the S_z = -1 sector is a model of its own.
+
+    The spin-down Wilson loop from the projected spin operator must equal the
+    plain Wilson loop of the sub-Hamiltonian on the S_z = -1 orbitals.
+    """
+    def restrict(hl, keep_mask):
+        keep = np.nonzero(keep_mask)[0]
+        cmap = -np.ones(hl.N, dtype=np.int64)
+        cmap[keep] = np.arange(keep.size)
+        sel = keep_mask[hl.i] & keep_mask[hl.j]
+        return syn.HopList(N=keep.size, dim=hl.dim, i=cmap[hl.i[sel]].astype(np.int32),
+                           j=cmap[hl.j[sel]].astype(np.int32), R=hl.R[sel], t=hl.t[sel])
+
+    for hl in (syn.bhz(), syn.bhz_disordered(2, 2.0, [6, 1, 0])):
+        sd = syn.bhz_spin_diag(hl)
+        kg = syn.kplane(16, 12)
+        m = hl.N // 2
+        out = orc.spin_resolved_wilson(hl, sd, kg, 0, m)
+        dn = restrict(hl, sd < 0)
+        up = restrict(hl, sd > 0)
+        ref_dn = orc.wilson_surface(dn, kg, 0, dn.N // 2)
+        ref_up = orc.wilson_surface(up, kg, 0, up.N // 2)
+        assert out["status"] == 0
+        assert phase_set_error(out["theta_dn"], ref_dn["theta"]) < 1e-12
+        assert phase_set_error(out["theta_up"], ref_up["theta"]) < 1e-12
+        assert out["C_dn"] == ref_dn["winding"] and out["C_up"] == ref_up["winding"]
+    # clean BHZ down block is QWZ(kx, -ky): theta_dn(ky_i) = theta_QWZ(ky_{n-i})
+    kg = syn.kplane(16, 12)
+    out = orc.spin_resolved_wilson(syn.bhz(), np.array([1.0, -1, -1, 1]), kg, 0, 2)
+    q = orc.wilson_surface(syn.qwz(1.5), kg, 0, 1)["theta"]
+    n = kg.shape[0]
+    flipped = q[[(n - i) % n for i in range(n)]]
+    assert phase_set_error(out["theta_dn"], flipped) < 1e-12
+
+
+def test_choti_spin_chern_matches_paper():
+    g = golden()["choti_kz0_abs_spin_chern"]
+    kg = syn.kplane(32, 32)
+    hl = syn.choti(1.0)
+    out = orc.spin_resolved_wilson(hl, np.array([1.0, -1, -1, 1]), kg, 0, 2)
+    assert out["status"] == 0
+    assert abs(out["C_s"]) == g["value"]
+    assert np.max(np.abs(np.abs(out["mu"]) - 1)) > 1e-3   # spin not conserved here
+    # the plain WCC spectrum is gapped at kz = 0 (Sec. III)
+    th = orc.wilson_surface(hl, kg, 0, 2)["theta"]
+    x = np.sort(np.mod(th.ravel() / (2 * np.pi), 1.0))
+    gaps = np.diff(np.concatenate([x, [x[0] + 1]]))
+    assert gaps.max() > 0.2
