@@ -1,0 +1,216 @@
+/*
+ * berryhip -- batched Wilson-loop engine for MI355X (gfx950).
+ *
+ * C ABI of the hot path: Bloch Hamiltonians from a hopping list, batched
+ * Hermitian eigensolver, Wilson loops, nested Wilson loops and
+ * spin-resolved Wilson loops. The method is that of BerryEasy
+ * (arXiv:2312.13051); each entry point names the passage it implements.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Complex numbers are interleaved (re, im) pairs: "c128" is double2,
+ *   "c64" is float2. Matrices are column-major with a leading dimension.
+ * - Pointers suffixed _h are host memory; all other array pointers are
+ *   device memory owned by the caller. The library never frees caller memory.
+ * - Every call is asynchronous on the given stream unless its comment says
+ *   it synchronizes. Outputs are valid once the stream has completed.
+ * - Return value: BE_OK (0) or a negative error code; be_last_error() gives
+ *   text. Argument errors are detected on the host before any launch.
+ * - Physics conditions (closed gaps, singular overlaps, ...) are never
+ *   errors: they set bits in a per-item status word (BE_ST_*). A result is
+ *   valid when its status is 0.
+ * - A context (be_ctx) owns a device workspace that grows on demand; growing
+ *   synchronizes the stream once. Use one context per host thread.
+ *
+ * k-point grids ("U-grids")
+ * ------------------------
+ * Wilson-loop calls take the selected eigenvectors of every point of a
+ * k-plane, U[s][i][j] for system s, transverse index i < n_perp and loop
+ * index j < n_par, at kappa = k0 + (j/n_par) e_par + (i/n_perp) e_perp
+ * (fractional coordinates of the (super)cell reciprocal basis). Matrix
+ * (s, i, j) starts at element ((s*n_perp + i)*n_par + j) * u_stride of U,
+ * is N x m with leading dimension ldu. The loop closes on itself: the point
+ * j = n_par is j = 0 (lattice gauge, H(kappa + G) = H(kappa)).
+ */
+#ifndef BERRYHIP_H
+#define BERRYHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define BE_OK 0
+#define BE_EINVAL (-1)   /* bad argument: null pointer, size out of range   */
+#define BE_ENOMEM (-2)   /* device workspace allocation failed              */
+#define BE_EHIP (-3)     /* a HIP runtime call failed (text in last_error)  */
+#define BE_ENOTIMPL (-4) /* combination of options not implemented          */
+
+/* ---- element types ---- */
+#define BE_C128 0 /* complex double */
+#define BE_C64 1  /* complex float  */
+
+/* ---- precision of the eigensolver ---- */
+#define BE_FP64 0       /* everything in FP64                                   */
+#define BE_MIXED_FP32 1 /* FP32 Householder reduction and back-transformation on
+                           MFMA with FP32 accumulation; FP64 tridiagonal solve,
+                           FP64 re-orthonormalization of the eigenvectors       */
+
+/* ---- overlap mode ---- */
+#define BE_OVL_POLAR 0 /* each overlap replaced by its unitary polar factor */
+#define BE_OVL_RAW 1   /* raw overlaps, as printed in eq. 2                 */
+
+/* ---- status bits (per matrix or per system) ---- */
+#define BE_ST_GAP_CLOSED 1u         /* selected bands touch their neighbours       */
+#define BE_ST_OVERLAP_SINGULAR 2u   /* an overlap has smallest singular value < 1e-8 */
+#define BE_ST_WINDING_UNRESOLVED 4u /* transverse step of Phi > 0.8 pi or non-integer */
+#define BE_ST_PSO_GAP 8u            /* projected spin spectrum touches 0 or its sign
+                                       count varies over the grid                  */
+#define BE_ST_WANNIER_GAP 16u       /* a Wilson phase sits on a sector window edge,
+                                       or the sector size varies                   */
+#define BE_ST_NONCONVERGED 32u      /* an iteration hit its cap                     */
+#define BE_ST_NAN_INF 64u           /* non-finite input or intermediate             */
+
+typedef struct be_ctx be_ctx;
+typedef struct be_hk_plan be_hk_plan;
+
+/* Hopping list of one (super)cell, host memory.
+ * Entry e is the amplitude t[e] (interleaved re, im) from orbital j[e] in the
+ * cell at integer lattice vector R[e*dim .. e*dim+dim-1] to orbital i[e] in
+ * the home cell. The list must be Hermitian: after adding duplicate
+ * (i, j, R) keys, every (i, j, R, t) must have the partner (j, i, -R, conj t)
+ * (relative tolerance 1e-12). 1 <= dim <= 3, 0 <= i, j < N. */
+typedef struct {
+  int32_t N;
+  int32_t dim;
+  int64_t nnz;
+  const int32_t *i;
+  const int32_t *j;
+  const int32_t *R;
+  const double *t;
+} be_hoplist;
+
+/* Create a context on HIP device `device` (the device becomes current on
+ * the calling thread). */
+int be_create(be_ctx **ctx, int device);
+/* Destroy a context and free its workspace. Waits for the device. */
+int be_destroy(be_ctx *ctx);
+/* Text of the last error on this context (never NULL). */
+const char *be_last_error(const be_ctx *ctx);
+/* Bytes of device workspace currently held by the context. */
+size_t be_workspace_bytes(const be_ctx *ctx);
+
+/* Row (a1) -- model to device hopping list.
+ * Packs n_sys hopping lists: merges duplicate (i, j, R) keys, checks that
+ * each list is Hermitian, keeps the upper triangle (i <= j) sorted by
+ * (j, i, R) and uploads it. Synchronous. The plan is independent of later
+ * calls and may be reused for any number of k-points.
+ * Errors: BE_EINVAL (bad sizes, index out of range, non-Hermitian list). */
+int be_hk_plan_create(be_ctx *ctx, const be_hoplist *sys_h, int32_t n_sys, be_hk_plan **plan);
+int be_hk_plan_destroy(be_hk_plan *plan);
+/* Orbital count of system s of a plan (or -1). */
+int32_t be_hk_plan_N(const be_hk_plan *plan, int32_t s);
+
+/* Row (a2) -- Bloch Hamiltonians (Sec. II-A: Bloch sum with periodic
+ * boundary conditions at the (super)cell period; supercells use the
+ * reciprocal basis of the supercell, the 2pi -> 2pi/L rule).
+ * Builds n_sys_call * n_kap matrices: matrix q = s_local*n_kap + k belongs to
+ * system sys_first + s_local of the plan and to the fractional k-point
+ * kappa[3k .. 3k+2] (device, float64; components beyond the system's dim are
+ * ignored):
+ *   H_q[a, b] = sum_e t_e exp(2 pi i kappa_k . R_e) over entries (a, b, R_e).
+ * Matrix q is written at H + q*mat_stride elements, column-major with
+ * leading dimension ld >= N; rows N..ld-1 are left untouched. Only the upper
+ * triangle is summed; the lower triangle is its exact conjugate and the
+ * diagonal is exactly real, so H is bitwise Hermitian, and every element is
+ * summed by one thread in a fixed order, so H is deterministic. All systems
+ * of one call must have the same N. dtype: BE_C128 or BE_C64 (phases and sums
+ * in FP64, one rounding at the store). */
+int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t n_sys_call, const double *kappa,
+                int32_t n_kap, void *H, int64_t mat_stride, int32_t ld, int32_t dtype, hipStream_t stream);
+
+/* Rows (a3)-(a5) -- batched Hermitian eigensolver (Sec. I: exact
+ * diagonalization at many k-points; the selected bands, eq. 2).
+ * n_mat matrices of order N (H + q*mat_stride, leading dimension ld, BE_C128
+ * for BE_FP64 or BE_C64 for BE_MIXED_FP32). Both triangles are read and must
+ * hold the same Hermitian matrix (as be_build_hk writes it). H is overwritten
+ * (its columns hold the Householder vectors afterwards).
+ * Steps: blocked Householder reduction to real tridiagonal form (panel
+ * kernel + MFMA rank-2k trailing updates), FP64 bisection for eigenvalues
+ * [lo-1, hi], FP64 inverse iteration with re-orthogonalization inside
+ * clusters for bands [lo, hi), back-transformation with compact-WY blocks on
+ * MFMA, and (mixed path) FP64 Cholesky-QR re-orthonormalization.
+ * Outputs:
+ *   evals[q*(m+2) + 0]     eigenvalue lo-1 (NaN if lo == 0)
+ *   evals[q*(m+2) + 1 + c] eigenvalue lo+c, c < m = hi-lo
+ *   evals[q*(m+2) + m + 1] eigenvalue hi   (NaN if hi == N)
+ *   U + q*u_stride: N x m eigenvectors (c128), leading dimension ldu >= N;
+ *   status[q]: BE_ST_GAP_CLOSED if min gap at lo or hi < 1e-9 max(1, |lambda|max),
+ *              BE_ST_NAN_INF, BE_ST_NONCONVERGED.
+ * Eigenvectors are unique only up to a unitary inside degenerate sets; the
+ * occupied projector U U^H is the gauge-invariant output. */
+int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, int64_t mat_stride,
+                    int32_t n_mat, int32_t band_lo, int32_t band_hi, int32_t precision, double *evals,
+                    void *U, int32_t ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
+
+/* Rows (a6)-(a8) -- Wilson loop over a U-grid (eq. 2 with the path ordering
+ * of eq. 1, hybrid centres of eq. 3, Chern winding of eq. 6).
+ *   F_j = U(kappa_{j+1})^H U(kappa_j), j < n_par (closing to j = 0);
+ *   mode BE_OVL_POLAR replaces F_j by its unitary polar factor (FP64);
+ *   W_i = F_{n_par-1} ... F_0;   theta_i = arg eig(W_i) in (-pi, pi],
+ *   ascending;  Phi_i = sum_n theta_{i,n} mod 2pi;
+ *   winding = (1/2pi) sum_i wrap(Phi_{(i+1) mod n_perp} - Phi_i).
+ * U is c128. Outputs (device): theta [n_sys][n_perp][m], phi [n_sys][n_perp],
+ * winding [n_sys], status [n_sys] (OVERLAP_SINGULAR, WINDING_UNRESOLVED,
+ * NONCONVERGED). */
+int be_wilson_loop(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                   int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, double *theta, double *phi,
+                   int32_t *winding, uint32_t *status, hipStream_t stream);
+
+/* Row (a9) -- nested Wilson loop (Sec. III, eq. 8).
+ * The Wilson loop of each transverse line is diagonalized at base point 0;
+ * its eigenvectors with x = theta/2pi in the open window (win_lo, win_hi)
+ * form the Wannier sector (size s). They are carried to every base point j
+ * by the path-ordered overlaps, w_{i,j} = U_{i,j} nu_S^{(i,j)}, and a second
+ * Wilson loop runs along the transverse direction at every j:
+ *   nested_theta [n_sys][n_par][m] (first s entries valid, ascending),
+ *   p [n_sys][n_par] = sum nested_theta / 2pi in (-1/2, 1/2],
+ *   p_mean [n_sys] = mean of p unwrapped along j, reduced to [0, 1),
+ *   s_out_h [n_sys] (host) sector sizes, status [n_sys] (WANNIER_GAP, ...).
+ * Synchronizes the stream once (the sector size is read back). */
+int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                     int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, double win_lo, double win_hi,
+                     double *nested_theta, double *p, double *p_mean, int32_t *s_out_h, uint32_t *status,
+                     hipStream_t stream);
+
+/* Row (a10) -- spin-resolved Wilson loop (Sec. IV; sign convention of Sec. V).
+ * Projected spin operator in the occupied space, A = U^H S U with
+ * S = diag(spin_diag[s*N .. s*N+N-1]) (device, float64), eigh(A) = (mu, Q);
+ * V_minus = U Q[:, mu < 0] (spin down), V_plus = U Q[:, mu > 0] (spin up);
+ * Wilson loop and winding of each sector:
+ *   pso_evals [n_sys][n_perp][n_par][m] (ascending mu),
+ *   theta_dn [n_sys][n_perp][m], theta_up [n_sys][n_perp][m] (first
+ *   m_dn_h[s] resp. m - m_dn_h[s] entries valid), C_dn, C_up [n_sys] (int32),
+ *   C_s [n_sys] = (C_up - C_dn)/2, m_dn_h [n_sys] (host), status [n_sys]
+ *   (PSO_GAP if min |mu| < 1e-6 or the count of mu < 0 varies).
+ * Synchronizes the stream once (the sector sizes are read back). */
+int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                            int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, const double *spin_diag,
+                            double *pso_evals, double *theta_dn, double *theta_up, int32_t *C_dn, int32_t *C_up,
+                            double *C_s, int32_t *m_dn_h, uint32_t *status, hipStream_t stream);
+
+/* Utility kernel exposed for tests: batched complex GEMM on MFMA,
+ *   C_q = alpha op(A_q) op(B_q) + beta C_q,   op = 'N' (none) or 'C'
+ * (conjugate transpose), c128, strided batches (element strides). */
+int be_zgemm_strided(be_ctx *ctx, char opA, char opB, int32_t M, int32_t Ncol, int32_t K, const double *alpha2_h,
+                     const void *A, int32_t lda, int64_t strideA, const void *B, int32_t ldb, int64_t strideB,
+                     const double *beta2_h, void *C, int32_t ldc, int64_t strideC, int32_t batch, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BERRYHIP_H */

@@ -1,0 +1,188 @@
+"""ctypes binding of libberryhip (argument marshalling only).
+
+Every function here forwards device pointers, sizes and the current torch
+stream to the C ABI declared in ``include/berryhip.h``; all computation runs in
+the library's HIP kernels. PyTorch provides device memory and streams only.
+The library must have been built (``paper_2312_13051_amd/build.py``); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libberryhip.so")
+
+BE_OK, BE_EINVAL, BE_ENOMEM, BE_EHIP, BE_ENOTIMPL = 0, -1, -2, -3, -4
+BE_C128, BE_C64 = 0, 1
+BE_FP64, BE_MIXED_FP32 = 0, 1
+BE_OVL_POLAR, BE_OVL_RAW = 0, 1
+ST_GAP_CLOSED, ST_OVERLAP_SINGULAR, ST_WINDING_UNRESOLVED = 1, 2, 4
+ST_PSO_GAP, ST_WANNIER_GAP, ST_NONCONVERGED, ST_NAN_INF = 8, 16, 32, 64
+
+EXPORTS = [
+    "be_create", "be_destroy", "be_last_error", "be_workspace_bytes",
+    "be_hk_plan_create", "be_hk_plan_destroy", "be_hk_plan_N",
+    "be_build_hk", "be_eigh_batched", "be_wilson_loop", "be_nested_wilson",
+    "be_spin_resolved_wilson", "be_zgemm_strided",
+]
+
+
+class be_hoplist(C.Structure):
+    _fields_ = [("N", C.c_int32), ("dim", C.c_int32), ("nnz", C.c_int64),
+                ("i", C.c_void_p), ("j", C.c_void_p), ("R", C.c_void_p), ("t", C.c_void_p)]
+
+
+class BerryError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libberryhip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BerryError(f"{LIB_PATH} is missing: run `python paper_2312_13051_amd/build.py` first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64p = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.be_create.argtypes = [C.POINTER(vp), C.c_int]
+    lib.be_destroy.argtypes = [vp]
+    lib.be_last_error.argtypes = [vp]
+    lib.be_last_error.restype = C.c_char_p
+    lib.be_workspace_bytes.argtypes = [vp]
+    lib.be_workspace_bytes.restype = C.c_size_t
+    lib.be_hk_plan_create.argtypes = [vp, C.POINTER(be_hoplist), i32, C.POINTER(vp)]
+    lib.be_hk_plan_destroy.argtypes = [vp]
+    lib.be_hk_plan_N.argtypes = [vp, i32]
+    lib.be_hk_plan_N.restype = i32
+    lib.be_build_hk.argtypes = [vp, vp, i32, i32, vp, i32, vp, i64, i32, i32, vp]
+    lib.be_eigh_batched.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, vp, vp, i32, i64, vp, vp]
+    lib.be_wilson_loop.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.be_nested_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, C.c_double, C.c_double,
+                                     vp, vp, vp, C.POINTER(i32), vp, vp]
+    lib.be_spin_resolved_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, vp,
+                                            vp, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp]
+    lib.be_zgemm_strided.argtypes = [vp, C.c_char, C.c_char, i32, i32, i32, f64p, vp, i32, i64, vp, i32, i64,
+                                     f64p, vp, i32, i64, i32, vp]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype if name in (
+            "be_last_error", "be_workspace_bytes", "be_hk_plan_N") else C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class HkPlan:
+    """Device copy of packed hopping lists (be_hk_plan)."""
+
+    def __init__(self, ctx: "Context", hoplists):
+        self.ctx = ctx
+        self._keep = []
+        arr = (be_hoplist * len(hoplists))()
+        for k, h in enumerate(hoplists):
+            i = np.ascontiguousarray(h.i, dtype=np.int32)
+            j = np.ascontiguousarray(h.j, dtype=np.int32)
+            R = np.ascontiguousarray(h.R, dtype=np.int32)
+            t = np.ascontiguousarray(np.asarray(h.t, dtype=np.complex128).view(np.float64))
+            self._keep += [i, j, R, t]
+            arr[k] = be_hoplist(int(h.N), int(h.dim), int(h.t.shape[0]), i.ctypes.data, j.ctypes.data,
+                                R.ctypes.data, t.ctypes.data)
+        self.handle = C.c_void_p()
+        ctx._check(ctx.lib.be_hk_plan_create(ctx.handle, arr, len(hoplists), C.byref(self.handle)))
+        self.N = [int(ctx.lib.be_hk_plan_N(self.handle, k)) for k in range(len(hoplists))]
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.be_hk_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """One be_ctx on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.handle = C.c_void_p()
+        rc = self.lib.be_create(C.byref(self.handle), int(device))
+        if rc != BE_OK:
+            raise BerryError(f"be_create failed ({rc})")
+
+    def _check(self, rc):
+        if rc != BE_OK:
+            raise BerryError(f"berryhip error {rc}: {self.lib.be_last_error(self.handle).decode()}")
+
+    def close(self):
+        if self.handle:
+            self.lib.be_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.lib.be_workspace_bytes(self.handle))
+
+    # ------------------------------------------------------------ calls
+    def hk_plan(self, hoplists) -> HkPlan:
+        return HkPlan(self, hoplists)
+
+    def build_hk(self, plan: HkPlan, sys_first: int, n_sys: int, kappa, H, mat_stride: int, ld: int, dtype: int):
+        self._check(self.lib.be_build_hk(self.handle, plan.handle, sys_first, n_sys, _ptr(kappa), kappa.shape[0],
+                                         _ptr(H), mat_stride, ld, dtype, _stream()))
+
+    def eigh_batched(self, H, dtype, N, ld, mat_stride, n_mat, lo, hi, precision, evals, U, ldu, u_stride, status):
+        self._check(self.lib.be_eigh_batched(self.handle, _ptr(H), dtype, N, ld, mat_stride, n_mat, lo, hi,
+                                             precision, _ptr(evals), _ptr(U), ldu, u_stride, _ptr(status),
+                                             _stream()))
+
+    def wilson_loop(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, theta, phi, winding, status):
+        self._check(self.lib.be_wilson_loop(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp, mode,
+                                            _ptr(theta), _ptr(phi), _ptr(winding), _ptr(status), _stream()))
+
+    def nested_wilson(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, win_lo, win_hi, nested_theta, p,
+                      p_mean, status):
+        s_out = (C.c_int32 * n_sys)()
+        self._check(self.lib.be_nested_wilson(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp, mode,
+                                              win_lo, win_hi, _ptr(nested_theta), _ptr(p), _ptr(p_mean), s_out,
+                                              _ptr(status), _stream()))
+        return [int(x) for x in s_out]
+
+    def spin_resolved_wilson(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, spin_diag, pso_evals,
+                             theta_dn, theta_up, C_dn, C_up, C_s, status):
+        m_dn = (C.c_int32 * n_sys)()
+        self._check(self.lib.be_spin_resolved_wilson(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
+                                                     mode, _ptr(spin_diag), _ptr(pso_evals), _ptr(theta_dn),
+                                                     _ptr(theta_up), _ptr(C_dn), _ptr(C_up), _ptr(C_s), m_dn,
+                                                     _ptr(status), _stream()))
+        return [int(x) for x in m_dn]
+
+    def zgemm_strided(self, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cm, ldc, sC, batch):
+        a = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        b = (C.c_double * 2)(complex(beta).real, complex(beta).imag)
+        self._check(self.lib.be_zgemm_strided(self.handle, opA.encode(), opB.encode(), M, N, K, a, _ptr(A), lda, sA,
+                                              _ptr(B), ldb, sB, b, _ptr(Cm), ldc, sC, batch, _stream()))

@@ -1,0 +1,181 @@
+// Internal runtime shared by the berryhip translation units: the context,
+// workspace carving, error plumbing and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/berryhip.h"
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Workspace slots: each pipeline stage carves its scratch from its own slot,
+// so a stage may call another stage without their scratch overlapping.
+enum { WS_EIGH = 0, WS_WILSON = 1, WS_OUTER = 2, WS_MISC = 3, WS_SLOTS = 4 };
+
+struct be_ctx {
+  int device = 0;
+  void *ws[WS_SLOTS] = {nullptr, nullptr, nullptr, nullptr};  // device workspaces (grow on demand)
+  size_t ws_bytes[WS_SLOTS] = {0, 0, 0, 0};
+  void *pinned = nullptr;  // small pinned host buffer for scalar read-backs
+  std::string err;
+  int n_cu = 256;
+};
+
+namespace be {
+
+// ---------------------------------------------------------------- errors
+int set_err(be_ctx *ctx, int code, const std::string &msg);
+
+#define BE_HIP_TRY(ctx, expr)                                                         \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess)                                                             \
+      return ::be::set_err((ctx), BE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define BE_CHECK_ARG(ctx, cond, msg)                                    \
+  do {                                                                  \
+    if (!(cond)) return ::be::set_err((ctx), BE_EINVAL, (msg));         \
+  } while (0)
+
+#define BE_RET_IF(rc) \
+  do {                \
+    int _r = (rc);    \
+    if (_r) return _r; \
+  } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Carves one contiguous device workspace into 256-byte aligned pieces.
+// Usage: declare every piece with add(), then call commit() once, then read
+// the resolved pointers.
+class Carve {
+ public:
+  template <typename T>
+  void add(T **slot, size_t count) {
+    slots_.push_back(reinterpret_cast<void **>(slot));
+    offs_.push_back(total_);
+    total_ += (count * sizeof(T) + 255) & ~size_t(255);
+  }
+  size_t total() const { return total_; }
+  int commit(be_ctx *ctx, hipStream_t stream, int slot);
+
+ private:
+  std::vector<void **> slots_;
+  std::vector<size_t> offs_;
+  size_t total_ = 0;
+};
+
+// ---------------------------------------------------------------- launches
+// Kernel launch error check (after hipLaunchKernelGGL).
+int check_launch(be_ctx *ctx, const char *what);
+
+// Number of workgroups for an XCD-aware 1D grid over `work` items: rounded
+// up to a multiple of 8 so that item w maps to XCD w / per_xcd.
+inline uint32_t xcd_grid(int64_t work) {
+  int64_t per = (work + 7) / 8;
+  return static_cast<uint32_t>(per * 8);
+}
+
+// Linear workgroup id -> work item, so that consecutive work items land on
+// the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_work_id(int64_t total) {
+  int64_t L = blockIdx.x;
+  int64_t per = (total + 7) / 8;
+  return (L & 7) * per + (L >> 3);
+}
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------- batched complex GEMM (internal)
+// Element offset of batch item q:
+//   (q / (n0*n1)) * s2 + ((q / n0) % n1) * s1 + ((q % n0 + shift) % n0) * s0
+// i.e. a three-level index (outer, middle, inner) with a cyclic shift of the
+// inner index (used for the closing link of a Wilson loop).
+struct ZBatch {
+  int64_t s0 = 0, s1 = 0, s2 = 0;
+  int32_t n0 = 1, n1 = 1;
+  int32_t shift = 0;
+  static ZBatch strided(int64_t s) {
+    ZBatch b;
+    b.s2 = s;
+    return b;
+  }
+  // inner index cyclic over n0 (stride s0, shifted), outer stride s2
+  static ZBatch cyclic(int64_t s0, int32_t n0, int32_t shift, int64_t s_outer) {
+    ZBatch b;
+    b.s0 = s0;
+    b.n0 = n0;
+    b.shift = shift;
+    b.s2 = s_outer;
+    return b;
+  }
+};
+
+__host__ __device__ inline int64_t zbatch_off(const ZBatch &b, int64_t q) {
+  int64_t inner = q % b.n0, rest = q / b.n0;
+  int64_t mid = rest % b.n1, outer = rest / b.n1;
+  inner += b.shift;
+  if (inner >= b.n0) inner -= b.n0;
+  return outer * b.s2 + mid * b.s1 + inner * b.s0;
+}
+
+struct ZGemm {
+  int M = 0, N = 0, K = 0;
+  int opA = 0, opB = 0;  // 0: none, 1: conjugate transpose
+  const double2 *A = nullptr;
+  int lda = 0;
+  ZBatch bA;
+  const double2 *B = nullptr;
+  int ldb = 0;
+  ZBatch bB;
+  double2 *C = nullptr;
+  int ldc = 0;
+  ZBatch bC;
+  double2 alpha = {1.0, 0.0};
+  double2 beta = {0.0, 0.0};
+  int64_t batch = 0;
+};
+
+// C = alpha op(A) op(B) + beta C, FP64 MFMA. C must not alias A or B.
+int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream);
+
+// Single-precision complex variant (FP32 MFMA, FP32 accumulation).
+struct CGemm {
+  int M = 0, N = 0, K = 0;
+  int opA = 0, opB = 0;
+  const float2 *A = nullptr;
+  int lda = 0;
+  ZBatch bA;
+  const float2 *B = nullptr;
+  int ldb = 0;
+  ZBatch bB;
+  float2 *C = nullptr;
+  int ldc = 0;
+  ZBatch bC;
+  float2 alpha = {1.0f, 0.0f};
+  float2 beta = {0.0f, 0.0f};
+  int64_t batch = 0;
+};
+int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
+
+// FP64 batched eigensolver for bands [band_lo, band_hi) (uses slot WS_EIGH).
+int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
+              double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
+
+}  // namespace be

@@ -1,0 +1,712 @@
+// Rows (a3)-(a5): batched Hermitian eigensolver for the selected bands.
+//
+// 1. Blocked Householder reduction to real symmetric tridiagonal form,
+//    Q^H H Q = T with Q = H_0 H_1 ... H_{N-2}, H_j = I - tau_j v_j v_j^H.
+//    One workgroup per matrix runs a panel of nb columns (hetrd_panel): for
+//    each column it applies the panel's earlier reflectors to that column,
+//    builds the reflector, forms the matrix-vector product with the trailing
+//    matrix (one wave per 64-row block, v broadcast from LDS) and the
+//    symmetric rank-2 correction vector w. The trailing matrix is then updated
+//    once per panel by a rank-2nb MFMA GEMM, C -= [V W] [W V]^H. The panel's
+//    compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the fly from
+//    the same dot products.
+// 2. FP64 tridiagonal eigensolver (tridiag_eig): bisection with Sturm counts,
+//    one lane per eigenvalue, for the selected indices and their neighbours;
+//    inverse iteration with partial pivoting, one lane per eigenvector;
+//    modified Gram-Schmidt (two passes) inside clusters of close eigenvalues,
+//    one wave per cluster.
+// 3. Back-transformation U = Q Z by panels in reverse order with three MFMA
+//    GEMMs each: X = V^H U, Y = T X, U -= V Y.
+// 4. Mixed precision only: FP64 Cholesky-QR re-orthonormalization of U.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int NB = 32;   // panel width
+constexpr int PT = 256;  // threads of the panel and tridiagonal kernels
+
+template <typename T>
+struct CT;
+template <>
+struct CT<double> {
+  typedef double2 c;
+};
+template <>
+struct CT<float> {
+  typedef float2 c;
+};
+
+template <typename C>
+__device__ __forceinline__ C mk(double x, double y) {
+  C r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+
+// ---------------------------------------------------------------- reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of two values (all threads get the result).
+template <typename T>
+__device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wave] = a;
+    red[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  T sa = 0, sb = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    sa += red[2 * w];
+    sb += red[2 * w + 1];
+  }
+  a = sa;
+  b = sb;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- panel kernel
+// A: matrices (full Hermitian storage), VW: [V | W | V] panel buffers (N x 3NB,
+// leading dimension N), Tm: per-matrix NB x NB compact-WY factor of each
+// panel, d/e: FP64 tridiagonal output.
+template <typename T>
+__global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
+                                                  typename CT<T>::c *VW, int64_t sVW, typename CT<T>::c *Tm,
+                                                  int64_t sTm, double *d, double *e, int64_t sDE, uint32_t *status) {
+  typedef typename CT<T>::c C;
+  extern __shared__ unsigned char smem_raw[];
+  C *sv = reinterpret_cast<C *>(smem_raw);  // v, length N
+  C *sy = sv + N;                           // y / w, length N
+  C *sVr = sy + N;                          // row j of V (NB)
+  C *sWr = sVr + NB;                        // row j of W (NB)
+  C *st1 = sWr + NB;                        // W^H v (NB)
+  C *st2 = st1 + NB;                        // V^H v (NB)
+  C *sT = st2 + NB;                         // NB x NB, column-major
+  T *red = reinterpret_cast<T *>(sT + NB * NB);  // 2 * waves
+  __shared__ C s_tau, s_scal;
+  __shared__ T s_beta;
+
+  const int64_t q = blockIdx.x;
+  C *Aq = A + q * sA;
+  C *V = VW + q * sVW;
+  C *W = V + int64_t(NB) * N;
+  C *V2 = W + int64_t(NB) * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
+
+  for (int e2 = tid; e2 < NB * NB; e2 += PT) sT[e2] = mk<C>(0, 0);
+  __syncthreads();
+
+  for (int jj = 0; jj < nbp; ++jj) {
+    const int j = p0 + jj;
+    // ---- (1) apply the panel's earlier reflectors to column j
+    for (int c = tid; c < jj; c += PT) {
+      sVr[c] = V[j + int64_t(c) * N];
+      sWr[c] = W[j + int64_t(c) * N];
+    }
+    __syncthreads();
+    for (int r = j + tid; r < N; r += PT) {
+      C a = Aq[r + int64_t(j) * lda];
+      T ar = a.x, ai = a.y;
+      for (int c = 0; c < jj; ++c) {
+        C vr = V[r + int64_t(c) * N], wr = W[r + int64_t(c) * N];
+        C wj = sWr[c], vj = sVr[c];
+        // a -= V(r,c) conj(W(j,c)) + W(r,c) conj(V(j,c))
+        ar -= vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
+        ai -= vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
+      }
+      if (r == j) {
+        ai = 0;
+        d[q * sDE + j] = double(ar);
+      }
+      Aq[r + int64_t(j) * lda] = mk<C>(ar, ai);
+    }
+    __syncthreads();
+    if (j == N - 1) {
+      // last column: no reflector. Column j of V and W is zero.
+      for (int r = tid; r < N; r += PT) {
+        Aq[r + int64_t(j) * lda] = mk<C>(0, 0);
+        V[r + int64_t(jj) * N] = mk<C>(0, 0);
+        W[r + int64_t(jj) * N] = mk<C>(0, 0);
+        V2[r + int64_t(jj) * N] = mk<C>(0, 0);
+      }
+      __syncthreads();
+      break;
+    }
+    // ---- (2) reflector from A(j+1:N, j)
+    T xn = 0, dummy = 0;
+    for (int r = j + 2 + tid; r < N; r += PT) {
+      C a = Aq[r + int64_t(j) * lda];
+      xn += a.x * a.x + a.y * a.y;
+    }
+    block_sum2(xn, dummy, red);
+    if (tid == 0) {
+      C alpha = Aq[(j + 1) + int64_t(j) * lda];
+      C tau, scal;
+      T beta;
+      if (xn == T(0) && alpha.y == T(0)) {
+        tau = mk<C>(0, 0);
+        scal = mk<C>(0, 0);
+        beta = alpha.x;
+      } else {
+        T nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn);
+        beta = alpha.x >= T(0) ? -nrm : nrm;
+        tau = mk<C>((beta - alpha.x) / beta, -alpha.y / beta);
+        // scal = 1 / (alpha - beta)
+        T dr = alpha.x - beta, di = alpha.y;
+        T den = dr * dr + di * di;
+        scal = mk<C>(dr / den, -di / den);
+      }
+      s_tau = tau;
+      s_scal = scal;
+      s_beta = beta;
+      e[q * sDE + j] = double(beta);
+    }
+    __syncthreads();
+    const C tau = s_tau, scal = s_scal;
+    // v: zero above j+1, one at j+1, scaled x below; into LDS, A's column j, V and V2
+    for (int r = tid; r < N; r += PT) {
+      C v;
+      if (r <= j) {
+        v = mk<C>(0, 0);
+      } else if (r == j + 1) {
+        v = mk<C>(1, 0);
+      } else {
+        C a = Aq[r + int64_t(j) * lda];
+        v = mk<C>(a.x * scal.x - a.y * scal.y, a.x * scal.y + a.y * scal.x);
+      }
+      sv[r] = v;
+      Aq[r + int64_t(j) * lda] = v;
+      V[r + int64_t(jj) * N] = v;
+      V2[r + int64_t(jj) * N] = v;
+    }
+    __syncthreads();
+    // ---- (3) y = A(j+1:N, j+1:N) v : one wave per 64-row block
+    const int r0 = j + 1;
+    const int nrow = N - r0;
+    const int nrb = (nrow + 63) / 64;
+    for (int rb = wave; rb < nrb; rb += nw) {
+      const int r = r0 + rb * 64 + lane;
+      T yr = 0, yi = 0;
+      if (r < N) {
+        const C *col = Aq + r;
+        int c = r0;
+        for (; c + 4 <= N; c += 4) {
+          C a0 = col[int64_t(c) * lda], a1 = col[int64_t(c + 1) * lda];
+          C a2 = col[int64_t(c + 2) * lda], a3 = col[int64_t(c + 3) * lda];
+          C v0 = sv[c], v1 = sv[c + 1], v2 = sv[c + 2], v3 = sv[c + 3];
+          yr += a0.x * v0.x - a0.y * v0.y + a1.x * v1.x - a1.y * v1.y;
+          yi += a0.x * v0.y + a0.y * v0.x + a1.x * v1.y + a1.y * v1.x;
+          yr += a2.x * v2.x - a2.y * v2.y + a3.x * v3.x - a3.y * v3.y;
+          yi += a2.x * v2.y + a2.y * v2.x + a3.x * v3.y + a3.y * v3.x;
+        }
+        for (; c < N; ++c) {
+          C a = col[int64_t(c) * lda], v = sv[c];
+          yr += a.x * v.x - a.y * v.y;
+          yi += a.x * v.y + a.y * v.x;
+        }
+        sy[r] = mk<C>(yr, yi);
+      }
+    }
+    // ---- (4) t1 = W^H v, t2 = V^H v over rows j+1..N-1 (one wave per column c)
+    for (int c = wave; c < jj; c += nw) {
+      T a_r = 0, a_i = 0, b_r = 0, b_i = 0;
+      for (int r = r0 + lane; r < N; r += 64) {
+        C v = sv[r], w = W[r + int64_t(c) * N], vv = V[r + int64_t(c) * N];
+        a_r += w.x * v.x + w.y * v.y;
+        a_i += w.x * v.y - w.y * v.x;
+        b_r += vv.x * v.x + vv.y * v.y;
+        b_i += vv.x * v.y - vv.y * v.x;
+      }
+      a_r = wave_sum(a_r);
+      a_i = wave_sum(a_i);
+      b_r = wave_sum(b_r);
+      b_i = wave_sum(b_i);
+      if (lane == 0) {
+        st1[c] = mk<C>(a_r, a_i);
+        st2[c] = mk<C>(b_r, b_i);
+      }
+    }
+    __syncthreads();
+    // y -= V t1 + W t2
+    for (int r = r0 + tid; r < N; r += PT) {
+      C y = sy[r];
+      T yr = y.x, yi = y.y;
+      for (int c = 0; c < jj; ++c) {
+        C vv = V[r + int64_t(c) * N], w = W[r + int64_t(c) * N], a = st1[c], b = st2[c];
+        yr -= vv.x * a.x - vv.y * a.y + w.x * b.x - w.y * b.y;
+        yi -= vv.x * a.y + vv.y * a.x + w.x * b.y + w.y * b.x;
+      }
+      // w = tau * y
+      sy[r] = mk<C>(tau.x * yr - tau.y * yi, tau.x * yi + tau.y * yr);
+    }
+    // compact-WY column: T(0:jj, jj) = -tau T(0:jj, 0:jj) t2, T(jj, jj) = tau
+    if (tid < jj) {
+      const int rr = tid;
+      T xr = 0, xi = 0;
+      for (int c = rr; c < jj; ++c) {
+        C tt = sT[rr + c * NB], b = st2[c];
+        xr += tt.x * b.x - tt.y * b.y;
+        xi += tt.x * b.y + tt.y * b.x;
+      }
+      sT[rr + jj * NB] = mk<C>(-(tau.x * xr - tau.y * xi), -(tau.x * xi + tau.y * xr));
+    }
+    if (tid == 0) sT[jj + jj * NB] = tau;
+    __syncthreads();
+    // ---- (5) w += alpha v with alpha = -1/2 tau (w^H v)
+    T dr = 0, di = 0;
+    for (int r = r0 + tid; r < N; r += PT) {
+      C w = sy[r], v = sv[r];
+      dr += w.x * v.x + w.y * v.y;
+      di += w.x * v.y - w.y * v.x;
+    }
+    block_sum2(dr, di, red);
+    const T alr = T(-0.5) * (tau.x * dr - tau.y * di), ali = T(-0.5) * (tau.x * di + tau.y * dr);
+    for (int r = tid; r < N; r += PT) {
+      C w;
+      if (r < r0) {
+        w = mk<C>(0, 0);
+      } else {
+        C y = sy[r], v = sv[r];
+        w = mk<C>(y.x + alr * v.x - ali * v.y, y.y + alr * v.y + ali * v.x);
+      }
+      W[r + int64_t(jj) * N] = w;
+    }
+    __syncthreads();
+  }
+  // ---- write the panel's T factor
+  C *Tq = Tm + q * sTm;
+  for (int e2 = tid; e2 < NB * NB; e2 += PT) Tq[e2] = sT[e2];
+  (void)status;
+}
+
+// ---------------------------------------------------------------- tridiagonal solver
+__device__ __forceinline__ int sturm_count(const double *sd, const double *se2, int N, double x, double pivmin) {
+  int cnt = 0;
+  double qv = sd[0] - x;
+  if (fabs(qv) < pivmin) qv = -pivmin;
+  cnt += qv < 0.0;
+  for (int i = 1; i < N; ++i) {
+    qv = (sd[i] - x) - se2[i - 1] / qv;
+    if (fabs(qv) < pivmin) qv = -pivmin;
+    cnt += qv < 0.0;
+  }
+  return cnt;
+}
+
+__device__ __forceinline__ double hash_unit(uint64_t a, uint64_t b) {
+  // splitmix64 of (a, b) -> uniform in (-1, 1)
+  uint64_t z = a * 0x9E3779B97F4A7C15ull + b + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Zs layout per matrix: 4 arrays [N][mp] (U0, U1, U2, x), lane index fastest.
+__global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double *e, int64_t sDE, int N, int lo, int hi,
+                                                  double *evals, double *Zs, int64_t sZ, int mp, double2 *U, int ldu,
+                                                  int64_t sU, uint32_t *status) {
+  extern __shared__ double tsm[];
+  double *sd = tsm;          // N
+  double *se = sd + N;       // N
+  double *se2 = se + N;      // N
+  double *slam = se2 + N;    // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
+  const int m = hi - lo;
+  int *sclu = reinterpret_cast<int *>(slam + m + 4);  // cluster start flags (m)
+  __shared__ double red[2 * (PT / 64)];
+  __shared__ int s_bad;
+
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int i = tid; i < N; i += PT) {
+    double di = d[q * sDE + i];
+    double ei = i < N - 1 ? e[q * sDE + i] : 0.0;
+    if (!isfinite(di) || !isfinite(ei)) s_bad = 1;
+    sd[i] = di;
+    se[i] = ei;
+    se2[i] = ei * ei;
+  }
+  __syncthreads();
+  uint32_t st = 0;
+  if (s_bad) {
+    if (tid == 0) status[q] |= BE_ST_NAN_INF;
+    for (int c = tid; c < m + 2; c += PT) evals[q * (m + 2) + c] = NAN;
+    for (int64_t k = tid; k < int64_t(N) * m; k += PT) {
+      int c = int(k / N), r = int(k % N);
+      U[q * sU + r + int64_t(c) * ldu] = make_double2(NAN, NAN);
+    }
+    return;
+  }
+  // Gershgorin interval and pivot threshold
+  double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
+  for (int i = tid; i < N; i += PT) {
+    double rad = fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
+    gl = fmin(gl, sd[i] - rad);
+    gu = fmax(gu, sd[i] + rad);
+    emax2 = fmax(emax2, se2[i]);
+  }
+  {
+    // min/max reductions via negation trick in block_sum-like code
+    for (int o = 32; o > 0; o >>= 1) {
+      gl = fmin(gl, __shfl_xor(gl, o, 64));
+      gu = fmax(gu, __shfl_xor(gu, o, 64));
+      emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+    }
+    __shared__ double mm[3 * (PT / 64)];
+    if (lane == 0) {
+      mm[3 * wave] = gl;
+      mm[3 * wave + 1] = gu;
+      mm[3 * wave + 2] = emax2;
+    }
+    __syncthreads();
+    gl = mm[0];
+    gu = mm[1];
+    emax2 = mm[2];
+    for (int w = 1; w < nw; ++w) {
+      gl = fmin(gl, mm[3 * w]);
+      gu = fmax(gu, mm[3 * w + 1]);
+      emax2 = fmax(emax2, mm[3 * w + 2]);
+    }
+    __syncthreads();
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  const double eps = DBL_EPSILON;
+  gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
+  gu += 2.0 * eps * tnorm + 2.0 * pivmin;
+  // ---- bisection for the wanted indices
+  const int nidx = m + 4;
+  for (int t = tid; t < nidx; t += PT) {
+    int k;
+    if (t == 0) k = 0;
+    else if (t == 1) k = N - 1;
+    else if (t == 2) k = lo > 0 ? lo - 1 : -1;
+    else if (t == 3) k = hi < N ? hi : -1;
+    else k = lo + (t - 4);
+    double val = NAN;
+    if (k >= 0) {
+      double a = gl, b = gu;
+      for (int it = 0; it < 128; ++it) {
+        double mid = 0.5 * (a + b);
+        if (b - a <= 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin || mid <= a || mid >= b) break;
+        if (sturm_count(sd, se2, N, mid, pivmin) > k) b = mid;
+        else a = mid;
+      }
+      val = 0.5 * (a + b);
+    }
+    slam[t] = val;
+  }
+  __syncthreads();
+  const double *lam = slam + 4;
+  for (int c = tid; c < m + 2; c += PT) {
+    double v;
+    if (c == 0) v = slam[2];
+    else if (c == m + 1) v = slam[3];
+    else v = lam[c - 1];
+    evals[q * (m + 2) + c] = v;
+  }
+  if (tid == 0) {
+    double scale = fmax(1.0, fmax(fabs(slam[0]), fabs(slam[1])));
+    double g = INFINITY;
+    if (lo > 0 && m > 0) g = fmin(g, lam[0] - slam[2]);
+    if (hi < N && m > 0) g = fmin(g, slam[3] - lam[m - 1]);
+    if (g < 1e-9 * scale) st |= BE_ST_GAP_CLOSED;
+  }
+  // ---- inverse iteration, one lane per eigenvector
+  double *Z0 = Zs + q * sZ;
+  double *Z1 = Z0 + int64_t(N) * mp;
+  double *Z2 = Z1 + int64_t(N) * mp;
+  double *X = Z2 + int64_t(N) * mp;
+  const double tiny = eps * fmax(tnorm, DBL_MIN);
+  bool lane_bad = false;
+  for (int c = tid; c < m; c += PT) {
+    const double lm = lam[c];
+    for (int it = 0; it < 3; ++it) {
+      // forward elimination with partial pivoting on [T - lm I | rhs]
+      double a = sd[0] - lm, b = N > 1 ? se[0] : 0.0;
+      double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, 0) : X[c];
+      for (int i = 0; i + 1 < N; ++i) {
+        const double ei = se[i], Dn = sd[i + 1] - lm, en = (i + 2 < N) ? se[i + 1] : 0.0;
+        const double rn = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, i + 1) : X[int64_t(i + 1) * mp + c];
+        const int64_t o = int64_t(i) * mp + c;
+        if (fabs(a) >= fabs(ei)) {
+          if (a == 0.0) a = tiny;
+          const double l = ei / a;
+          Z0[o] = a;
+          Z1[o] = b;
+          Z2[o] = 0.0;
+          X[o] = r;
+          a = Dn - l * b;
+          b = en;
+          r = rn - l * r;
+        } else {
+          const double l = a / ei;
+          Z0[o] = ei;
+          Z1[o] = Dn;
+          Z2[o] = en;
+          X[o] = rn;
+          const double an = b - l * Dn, bn = -l * en, rr = r - l * rn;
+          a = an;
+          b = bn;
+          r = rr;
+        }
+      }
+      if (a == 0.0) a = tiny;
+      {
+        const int64_t o = int64_t(N - 1) * mp + c;
+        Z0[o] = a;
+        Z1[o] = 0.0;
+        Z2[o] = 0.0;
+        X[o] = r;
+      }
+      // back substitution
+      double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+      for (int i = N - 1; i >= 0; --i) {
+        const int64_t o = int64_t(i) * mp + c;
+        double xi = (X[o] - Z1[o] * x1 - Z2[o] * x2) / Z0[o];
+        X[o] = xi;
+        x2 = x1;
+        x1 = xi;
+        nrm = fma(xi, xi, nrm);
+      }
+      double inv = 1.0 / sqrt(nrm);
+      if (!isfinite(inv) || inv == 0.0) lane_bad = true;
+      for (int i = 0; i < N; ++i) X[int64_t(i) * mp + c] *= inv;
+    }
+  }
+  if (lane_bad) st |= BE_ST_NONCONVERGED;
+  // ---- clusters of close eigenvalues: start flags
+  const double ortol = 1e-3 * tnorm;
+  for (int c = tid; c < m; c += PT) sclu[c] = (c == 0) || (lam[c] - lam[c - 1] > ortol);
+  __syncthreads();
+  // ---- MGS (two passes) inside each cluster, one wave per cluster
+  for (int c0 = wave; c0 < m; c0 += nw) {
+    // find clusters whose start index is congruent to this wave's turn: walk starts
+    if (!sclu[c0]) continue;
+    int c1 = c0 + 1;
+    while (c1 < m && !sclu[c1]) ++c1;
+    if (c1 - c0 < 2) continue;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int t = c0; t < c1; ++t) {
+        for (int s = c0; s < t; ++s) {
+          double dt = 0.0;
+          for (int i = lane; i < N; i += 64) dt = fma(X[int64_t(i) * mp + s], X[int64_t(i) * mp + t], dt);
+          dt = wave_sum(dt);
+          for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] -= dt * X[int64_t(i) * mp + s];
+        }
+        double nr = 0.0;
+        for (int i = lane; i < N; i += 64) {
+          double v = X[int64_t(i) * mp + t];
+          nr = fma(v, v, nr);
+        }
+        nr = wave_sum(nr);
+        double inv = 1.0 / sqrt(nr);
+        for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] *= inv;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- Z -> U (complex, column-major)
+  for (int64_t k = tid; k < int64_t(N) * m; k += PT) {
+    int c = int(k / N), r = int(k % N);
+    U[q * sU + r + int64_t(c) * ldu] = make_double2(X[int64_t(r) * mp + c], 0.0);
+  }
+  // status: OR of lane flags
+  {
+    __shared__ unsigned int sst;
+    if (tid == 0) sst = 0;
+    __syncthreads();
+    if (st) atomicOr(&sst, st);
+    __syncthreads();
+    if (tid == 0) status[q] |= sst;
+  }
+}
+
+__global__ void zero_u32(uint32_t *p, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+size_t panel_smem(int N, size_t csize) {
+  return (2 * size_t(N) + 4 * NB + NB * NB) * csize + 2 * (PT / 64) * (csize / 2) + 64;
+}
+
+}  // namespace
+
+namespace be {
+
+// FP64 path for one sub-batch of nb_mat matrices.
+static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, int64_t nb_mat, int lo, int hi,
+                           double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream) {
+  const int m = hi - lo;
+  const int P = (N + NB - 1) / NB;
+  const int mp = std::max(64, (m + 63) / 64 * 64);
+  double2 *VW = nullptr, *Tm = nullptr, *Xb = nullptr, *Yb = nullptr;
+  double *dd = nullptr, *ee = nullptr, *Zs = nullptr;
+  Carve cv;
+  cv.add(&VW, size_t(nb_mat) * N * 3 * NB);
+  cv.add(&Tm, size_t(nb_mat) * P * NB * NB);
+  cv.add(&dd, size_t(nb_mat) * N);
+  cv.add(&ee, size_t(nb_mat) * N);
+  cv.add(&Zs, size_t(nb_mat) * 4 * N * mp);
+  cv.add(&Xb, size_t(nb_mat) * NB * std::max(m, 1));
+  cv.add(&Yb, size_t(nb_mat) * NB * std::max(m, 1));
+  BE_RET_IF(cv.commit(ctx, stream, WS_EIGH));
+  hipLaunchKernelGGL(zero_u32, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, status, nb_mat);
+  BE_RET_IF(check_launch(ctx, "zero_u32"));
+  const int64_t sVW = int64_t(N) * 3 * NB;
+  const int64_t sT = int64_t(P) * NB * NB;
+  const size_t psm = panel_smem(N, sizeof(double2));
+  if (psm > 65536)
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&hetrd_panel<double>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)));
+  // ---- Householder reduction
+  for (int p = 0; p < P; ++p) {
+    const int p0 = p * NB, nbp = std::min(NB, N - p0);
+    hipLaunchKernelGGL(hetrd_panel<double>, dim3(nb_mat), dim3(PT), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
+                       Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
+    BE_RET_IF(check_launch(ctx, "hetrd_panel"));
+    const int n2 = N - p0 - NB;
+    if (n2 > 0) {
+      ZGemm g;
+      g.M = n2;
+      g.N = n2;
+      g.K = 2 * NB;
+      g.opA = 0;
+      g.opB = 1;
+      g.A = VW + (p0 + NB);
+      g.lda = N;
+      g.bA = ZBatch::strided(sVW);
+      g.B = VW + int64_t(NB) * N + (p0 + NB);
+      g.ldb = N;
+      g.bB = ZBatch::strided(sVW);
+      g.C = H + (p0 + NB) + int64_t(p0 + NB) * ld;
+      g.ldc = ld;
+      g.bC = ZBatch::strided(ms);
+      g.alpha = make_double2(-1.0, 0.0);
+      g.beta = make_double2(1.0, 0.0);
+      g.batch = nb_mat;
+      BE_RET_IF(zgemm(ctx, g, stream));
+    }
+  }
+  // ---- tridiagonal eigenpairs
+  const size_t tsm = (3 * size_t(N) + m + 4) * sizeof(double) + size_t(std::max(m, 1)) * sizeof(int) + 64;
+  if (tsm > 65536)
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tridiag_eig),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(tsm)));
+  hipLaunchKernelGGL(tridiag_eig, dim3(nb_mat), dim3(PT), tsm, stream, dd, ee, int64_t(N), N, lo, hi, evals, Zs,
+                     int64_t(4) * N * mp, mp, U, ldu, us, status);
+  BE_RET_IF(check_launch(ctx, "tridiag_eig"));
+  if (m == 0) return BE_OK;
+  // ---- back-transformation, panels in reverse order
+  for (int p = P - 1; p >= 0; --p) {
+    const int p0 = p * NB, nbp = std::min(NB, N - p0);
+    const int K = N - p0 - 1;
+    if (K <= 0) continue;
+    ZGemm g1;  // X = V^H U(p0+1:, :)
+    g1.M = nbp;
+    g1.N = m;
+    g1.K = K;
+    g1.opA = 1;
+    g1.opB = 0;
+    g1.A = H + (p0 + 1) + int64_t(p0) * ld;
+    g1.lda = ld;
+    g1.bA = ZBatch::strided(ms);
+    g1.B = U + (p0 + 1);
+    g1.ldb = ldu;
+    g1.bB = ZBatch::strided(us);
+    g1.C = Xb;
+    g1.ldc = NB;
+    g1.bC = ZBatch::strided(int64_t(NB) * m);
+    g1.batch = nb_mat;
+    BE_RET_IF(zgemm(ctx, g1, stream));
+    ZGemm g2;  // Y = T X
+    g2.M = nbp;
+    g2.N = m;
+    g2.K = nbp;
+    g2.A = Tm + int64_t(p) * NB * NB;
+    g2.lda = NB;
+    g2.bA = ZBatch::strided(sT);
+    g2.B = Xb;
+    g2.ldb = NB;
+    g2.bB = ZBatch::strided(int64_t(NB) * m);
+    g2.C = Yb;
+    g2.ldc = NB;
+    g2.bC = ZBatch::strided(int64_t(NB) * m);
+    g2.batch = nb_mat;
+    BE_RET_IF(zgemm(ctx, g2, stream));
+    ZGemm g3;  // U -= V Y
+    g3.M = K;
+    g3.N = m;
+    g3.K = nbp;
+    g3.A = H + (p0 + 1) + int64_t(p0) * ld;
+    g3.lda = ld;
+    g3.bA = ZBatch::strided(ms);
+    g3.B = Yb;
+    g3.ldb = NB;
+    g3.bB = ZBatch::strided(int64_t(NB) * m);
+    g3.C = U + (p0 + 1);
+    g3.ldc = ldu;
+    g3.bC = ZBatch::strided(us);
+    g3.alpha = make_double2(-1.0, 0.0);
+    g3.beta = make_double2(1.0, 0.0);
+    g3.batch = nb_mat;
+    BE_RET_IF(zgemm(ctx, g3, stream));
+  }
+  return BE_OK;
+}
+
+int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
+              double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream) {
+  const int m = band_hi - band_lo;
+  if (n_mat == 0) return BE_OK;
+  // sub-batches bounded to ~4 GiB of workspace
+  const int P = (N + NB - 1) / NB;
+  const int mp = std::max(64, (m + 63) / 64 * 64);
+  const size_t per = sizeof(double2) * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1)) +
+                     sizeof(double) * (2 * size_t(N) + 4 * size_t(N) * mp) + 7 * 256;
+  const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
+  for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
+    const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
+    BE_RET_IF(eigh_fp64_chunk(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo,
+                              band_hi, evals + b0 * (m + 2), U + b0 * u_stride, ldu, u_stride,
+                              status + b0, stream));
+  }
+  return BE_OK;
+}
+
+}  // namespace be
+
+extern "C" int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, int64_t mat_stride,
+                               int32_t n_mat, int32_t band_lo, int32_t band_hi, int32_t precision, double *evals,
+                               void *U, int32_t ldu, int64_t u_stride, uint32_t *status, hipStream_t stream) {
+  using namespace be;
+  BE_CHECK_ARG(ctx, ctx && H && evals && U && status, "be_eigh_batched: null argument");
+  BE_CHECK_ARG(ctx, N >= 1 && n_mat >= 0, "be_eigh_batched: N < 1 or n_mat < 0");
+  BE_CHECK_ARG(ctx, 0 <= band_lo && band_lo <= band_hi && band_hi <= N, "be_eigh_batched: need 0 <= lo <= hi <= N");
+  BE_CHECK_ARG(ctx, ld >= N && mat_stride >= int64_t(ld) * N, "be_eigh_batched: ld < N or mat_stride < ld*N");
+  const int m = band_hi - band_lo;
+  BE_CHECK_ARG(ctx, ldu >= N && u_stride >= int64_t(ldu) * std::max(m, 1), "be_eigh_batched: ldu < N or u_stride too small");
+  if (precision == BE_FP64) {
+    BE_CHECK_ARG(ctx, dtype == BE_C128, "be_eigh_batched: BE_FP64 needs BE_C128 matrices");
+  } else {
+    return set_err(ctx, BE_ENOTIMPL, "be_eigh_batched: precision not implemented");
+  }
+  return eigh_fp64(ctx, static_cast<double2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
+                   static_cast<double2 *>(U), ldu, u_stride, status, stream);
+}

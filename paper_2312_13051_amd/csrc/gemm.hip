@@ -1,0 +1,303 @@
+// Batched complex GEMM on CDNA4 matrix cores.
+//
+//   C_q = alpha op(A_q) op(B_q) + beta C_q,  op in {none, conjugate transpose}
+//
+// Complex products use four real MFMAs per 16x16 tile and k-step
+// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br). Tiles of A and B are staged
+// through LDS as separate real and imaginary planes laid out [k][row], so
+// every MFMA operand fetch is one conflict-free 8-byte (4-byte) LDS read per
+// lane. The MFMA's "A" operand is taken from the B tile and its "B" operand
+// from the A tile, so that the accumulator registers of a lane hold one row
+// index i = lane % 16 and four column indices (the register-to-row map of
+// the accumulator differs between the FP64 and FP32 instructions): the
+// epilogue then writes 16 consecutive rows of a column-major C per
+// quarter-wave.
+//
+// Workgroups are mapped XCD-aware: the tiles of one batch item are given
+// consecutive work ids, which land on the same XCD (shared L2).
+#include "common.hpp"
+
+namespace {
+
+constexpr int KB = 16;  // complex k per LDS stage (4 MFMA k-steps of 4)
+
+template <typename T>
+struct MF;
+
+template <>
+struct MF<double> {
+  typedef v4d acc_t;
+  typedef double2 cplx;
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator register r of lane (lk = lane / 16) holds output row lk + 4 r
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+
+template <>
+struct MF<float> {
+  typedef v4f acc_t;
+  typedef float2 cplx;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator register r of lane (lk = lane / 16) holds output row 4 lk + r
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <typename T>
+struct GP {
+  typedef typename MF<T>::cplx cplx;
+  int M, N, K;
+  const cplx *A;
+  int lda;
+  be::ZBatch bA;
+  const cplx *B;
+  int ldb;
+  be::ZBatch bB;
+  cplx *C;
+  int ldc;
+  be::ZBatch bC;
+  cplx alpha, beta;
+  int64_t batch;
+  int tiles_m, tiles_n;
+};
+
+// BM x BN block tile, WM x WN waves, each wave (BM/WM) x (BN/WN).
+template <typename T, int BM, int BN, int WM, int WN, int OPA, int OPB>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
+  typedef typename MF<T>::cplx cplx;
+  typedef typename MF<T>::acc_t acc_t;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  constexpr int PA = BM + 2;  // LDS pitch (elements)
+  constexpr int PB = BN + 2;
+  __shared__ T sAr[KB * PA], sAi[KB * PA], sBr[KB * PB], sBi[KB * PB];
+
+  const int64_t tiles = int64_t(p.tiles_m) * p.tiles_n;
+  const int64_t total = tiles * p.batch;
+  const int64_t w = be::xcd_work_id(total);
+  if (w >= total) return;
+  const int64_t q = w / tiles;
+  const int t2 = static_cast<int>(w - q * tiles);
+  const int tm = t2 % p.tiles_m, tn = t2 / p.tiles_m;
+  const int i0 = tm * BM, j0 = tn * BN;
+  const cplx *A = p.A + be::zbatch_off(p.bA, q);
+  const cplx *B = p.B + be::zbatch_off(p.bB, q);
+  cplx *C = p.C + be::zbatch_off(p.bC, q);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int li = lane & 15, lk = lane >> 4;
+
+  acc_t accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      accr[a][b] = acc_t{0, 0, 0, 0};
+      acci[a][b] = acc_t{0, 0, 0, 0};
+    }
+
+  for (int k0 = 0; k0 < p.K; k0 += KB) {
+    // ---- stage A tile: element (i, k) of op(A)
+#pragma unroll
+    for (int e = tid; e < BM * KB; e += NT) {
+      int i, k;
+      if (OPA == 0) {
+        i = e % BM;
+        k = e / BM;
+      } else {
+        k = e % KB;
+        i = e / KB;
+      }
+      int gi = i0 + i, gk = k0 + k;
+      T vr = 0, vi = 0;
+      if (gi < p.M && gk < p.K) {
+        cplx v = OPA == 0 ? A[gi + int64_t(gk) * p.lda] : A[gk + int64_t(gi) * p.lda];
+        vr = v.x;
+        vi = OPA == 0 ? v.y : -v.y;
+      }
+      sAr[k * PA + i] = vr;
+      sAi[k * PA + i] = vi;
+    }
+    // ---- stage B tile: element (k, j) of op(B)
+#pragma unroll
+    for (int e = tid; e < BN * KB; e += NT) {
+      int j, k;
+      if (OPB == 0) {
+        k = e % KB;
+        j = e / KB;
+      } else {
+        j = e % BN;
+        k = e / BN;
+      }
+      int gj = j0 + j, gk = k0 + k;
+      T vr = 0, vi = 0;
+      if (gj < p.N && gk < p.K) {
+        cplx v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
+        vr = v.x;
+        vi = OPB == 0 ? v.y : -v.y;
+      }
+      sBr[k * PB + j] = vr;
+      sBi[k * PB + j] = vi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 4) {
+      T ar[TM], ai[TM], br[TN], bi[TN], nbi[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        int ii = wm * (BM / WM) + a * 16 + li;
+        ar[a] = sAr[(kk + lk) * PA + ii];
+        ai[a] = sAi[(kk + lk) * PA + ii];
+      }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        int jj = wn * (BN / WN) + b * 16 + li;
+        br[b] = sBr[(kk + lk) * PB + jj];
+        bi[b] = sBi[(kk + lk) * PB + jj];
+        nbi[b] = -bi[b];
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          accr[a][b] = MF<T>::mfma(br[b], ar[a], accr[a][b]);
+          accr[a][b] = MF<T>::mfma(nbi[b], ai[a], accr[a][b]);
+          acci[a][b] = MF<T>::mfma(bi[b], ar[a], acci[a][b]);
+          acci[a][b] = MF<T>::mfma(br[b], ai[a], acci[a][b]);
+        }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: lane holds C(i = i_base + li, j = j_base + row(lk, r))
+  const bool use_beta = (p.beta.x != T(0)) || (p.beta.y != T(0));
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      int gi = i0 + wm * (BM / WM) + a * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gj = j0 + wn * (BN / WN) + b * 16 + MF<T>::row(lk, r);
+        if (gi < p.M && gj < p.N) {
+          T xr = accr[a][b][r], xi = acci[a][b][r];
+          cplx out;
+          out.x = p.alpha.x * xr - p.alpha.y * xi;
+          out.y = p.alpha.x * xi + p.alpha.y * xr;
+          int64_t idx = gi + int64_t(gj) * p.ldc;
+          if (use_beta) {
+            cplx c = C[idx];
+            out.x += p.beta.x * c.x - p.beta.y * c.y;
+            out.y += p.beta.x * c.y + p.beta.y * c.x;
+          }
+          C[idx] = out;
+        }
+      }
+    }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+int launch_cfg(be_ctx *ctx, GP<T> p, int opA, int opB, hipStream_t s) {
+  p.tiles_m = (p.M + BM - 1) / BM;
+  p.tiles_n = (p.N + BN - 1) / BN;
+  int64_t total = int64_t(p.tiles_m) * p.tiles_n * p.batch;
+  dim3 grid(be::xcd_grid(total)), block(64 * WM * WN);
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 0>), grid, block, 0, s, p);
+  if (opA == 0 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 1>), grid, block, 0, s, p);
+  if (opA == 1 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 0>), grid, block, 0, s, p);
+  if (opA == 1 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 1>), grid, block, 0, s, p);
+  return be::check_launch(ctx, "zgemm");
+}
+
+template <typename T>
+int dispatch(be_ctx *ctx, GP<T> p, int opA, int opB, hipStream_t s) {
+  if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
+  // Tile choice by output size; small outputs use one-wave tiles.
+  if (p.M >= 48 && p.N >= 48) return launch_cfg<T, 64, 64, 2, 2>(ctx, p, opA, opB, s);
+  if (p.M >= 24 && p.N >= 24) return launch_cfg<T, 32, 32, 2, 2>(ctx, p, opA, opB, s);
+  return launch_cfg<T, 16, 16, 1, 1>(ctx, p, opA, opB, s);
+}
+
+}  // namespace
+
+namespace be {
+
+int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
+  GP<double> p;
+  p.M = g.M;
+  p.N = g.N;
+  p.K = g.K;
+  p.A = g.A;
+  p.lda = g.lda;
+  p.bA = g.bA;
+  p.B = g.B;
+  p.ldb = g.ldb;
+  p.bB = g.bB;
+  p.C = g.C;
+  p.ldc = g.ldc;
+  p.bC = g.bC;
+  p.alpha = g.alpha;
+  p.beta = g.beta;
+  p.batch = g.batch;
+  return dispatch<double>(ctx, p, g.opA, g.opB, stream);
+}
+
+int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
+  GP<float> p;
+  p.M = g.M;
+  p.N = g.N;
+  p.K = g.K;
+  p.A = g.A;
+  p.lda = g.lda;
+  p.bA = g.bA;
+  p.B = g.B;
+  p.ldb = g.ldb;
+  p.bB = g.bB;
+  p.C = g.C;
+  p.ldc = g.ldc;
+  p.bC = g.bC;
+  p.alpha = g.alpha;
+  p.beta = g.beta;
+  p.batch = g.batch;
+  return dispatch<float>(ctx, p, g.opA, g.opB, stream);
+}
+
+}  // namespace be
+
+extern "C" int be_zgemm_strided(be_ctx *ctx, char opA, char opB, int32_t M, int32_t Ncol, int32_t K,
+                                const double *alpha2_h, const void *A, int32_t lda, int64_t strideA, const void *B,
+                                int32_t ldb, int64_t strideB, const double *beta2_h, void *C, int32_t ldc,
+                                int64_t strideC, int32_t batch, hipStream_t stream) {
+  using namespace be;
+  BE_CHECK_ARG(ctx, ctx && alpha2_h && beta2_h && A && B && C, "be_zgemm_strided: null argument");
+  BE_CHECK_ARG(ctx, (opA == 'N' || opA == 'C') && (opB == 'N' || opB == 'C'), "be_zgemm_strided: op must be 'N' or 'C'");
+  BE_CHECK_ARG(ctx, M >= 0 && Ncol >= 0 && K >= 0 && batch >= 0, "be_zgemm_strided: negative size");
+  int ra = opA == 'N' ? M : K, rb = opB == 'N' ? K : Ncol;
+  BE_CHECK_ARG(ctx, lda >= std::max(1, ra) && ldb >= std::max(1, rb) && ldc >= std::max(1, M),
+               "be_zgemm_strided: leading dimension too small");
+  ZGemm g;
+  g.M = M;
+  g.N = Ncol;
+  g.K = K;
+  g.opA = opA == 'C';
+  g.opB = opB == 'C';
+  g.A = static_cast<const double2 *>(A);
+  g.lda = lda;
+  g.bA = ZBatch::strided(strideA);
+  g.B = static_cast<const double2 *>(B);
+  g.ldb = ldb;
+  g.bB = ZBatch::strided(strideB);
+  g.C = static_cast<double2 *>(C);
+  g.ldc = ldc;
+  g.bC = ZBatch::strided(strideC);
+  g.alpha = make_double2(alpha2_h[0], alpha2_h[1]);
+  g.beta = make_double2(beta2_h[0], beta2_h[1]);
+  g.batch = batch;
+  return zgemm(ctx, g, stream);
+}

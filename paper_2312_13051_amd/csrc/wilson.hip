@@ -1,0 +1,961 @@
+// Rows (a6)-(a10): overlaps, polar factors, ordered products, eigenphases,
+// Chern winding, nested Wilson loop and spin-resolved Wilson loop.
+//
+// Every stage works on "grids": matrix (line, j) of a grid lives at
+// base + (line * n_loop + j) * stride, with j running along the closed loop.
+//   overlaps      F_{line,j} = U_{line,j+1}^H U_{line,j}      (batched MFMA GEMM,
+//                 the closing link via a cyclic batch index)
+//   polar         X <- X (3 I - X^H X) / 2  (Newton-Schulz, FP64 MFMA GEMMs),
+//                 iterated to convergence of max |X^H X - I|; the limit is the
+//                 unitary polar factor of F for every nonsingular F with
+//                 singular values in (0, sqrt 3), which holds since ||F|| <= 1
+//   chain         W_line = F_{n-1} ... F_0 as a binary tree of batched GEMMs
+//                 that keeps the left-to-right order
+//   eigenphases   one wave per W: Householder reduction to Hessenberg form,
+//                 then single-shift complex QR with Wilkinson shifts; for
+//                 unitary W all entries are bounded by one, so deflation uses
+//                 an absolute threshold
+//   winding       Phi_i = sum theta mod 2pi, C = (1/2pi) sum wrap(dPhi)
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+struct Grid {
+  const double2 *base;
+  int ld;
+  int64_t stride;
+};
+
+__device__ __forceinline__ double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+
+__device__ __forceinline__ double2 csqrt_d(double2 z) {
+  double r = hypot(z.x, z.y);
+  if (r == 0.0) return make_double2(0.0, 0.0);
+  double t = sqrt(0.5 * (r + fabs(z.x)));
+  if (z.x >= 0.0) return make_double2(t, z.y / (2.0 * t));
+  return make_double2(fabs(z.y) / (2.0 * t), z.y >= 0.0 ? t : -t);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+__device__ __forceinline__ double wrap_pi(double x) {
+  // into (-pi, pi]
+  x = x - TWO_PI * floor(x / TWO_PI + 0.5);
+  if (x <= -M_PI) x += TWO_PI;
+  if (x > M_PI) x -= TWO_PI;
+  return x;
+}
+
+__device__ __forceinline__ double arg_pi(double2 z) {
+  double t = atan2(z.y, z.x);
+  return t <= -M_PI ? M_PI : t;
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// G <- 1.5 I - 0.5 G for every m x m matrix; per-matrix err = max |G - I|
+// (before the update) into err[q] and atomically into *gmax (bit pattern of a
+// non-negative double orders like an integer).
+__global__ void k_ns_prep(double2 *G, int m, int64_t n_mat, double *err, unsigned long long *gmax) {
+  const int64_t q = blockIdx.x;
+  if (q >= n_mat) return;
+  double2 *Gq = G + q * int64_t(m) * m;
+  double e = 0.0;
+  for (int k = threadIdx.x; k < m * m; k += blockDim.x) {
+    int r = k % m, c = k / m;
+    double2 g = Gq[k];
+    double dr = g.x - (r == c ? 1.0 : 0.0);
+    e = fmax(e, fmax(fabs(dr), fabs(g.y)));
+    Gq[k] = make_double2((r == c ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
+    if (!(t == t)) t = INFINITY;
+    err[q] = t;
+    atomicMax(gmax, (unsigned long long)__double_as_longlong(t));
+  }
+}
+
+// status[line] |= bit where err of any of the line's n_loop matrices > tol
+__global__ void k_flag_err(const double *err, int64_t n_lines, int n_loop, double tol, uint32_t bit, uint32_t *st) {
+  int64_t line = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (line >= n_lines) return;
+  for (int j = 0; j < n_loop; ++j)
+    if (!(err[line * n_loop + j] <= tol)) {
+      st[line] |= bit;
+      break;
+    }
+}
+
+__global__ void k_copy_mats(const double2 *src, int64_t s_src, double2 *dst, int64_t s_dst, int64_t count, int64_t n) {
+  int64_t q = blockIdx.y;
+  for (; q < n; q += gridDim.y)
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < count; k += int64_t(gridDim.x) * blockDim.x)
+      dst[q * s_dst + k] = src[q * s_src + k];
+}
+
+// Chain-tree carry: dst[line*n_dst + n_dst - 1] = src[line*n_src + n_src - 1]
+__global__ void k_carry_last(const double2 *src, int n_src, double2 *dst, int n_dst, int64_t mm, int64_t n_lines) {
+  int64_t line = blockIdx.y;
+  for (; line < n_lines; line += gridDim.y) {
+    const double2 *s = src + (line * n_src + n_src - 1) * mm;
+    double2 *d = dst + (line * n_dst + n_dst - 1) * mm;
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < mm; k += int64_t(gridDim.x) * blockDim.x) d[k] = s[k];
+  }
+}
+
+// ---------------------------------------------------------------- unitary eigenproblem
+// One 64-lane workgroup per matrix. W: m x m (ld m). H: scratch m x m. Z: optional
+// Schur vectors (m x m). Outputs: theta_sorted[q*ldt + 0..m-1] ascending in
+// (-pi, pi]; theta_raw[q*m + n] (optional) = phase of the eigenvalue belonging
+// to column n of Z.
+__global__ __launch_bounds__(64) void k_unitary_eig(const double2 *W, int m, int64_t n_mat, double2 *Hs,
+                                                    double2 *Zs, double *theta_sorted, int ldt, double *theta_raw,
+                                                    uint32_t *flags, int flag_div) {
+  extern __shared__ double2 sv[];  // Householder vector (m) then eigenvalues (m)
+  double2 *slam = sv + m;
+  const int64_t q = blockIdx.x;
+  if (q >= n_mat) return;
+  const int lane = threadIdx.x;
+  const double2 *Wq = W + q * int64_t(m) * m;
+  double2 *H = Hs + q * int64_t(m) * m;
+  double2 *Z = Zs ? Zs + q * int64_t(m) * m : nullptr;
+  for (int k = lane; k < m * m; k += 64) {
+    H[k] = Wq[k];
+    if (Z) Z[k] = make_double2((k % m) == (k / m) ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const double eps = DBL_EPSILON;
+  // ---- Hessenberg reduction: H <- P^H H P, P = I - tau v v^H
+  for (int k = 0; k + 2 < m; ++k) {
+    double xn = 0.0;
+    for (int r = k + 2 + lane; r < m; r += 64) {
+      double2 a = H[r + int64_t(k) * m];
+      xn = fma(a.x, a.x, fma(a.y, a.y, xn));
+    }
+    for (int o = 32; o > 0; o >>= 1) xn += __shfl_xor(xn, o, 64);
+    double2 alpha = H[(k + 1) + int64_t(k) * m];
+    double2 tau, scal;
+    double beta;
+    if (xn == 0.0 && alpha.y == 0.0) {
+      tau = make_double2(0.0, 0.0);
+      scal = make_double2(0.0, 0.0);
+      beta = alpha.x;
+    } else {
+      double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn);
+      beta = alpha.x >= 0.0 ? -nrm : nrm;
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      scal = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+    }
+    __syncthreads();
+    for (int r = lane; r < m; r += 64) {
+      double2 v;
+      if (r <= k) v = make_double2(0.0, 0.0);
+      else if (r == k + 1) v = make_double2(1.0, 0.0);
+      else v = be::cmul(H[r + int64_t(k) * m], scal);
+      sv[r] = v;
+    }
+    __syncthreads();
+    for (int r = k + 1 + lane; r < m; r += 64) H[r + int64_t(k) * m] = r == k + 1 ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+    if (tau.x != 0.0 || tau.y != 0.0) {
+      const double2 ctau = be::cconj(tau);
+      // left: columns k+1..m-1, rows k+1..m-1
+      for (int c = k + 1 + lane; c < m; c += 64) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int r = k + 1; r < m; ++r) s = be::cadd(s, be::cmulc(sv[r], H[r + int64_t(c) * m]));
+        double2 f = be::cmul(ctau, s);
+        for (int r = k + 1; r < m; ++r) H[r + int64_t(c) * m] = be::csub(H[r + int64_t(c) * m], be::cmul(sv[r], f));
+      }
+      __syncthreads();
+      // right: rows 0..m-1, columns k+1..m-1
+      for (int i = lane; i < m; i += 64) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int c = k + 1; c < m; ++c) s = be::cadd(s, be::cmul(H[i + int64_t(c) * m], sv[c]));
+        double2 f = be::cmul(tau, s);
+        for (int c = k + 1; c < m; ++c) H[i + int64_t(c) * m] = be::csub(H[i + int64_t(c) * m], be::cmul(f, be::cconj(sv[c])));
+        if (Z) {
+          double2 sz = make_double2(0.0, 0.0);
+          for (int c = k + 1; c < m; ++c) sz = be::cadd(sz, be::cmul(Z[i + int64_t(c) * m], sv[c]));
+          double2 fz = be::cmul(tau, sz);
+          for (int c = k + 1; c < m; ++c) Z[i + int64_t(c) * m] = be::csub(Z[i + int64_t(c) * m], be::cmul(fz, be::cconj(sv[c])));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // ---- single-shift QR on the Hessenberg matrix
+  const double tol = 4.0 * eps;
+  int ihi = m - 1, its = 0, total = 0;
+  bool failed = false;
+  while (ihi >= 0) {
+    int l = 0;
+    for (int k = ihi; k >= 1; --k) {
+      if (cabs1(H[k + int64_t(k - 1) * m]) <= tol) {
+        l = k;
+        break;
+      }
+    }
+    __syncthreads();
+    if (l == ihi) {
+      if (lane == 0) {
+        slam[ihi] = H[ihi + int64_t(ihi) * m];
+        if (ihi > 0) H[ihi + int64_t(ihi - 1) * m] = make_double2(0.0, 0.0);
+      }
+      --ihi;
+      its = 0;
+      __syncthreads();
+      continue;
+    }
+    if (l > 0 && lane == 0) H[l + int64_t(l - 1) * m] = make_double2(0.0, 0.0);
+    double2 mu;
+    const double2 dd = H[ihi + int64_t(ihi) * m];
+    if (its == 10 || its == 20) {
+      mu = make_double2(dd.x + 0.75 * cabs1(H[ihi + int64_t(ihi - 1) * m]), dd.y);
+    } else {
+      const double2 a = H[(ihi - 1) + int64_t(ihi - 1) * m], b = H[(ihi - 1) + int64_t(ihi) * m],
+                    c = H[ihi + int64_t(ihi - 1) * m];
+      const double2 t = make_double2(0.5 * (a.x - dd.x), 0.5 * (a.y - dd.y));
+      const double2 disc = csqrt_d(be::cadd(be::cmul(t, t), be::cmul(b, c)));
+      const double sgn = (t.x * disc.x + t.y * disc.y) >= 0.0 ? -1.0 : 1.0;
+      mu = make_double2(dd.x + t.x + sgn * disc.x, dd.y + t.y + sgn * disc.y);
+    }
+    __syncthreads();
+    for (int k = l; k < ihi; ++k) {
+      double2 f, g;
+      if (k == l) {
+        f = be::csub(H[l + int64_t(l) * m], mu);
+        g = H[(l + 1) + int64_t(l) * m];
+      } else {
+        f = H[k + int64_t(k - 1) * m];
+        g = H[(k + 1) + int64_t(k - 1) * m];
+      }
+      // rotation [c s; -conj(s) c] [f; g] = [r; 0]
+      double cr;
+      double2 sn, rr;
+      const double af = hypot(f.x, f.y), ag = hypot(g.x, g.y);
+      if (ag == 0.0) {
+        cr = 1.0;
+        sn = make_double2(0.0, 0.0);
+        rr = f;
+      } else if (af == 0.0) {
+        cr = 0.0;
+        sn = make_double2(g.x / ag, -g.y / ag);
+        rr = make_double2(ag, 0.0);
+      } else {
+        const double nrm = hypot(af, ag);
+        const double2 fu = make_double2(f.x / af, f.y / af);
+        cr = af / nrm;
+        sn = be::cscale(be::cmul(fu, be::cconj(g)), 1.0 / nrm);
+        rr = be::cscale(fu, nrm);
+      }
+      __syncthreads();
+      if (k > l && lane == 0) {
+        H[k + int64_t(k - 1) * m] = rr;
+        H[(k + 1) + int64_t(k - 1) * m] = make_double2(0.0, 0.0);
+      }
+      // rows k, k+1 over columns k..ihi
+      for (int c = k + lane; c <= ihi; c += 64) {
+        double2 x = H[k + int64_t(c) * m], y = H[(k + 1) + int64_t(c) * m];
+        H[k + int64_t(c) * m] = be::cadd(be::cscale(x, cr), be::cmul(sn, y));
+        H[(k + 1) + int64_t(c) * m] = be::csub(be::cscale(y, cr), be::cmul(be::cconj(sn), x));
+      }
+      __syncthreads();
+      // columns k, k+1 over rows l..min(k+2, ihi)
+      const int rmax = min(k + 2, ihi);
+      for (int r = l + lane; r <= rmax; r += 64) {
+        double2 x = H[r + int64_t(k) * m], y = H[r + int64_t(k + 1) * m];
+        H[r + int64_t(k) * m] = be::cadd(be::cscale(x, cr), be::cmul(be::cconj(sn), y));
+        H[r + int64_t(k + 1) * m] = be::csub(be::cscale(y, cr), be::cmul(sn, x));
+      }
+      if (Z) {
+        for (int r = lane; r < m; r += 64) {
+          double2 x = Z[r + int64_t(k) * m], y = Z[r + int64_t(k + 1) * m];
+          Z[r + int64_t(k) * m] = be::cadd(be::cscale(x, cr), be::cmul(be::cconj(sn), y));
+          Z[r + int64_t(k + 1) * m] = be::csub(be::cscale(y, cr), be::cmul(sn, x));
+        }
+      }
+      __syncthreads();
+    }
+    ++its;
+    ++total;
+    if (total > 60 * m + 60) {
+      failed = true;
+      // take the remaining diagonal as it stands
+      for (int r = lane; r <= ihi; r += 64) slam[r] = H[r + int64_t(r) * m];
+      __syncthreads();
+      break;
+    }
+  }
+  __syncthreads();
+  // ---- phases, ascending rank sort
+  for (int n = lane; n < m; n += 64) {
+    double2 z = slam[n];
+    double th = arg_pi(z);
+    if (theta_raw) theta_raw[q * m + n] = th;
+    int rank = 0;
+    for (int k = 0; k < m; ++k) {
+      double tk = arg_pi(slam[k]);
+      rank += (tk < th) || (tk == th && k < n);
+    }
+    theta_sorted[q * int64_t(ldt) + rank] = th;
+  }
+  if (failed && lane == 0) atomicOr(&flags[q / flag_div], BE_ST_NONCONVERGED);
+}
+
+// Chern winding of each system from theta [line][ldt] (first m valid).
+__global__ void k_winding(const double *theta, int ldt, int m, int n_sys, int n_perp, double *phi, int32_t *winding,
+                          uint32_t *status) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  double total = 0.0, dmax = 0.0;
+  double prev = 0.0, first = 0.0;
+  for (int i = 0; i <= n_perp; ++i) {
+    double ph;
+    if (i < n_perp) {
+      double acc = 0.0;
+      const double *th = theta + (int64_t(s) * n_perp + i) * ldt;
+      for (int n = 0; n < m; ++n) acc += th[n];
+      ph = acc - TWO_PI * floor(acc / TWO_PI);
+      if (ph >= TWO_PI) ph -= TWO_PI;
+      if (phi) phi[int64_t(s) * n_perp + i] = ph;
+      if (i == 0) first = ph;
+    } else {
+      ph = first;
+    }
+    if (i > 0) {
+      double d = ph - prev;
+      d -= TWO_PI * rint(d / TWO_PI);
+      total += d;
+      dmax = fmax(dmax, fabs(d));
+    }
+    prev = ph;
+  }
+  double c = total / TWO_PI;
+  int ci = int(rint(c));
+  winding[s] = ci;
+  if (dmax > 0.8 * M_PI || fabs(c - ci) > 1e-6) atomicOr(&status[s], BE_ST_WINDING_UNRESOLVED);
+}
+
+// OR line flags into system flags
+__global__ void k_or_lines(const uint32_t *line_st, int64_t n_lines, int per_sys, uint32_t *sys_st) {
+  int64_t line = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (line >= n_lines) return;
+  uint32_t v = line_st[line];
+  if (v) atomicOr(&sys_st[line / per_sys], v);
+}
+
+}  // namespace
+
+namespace be {
+
+// Wilson loops of n_lines closed lines of a grid of N x m matrices.
+// theta_sorted: [line][ldt]; Zout/theta_raw: optional eigenvectors of each W
+// (m x m per line) and the phase of each column. Fkeep: if non-null receives
+// the (polar) overlaps, [line][n_loop] m x m, which stay valid until the next
+// call that uses slot WS_WILSON. line_status: [n_lines], OR-ed.
+static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n_loop, int mode, double *theta_sorted,
+                       int ldt, double2 *Zout, double *theta_raw, uint32_t *line_status, const double2 **Fkeep,
+                       hipStream_t stream) {
+  if (n_lines == 0) return BE_OK;
+  if (m == 0) return BE_OK;
+  const int64_t mm = int64_t(m) * m;
+  const int64_t nm = n_lines * n_loop;
+  double2 *F = nullptr, *B1 = nullptr, *B2 = nullptr, *Hs = nullptr;
+  double *err = nullptr;
+  unsigned long long *gmax = nullptr;
+  Carve cv;
+  cv.add(&F, size_t(nm * mm));
+  cv.add(&B1, size_t(nm * mm));
+  cv.add(&B2, size_t(nm * mm));
+  cv.add(&Hs, size_t(n_lines * mm));
+  cv.add(&err, size_t(nm));
+  cv.add(&gmax, 1);
+  BE_RET_IF(cv.commit(ctx, stream, WS_WILSON));
+  // ---- overlaps
+  {
+    ZGemm g;
+    g.M = m;
+    g.N = m;
+    g.K = N;
+    g.opA = 1;
+    g.opB = 0;
+    g.A = U.base;
+    g.lda = U.ld;
+    g.bA = ZBatch::cyclic(U.stride, n_loop, 1, int64_t(n_loop) * U.stride);
+    g.B = U.base;
+    g.ldb = U.ld;
+    g.bB = ZBatch::cyclic(U.stride, n_loop, 0, int64_t(n_loop) * U.stride);
+    g.C = F;
+    g.ldc = m;
+    g.bC = ZBatch::strided(mm);
+    g.batch = nm;
+    BE_RET_IF(zgemm(ctx, g, stream));
+  }
+  // ---- polar factors (Newton-Schulz)
+  if (mode == BE_OVL_POLAR) {
+    double2 *X = F, *Xn = B2;
+    double *hmax = static_cast<double *>(ctx->pinned);
+    int it = 0;
+    bool converged = false;
+    for (; it < 80; ++it) {
+      BE_HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), stream));
+      ZGemm g;  // G = X^H X
+      g.M = m;
+      g.N = m;
+      g.K = m;
+      g.opA = 1;
+      g.A = X;
+      g.lda = m;
+      g.bA = ZBatch::strided(mm);
+      g.B = X;
+      g.ldb = m;
+      g.bB = ZBatch::strided(mm);
+      g.C = B1;
+      g.ldc = m;
+      g.bC = ZBatch::strided(mm);
+      g.batch = nm;
+      BE_RET_IF(zgemm(ctx, g, stream));
+      hipLaunchKernelGGL(k_ns_prep, dim3(static_cast<uint32_t>(nm)), dim3(256), 0, stream, B1, m, nm, err, gmax);
+      BE_RET_IF(check_launch(ctx, "ns_prep"));
+      BE_HIP_TRY(ctx, hipMemcpyAsync(hmax, gmax, sizeof(double), hipMemcpyDeviceToHost, stream));
+      BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+      const double e = *hmax;
+      ZGemm h;  // Xn = X (1.5 I - 0.5 G)
+      h.M = m;
+      h.N = m;
+      h.K = m;
+      h.A = X;
+      h.lda = m;
+      h.bA = ZBatch::strided(mm);
+      h.B = B1;
+      h.ldb = m;
+      h.bB = ZBatch::strided(mm);
+      h.C = Xn;
+      h.ldc = m;
+      h.bC = ZBatch::strided(mm);
+      h.batch = nm;
+      if (e < 1e-30) break;  // already unitary to working precision
+      BE_RET_IF(zgemm(ctx, h, stream));
+      std::swap(X, Xn);
+      if (e < 1e-9) {
+        // quadratic convergence: one more step after this brings the
+        // error below 1e-17 relative; stop after it
+        if (e < 1e-13) {
+          converged = true;
+          ++it;
+          break;
+        }
+      }
+    }
+    if (X != F) {
+      hipLaunchKernelGGL(k_copy_mats, dim3(64, static_cast<uint32_t>(std::min<int64_t>(nm, 65535))), dim3(256), 0, stream,
+                         X, mm, F, mm, mm, nm);
+      BE_RET_IF(check_launch(ctx, "copy_mats"));
+    }
+    (void)converged;
+    // matrices whose Gram error never fell below 1e-9 are (near) singular
+    hipLaunchKernelGGL(k_flag_err, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, err,
+                       n_lines, n_loop, 1e-9, BE_ST_OVERLAP_SINGULAR, line_status);
+    BE_RET_IF(check_launch(ctx, "flag_err"));
+  }
+  if (Fkeep) *Fkeep = F;
+  // ---- ordered product W = F_{n-1} ... F_0 (tree)
+  const double2 *cur = F;
+  int n = n_loop;
+  double2 *bufs[2] = {B1, B2};
+  int which = 0;
+  while (n > 1) {
+    const int half = n / 2, n2 = (n + 1) / 2;
+    double2 *dst = bufs[which];
+    ZGemm g;  // dst[k] = cur[2k+1] cur[2k]
+    g.M = m;
+    g.N = m;
+    g.K = m;
+    g.A = cur + mm;
+    g.lda = m;
+    g.bA = ZBatch::cyclic(2 * mm, half, 0, int64_t(n) * mm);
+    g.B = cur;
+    g.ldb = m;
+    g.bB = ZBatch::cyclic(2 * mm, half, 0, int64_t(n) * mm);
+    g.C = dst;
+    g.ldc = m;
+    g.bC = ZBatch::cyclic(mm, half, 0, int64_t(n2) * mm);
+    g.batch = n_lines * half;
+    BE_RET_IF(zgemm(ctx, g, stream));
+    if (n & 1) {
+      hipLaunchKernelGGL(k_carry_last, dim3(16, static_cast<uint32_t>(std::min<int64_t>(n_lines, 65535))), dim3(256), 0,
+                         stream, cur, n, dst, n2, mm, n_lines);
+      BE_RET_IF(check_launch(ctx, "carry_last"));
+    }
+    cur = dst;
+    which ^= 1;
+    n = n2;
+  }
+  // cur now holds W per line (n_loop == 1 means W = F_0)
+  // ---- eigenphases
+  const size_t esm = 2 * size_t(m) * sizeof(double2);
+  if (esm > 65536)
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
+  hipLaunchKernelGGL(k_unitary_eig, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs,
+                     Zout, theta_sorted, ldt, theta_raw, line_status, 1);
+  return check_launch(ctx, "unitary_eig");
+}
+
+}  // namespace be
+
+// ============================================================================ C ABI
+
+namespace {
+
+int check_grid_args(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride, int32_t n_sys,
+                    int32_t n_par, int32_t n_perp, int32_t mode) {
+  using namespace be;
+  BE_CHECK_ARG(ctx, ctx && U, "null U");
+  BE_CHECK_ARG(ctx, N >= 1 && m >= 0 && m <= N, "need 0 <= m <= N");
+  BE_CHECK_ARG(ctx, ldu >= N && u_stride >= int64_t(ldu) * std::max(m, 1), "ldu < N or u_stride < ldu*m");
+  BE_CHECK_ARG(ctx, n_sys >= 0 && n_par >= 1 && n_perp >= 1, "need n_sys >= 0, n_par >= 1, n_perp >= 1");
+  BE_CHECK_ARG(ctx, mode == BE_OVL_POLAR || mode == BE_OVL_RAW, "mode must be BE_OVL_POLAR or BE_OVL_RAW");
+  return BE_OK;
+}
+
+}  // namespace
+
+extern "C" int be_wilson_loop(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                              int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, double *theta, double *phi,
+                              int32_t *winding, uint32_t *status, hipStream_t stream) {
+  using namespace be;
+  BE_RET_IF(check_grid_args(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode));
+  BE_CHECK_ARG(ctx, theta && phi && winding && status, "be_wilson_loop: null output");
+  if (n_sys == 0) return BE_OK;
+  const int64_t n_lines = int64_t(n_sys) * n_perp;
+  uint32_t *line_st = nullptr;
+  Carve cv;
+  cv.add(&line_st, size_t(n_lines));
+  BE_RET_IF(cv.commit(ctx, stream, WS_OUTER));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, line_st, n_lines);
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
+                     int64_t(n_sys));
+  BE_RET_IF(check_launch(ctx, "zero"));
+  Grid g{static_cast<const double2 *>(U), ldu, u_stride};
+  BE_RET_IF(wilson_core(ctx, g, N, m, n_lines, n_par, mode, theta, m, nullptr, nullptr, line_st, nullptr, stream));
+  hipLaunchKernelGGL(k_or_lines, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, line_st,
+                     n_lines, n_perp, status);
+  hipLaunchKernelGGL(k_winding, dim3((n_sys + 63) / 64), dim3(64), 0, stream, theta, m, m, n_sys, n_perp, phi, winding,
+                     status);
+  return check_launch(ctx, "winding");
+}
+
+// ---------------------------------------------------------------- nested Wilson loop
+namespace {
+
+// Per line: sector = columns n of Z with x = theta_raw/2pi in (lo, hi).
+// Writes s_line[line]; flags WANNIER_GAP if a phase is within 1e-6 of a window edge.
+__global__ void k_sector_count(const double *theta_raw, int m, int64_t n_lines, double lo, double hi, int32_t *s_line,
+                               uint32_t *line_st) {
+  int64_t line = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (line >= n_lines) return;
+  int s = 0;
+  bool edge = false;
+  for (int n = 0; n < m; ++n) {
+    double x = theta_raw[line * m + n] / TWO_PI;
+    if (x > lo && x < hi) ++s;
+    if (fabs(x - lo) < 1e-6 || fabs(x - hi) < 1e-6) edge = true;
+  }
+  s_line[line] = s;
+  if (edge) line_st[line] |= BE_ST_WANNIER_GAP;
+}
+
+// Per system: sector size of line 0; WANNIER_GAP if any line differs.
+__global__ void k_sector_sys(const int32_t *s_line, int n_sys, int n_perp, int32_t *s_sys, uint32_t *status) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  int s0 = s_line[int64_t(s) * n_perp];
+  for (int i = 1; i < n_perp; ++i)
+    if (s_line[int64_t(s) * n_perp + i] != s0) atomicOr(&status[s], BE_ST_WANNIER_GAP);
+  s_sys[s] = s0;
+}
+
+// nu[line][0] = Z_line[:, sector] (m x sc, ld m), in the order of the columns.
+__global__ void k_gather_sector(const double2 *Z, const double *theta_raw, int m, int64_t n_lines, double lo, double hi,
+                                int sc, int n_loop, double2 *nu) {
+  int64_t line = blockIdx.x;
+  if (line >= n_lines) return;
+  int col = 0;
+  for (int n = 0; n < m; ++n) {
+    double x = theta_raw[line * m + n] / TWO_PI;
+    if (x > lo && x < hi) {
+      if (col < sc)
+        for (int r = threadIdx.x; r < m; r += blockDim.x)
+          nu[(line * n_loop) * int64_t(m) * sc + r + int64_t(col) * m] = Z[line * int64_t(m) * m + r + int64_t(n) * m];
+      ++col;
+    }
+  }
+}
+
+// p[s][j] and p_mean[s] from nested theta [s][j][ldt] (first sc valid).
+__global__ void k_nested_p(const double *th, int ldt, int sc, int n_sys, int n_par, double *p, double *p_mean) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  double prev = 0.0, acc_u = 0.0, sum = 0.0;
+  for (int j = 0; j < n_par; ++j) {
+    double a = 0.0;
+    const double *t = th + (int64_t(s) * n_par + j) * ldt;
+    for (int n = 0; n < sc; ++n) a += t[n];
+    double pj = a / TWO_PI;
+    pj -= rint(pj);
+    if (pj <= -0.5) pj += 1.0;
+    if (pj > 0.5) pj -= 1.0;
+    if (fabs(fabs(pj) - 0.5) < 1e-15) pj = 0.5;
+    p[int64_t(s) * n_par + j] = pj;
+    if (j == 0) {
+      acc_u = pj;
+    } else {
+      double d = pj - prev;
+      d -= rint(d);
+      acc_u += d;
+    }
+    sum += acc_u;
+    prev = pj;
+  }
+  double mean = sum / n_par;
+  mean -= floor(mean);
+  if (mean >= 1.0) mean -= 1.0;
+  p_mean[s] = mean;
+}
+
+__global__ void k_fill_nan(double *p, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = NAN;
+}
+
+}  // namespace
+
+extern "C" int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                                int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, double win_lo,
+                                double win_hi, double *nested_theta, double *p, double *p_mean, int32_t *s_out_h,
+                                uint32_t *status, hipStream_t stream) {
+  using namespace be;
+  BE_RET_IF(check_grid_args(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode));
+  BE_CHECK_ARG(ctx, nested_theta && p && p_mean && s_out_h && status, "be_nested_wilson: null output");
+  BE_CHECK_ARG(ctx, win_lo < win_hi, "be_nested_wilson: need win_lo < win_hi");
+  if (n_sys == 0) return BE_OK;
+  const int64_t n_lines = int64_t(n_sys) * n_perp;
+  const int64_t mm = int64_t(m) * m;
+  uint32_t *line_st = nullptr, *line_st2 = nullptr;
+  double *th0 = nullptr, *thraw = nullptr;
+  double2 *Z = nullptr, *nu = nullptr, *w = nullptr;
+  int32_t *s_line = nullptr, *s_sys = nullptr;
+  Carve cv;
+  cv.add(&line_st, size_t(n_lines));
+  cv.add(&line_st2, size_t(int64_t(n_sys) * n_par));
+  cv.add(&th0, size_t(n_lines * std::max(m, 1)));
+  cv.add(&thraw, size_t(n_lines * std::max(m, 1)));
+  cv.add(&Z, size_t(n_lines * std::max<int64_t>(mm, 1)));
+  cv.add(&nu, size_t(n_lines * n_par * std::max<int64_t>(mm, 1)));
+  cv.add(&w, size_t(n_lines * n_par * int64_t(N) * std::max(m, 1)));
+  cv.add(&s_line, size_t(n_lines));
+  cv.add(&s_sys, size_t(n_sys));
+  BE_RET_IF(cv.commit(ctx, stream, WS_OUTER));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, line_st, n_lines);
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys * int64_t(n_par) + 255) / 256)), dim3(256), 0, stream,
+                     line_st2, int64_t(n_sys) * n_par);
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
+                     int64_t(n_sys));
+  hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<uint32_t>((int64_t(n_sys) * n_par * std::max(m, 1) + 255) / 256)), dim3(256),
+                     0, stream, nested_theta, int64_t(n_sys) * n_par * std::max(m, 1));
+  BE_RET_IF(check_launch(ctx, "zero"));
+  for (int s = 0; s < n_sys; ++s) s_out_h[s] = 0;
+  if (m == 0) return BE_OK;
+  // ---- first Wilson loop at base point 0 with eigenvectors; keep the overlaps
+  Grid g{static_cast<const double2 *>(U), ldu, u_stride};
+  const double2 *F = nullptr;
+  BE_RET_IF(wilson_core(ctx, g, N, m, n_lines, n_par, mode, th0, m, Z, thraw, line_st, &F, stream));
+  // ---- sector sizes
+  hipLaunchKernelGGL(k_sector_count, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, thraw, m,
+                     n_lines, win_lo, win_hi, s_line, line_st);
+  hipLaunchKernelGGL(k_or_lines, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, line_st,
+                     n_lines, n_perp, status);
+  hipLaunchKernelGGL(k_sector_sys, dim3((n_sys + 63) / 64), dim3(64), 0, stream, s_line, n_sys, n_perp, s_sys, status);
+  BE_RET_IF(check_launch(ctx, "sector"));
+  int32_t *hs = static_cast<int32_t *>(ctx->pinned);
+  BE_CHECK_ARG(ctx, n_sys <= 1024, "be_nested_wilson: at most 1024 systems per call");
+  BE_HIP_TRY(ctx, hipMemcpyAsync(hs, s_sys, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost, stream));
+  BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+  for (int s = 0; s < n_sys; ++s) s_out_h[s] = hs[s];
+  // ---- pass 1, per run of systems with equal sector size: carry the sector
+  // to every base point and form w (needs the overlaps F of the first loop)
+  std::vector<int64_t> w_off(n_sys + 1, 0);
+  for (int s = 0; s < n_sys; ++s) w_off[s + 1] = w_off[s] + int64_t(n_perp) * n_par * N * s_out_h[s];
+  for (int s0 = 0; s0 < n_sys;) {
+    const int sc = s_out_h[s0];
+    int s1 = s0 + 1;
+    while (s1 < n_sys && s_out_h[s1] == sc) ++s1;
+    if (sc == 0) {
+      s0 = s1;
+      continue;
+    }
+    const int64_t l0 = int64_t(s0) * n_perp, nl = int64_t(s1 - s0) * n_perp;
+    const int64_t nus = int64_t(m) * sc;  // one nu block
+    hipLaunchKernelGGL(k_gather_sector, dim3(static_cast<uint32_t>(nl)), dim3(64), 0, stream, Z + l0 * mm, thraw + l0 * m, m,
+                       nl, win_lo, win_hi, sc, n_par, nu);
+    BE_RET_IF(check_launch(ctx, "gather_sector"));
+    // transport nu[line][j+1] = F[line][j] nu[line][j]
+    for (int j = 0; j + 1 < n_par; ++j) {
+      ZGemm t;
+      t.M = m;
+      t.N = sc;
+      t.K = m;
+      t.A = F + (l0 * n_par + j) * mm;
+      t.lda = m;
+      t.bA = ZBatch::strided(int64_t(n_par) * mm);
+      t.B = nu + int64_t(j) * nus;
+      t.ldb = m;
+      t.bB = ZBatch::strided(int64_t(n_par) * nus);
+      t.C = nu + int64_t(j + 1) * nus;
+      t.ldc = m;
+      t.bC = ZBatch::strided(int64_t(n_par) * nus);
+      t.batch = nl;
+      BE_RET_IF(zgemm(ctx, t, stream));
+    }
+    // w[s][j][i] = U[s][i][j] nu[(s,i)][j]   (N x sc, ld N)
+    const int64_t ws = int64_t(N) * sc;
+    ZGemm t;
+    t.M = N;
+    t.N = sc;
+    t.K = m;
+    t.A = static_cast<const double2 *>(U) + l0 * n_par * u_stride;
+    t.lda = ldu;
+    t.bA = ZBatch::strided(u_stride);
+    t.B = nu;
+    t.ldb = m;
+    t.bB = ZBatch::strided(nus);
+    t.C = w + w_off[s0];
+    t.ldc = N;
+    ZBatch bc;
+    bc.s0 = int64_t(n_perp) * ws;  // j
+    bc.n0 = n_par;
+    bc.s1 = ws;  // i
+    bc.n1 = n_perp;
+    bc.s2 = int64_t(n_par) * n_perp * ws;
+    t.bC = bc;
+    t.batch = nl * n_par;
+    BE_RET_IF(zgemm(ctx, t, stream));
+    s0 = s1;
+  }
+  // ---- pass 2: nested loops along the transverse direction, one per (system, j)
+  for (int s0 = 0; s0 < n_sys;) {
+    const int sc = s_out_h[s0];
+    int s1 = s0 + 1;
+    while (s1 < n_sys && s_out_h[s1] == sc) ++s1;
+    if (sc == 0) {
+      s0 = s1;
+      continue;
+    }
+    const int64_t ws = int64_t(N) * sc;
+    Grid gw{w + w_off[s0], N, ws};
+    const int64_t nl2 = int64_t(s1 - s0) * n_par;
+    BE_RET_IF(wilson_core(ctx, gw, N, sc, nl2, n_perp, mode, nested_theta + int64_t(s0) * n_par * m, m, nullptr, nullptr,
+                          line_st2 + int64_t(s0) * n_par, nullptr, stream));
+    hipLaunchKernelGGL(k_or_lines, dim3(static_cast<uint32_t>((nl2 + 255) / 256)), dim3(256), 0, stream,
+                       line_st2 + int64_t(s0) * n_par, nl2, n_par, status + s0);
+    hipLaunchKernelGGL(k_nested_p, dim3((s1 - s0 + 63) / 64), dim3(64), 0, stream, nested_theta + int64_t(s0) * n_par * m, m,
+                       sc, s1 - s0, n_par, p + int64_t(s0) * n_par, p_mean + s0);
+    BE_RET_IF(check_launch(ctx, "nested_p"));
+    s0 = s1;
+  }
+  return BE_OK;
+}
+
+// ---------------------------------------------------------------- spin-resolved Wilson loop
+namespace {
+
+// SU[k] = diag(spin) U[k] for every k of every system (N x m, ld N)
+__global__ void k_spin_scale(const double2 *U, int ldu, int64_t us, const double *spin, int N, int m, int64_t k_per_sys,
+                             int64_t n_k, double2 *SU) {
+  for (int64_t k = blockIdx.y; k < n_k; k += gridDim.y) {
+    const double *sd = spin + (k / k_per_sys) * N;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < int64_t(N) * m; e += int64_t(gridDim.x) * blockDim.x) {
+      int c = int(e / N), r = int(e % N);
+      SU[k * int64_t(N) * m + e] = be::cscale(U[k * us + r + int64_t(c) * ldu], sd[r]);
+    }
+  }
+}
+
+// Projected-spin eigenvalues: copy into the output, count negatives, flag gaps.
+__global__ void k_pso_post(const double *ev, int m, int64_t n_k, int64_t k_per_sys, double *pso, int32_t *cnt,
+                           uint32_t *status) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n_k) return;
+  int c = 0;
+  double mn = INFINITY;
+  for (int n = 0; n < m; ++n) {
+    double v = ev[k * (m + 2) + 1 + n];
+    pso[k * m + n] = v;
+    c += v < 0.0;
+    mn = fmin(mn, fabs(v));
+  }
+  cnt[k] = c;
+  if (!(mn >= 1e-6)) atomicOr(&status[k / k_per_sys], BE_ST_PSO_GAP);
+}
+
+__global__ void k_pso_sys(const int32_t *cnt, int n_sys, int64_t k_per_sys, int32_t *m_dn, uint32_t *status) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  int c0 = cnt[int64_t(s) * k_per_sys];
+  for (int64_t k = 1; k < k_per_sys; ++k)
+    if (cnt[int64_t(s) * k_per_sys + k] != c0) {
+      atomicOr(&status[s], BE_ST_PSO_GAP);
+      break;
+    }
+  m_dn[s] = c0;
+}
+
+__global__ void k_spin_chern(const int32_t *cd, const int32_t *cu, int n, double *cs) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) cs[s] = 0.5 * double(cu[s] - cd[s]);
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                                       int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode,
+                                       const double *spin_diag, double *pso_evals, double *theta_dn, double *theta_up,
+                                       int32_t *C_dn, int32_t *C_up, double *C_s, int32_t *m_dn_h, uint32_t *status,
+                                       hipStream_t stream) {
+  using namespace be;
+  BE_RET_IF(check_grid_args(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode));
+  BE_CHECK_ARG(ctx, spin_diag && pso_evals && theta_dn && theta_up && C_dn && C_up && C_s && m_dn_h && status,
+               "be_spin_resolved_wilson: null argument");
+  BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_resolved_wilson: at most 1024 systems per call");
+  if (n_sys == 0) return BE_OK;
+  const int64_t kps = int64_t(n_par) * n_perp;
+  const int64_t n_k = int64_t(n_sys) * kps;
+  const int64_t n_lines = int64_t(n_sys) * n_perp;
+  const int64_t mm = int64_t(m) * std::max(m, 1);
+  const int64_t Nm = int64_t(N) * std::max(m, 1);
+  double2 *SU = nullptr, *A = nullptr, *Q = nullptr, *V = nullptr;
+  double *ev = nullptr;
+  uint32_t *kst = nullptr, *lst = nullptr;
+  int32_t *cnt = nullptr, *mdn = nullptr;
+  Carve cv;
+  cv.add(&SU, size_t(n_k * Nm));
+  cv.add(&A, size_t(n_k * mm));
+  cv.add(&Q, size_t(n_k * mm));
+  cv.add(&V, size_t(n_k * Nm));
+  cv.add(&ev, size_t(n_k * (m + 2)));
+  cv.add(&kst, size_t(n_k));
+  cv.add(&lst, size_t(2 * n_lines));
+  cv.add(&cnt, size_t(n_k));
+  cv.add(&mdn, size_t(n_sys));
+  BE_RET_IF(cv.commit(ctx, stream, WS_OUTER));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
+                     int64_t(n_sys));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((2 * n_lines + 255) / 256)), dim3(256), 0, stream, lst,
+                     2 * n_lines);
+  BE_RET_IF(check_launch(ctx, "zero"));
+  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
+  if (m == 0) return BE_OK;
+  // ---- A = U^H S U
+  hipLaunchKernelGGL(k_spin_scale, dim3(64, static_cast<uint32_t>(std::min<int64_t>(n_k, 65535))), dim3(256), 0, stream,
+                     static_cast<const double2 *>(U), ldu, u_stride, spin_diag, N, m, kps, n_k, SU);
+  BE_RET_IF(check_launch(ctx, "spin_scale"));
+  {
+    ZGemm g;
+    g.M = m;
+    g.N = m;
+    g.K = N;
+    g.opA = 1;
+    g.A = static_cast<const double2 *>(U);
+    g.lda = ldu;
+    g.bA = ZBatch::strided(u_stride);
+    g.B = SU;
+    g.ldb = N;
+    g.bB = ZBatch::strided(Nm);
+    g.C = A;
+    g.ldc = m;
+    g.bC = ZBatch::strided(mm);
+    g.batch = n_k;
+    BE_RET_IF(zgemm(ctx, g, stream));
+  }
+  // ---- eigh of the m x m projected spin operator (all bands)
+  BE_RET_IF(eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream));
+  hipLaunchKernelGGL(k_pso_post, dim3(static_cast<uint32_t>((n_k + 255) / 256)), dim3(256), 0, stream, ev, m, n_k, kps,
+                     pso_evals, cnt, status);
+  hipLaunchKernelGGL(k_pso_sys, dim3((n_sys + 63) / 64), dim3(64), 0, stream, cnt, n_sys, kps, mdn, status);
+  BE_RET_IF(check_launch(ctx, "pso"));
+  int32_t *hm = static_cast<int32_t *>(ctx->pinned);
+  BE_HIP_TRY(ctx, hipMemcpyAsync(hm, mdn, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost, stream));
+  BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = hm[s];
+  hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<uint32_t>((n_lines * m + 255) / 256)), dim3(256), 0, stream, theta_dn,
+                     n_lines * m);
+  hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<uint32_t>((n_lines * m + 255) / 256)), dim3(256), 0, stream, theta_up,
+                     n_lines * m);
+  hipLaunchKernelGGL(k_fill_i32, dim3((n_sys + 255) / 256), dim3(256), 0, stream, C_dn, int64_t(n_sys), 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3((n_sys + 255) / 256), dim3(256), 0, stream, C_up, int64_t(n_sys), 0);
+  BE_RET_IF(check_launch(ctx, "fill"));
+  // ---- per run of systems with equal sector sizes: V = U Q_sector, Wilson loop
+  for (int s0 = 0; s0 < n_sys;) {
+    const int md = m_dn_h[s0];
+    int s1 = s0 + 1;
+    while (s1 < n_sys && m_dn_h[s1] == md) ++s1;
+    const int64_t k0 = int64_t(s0) * kps, nk = int64_t(s1 - s0) * kps;
+    const int64_t l0 = int64_t(s0) * n_perp, nl = int64_t(s1 - s0) * n_perp;
+    for (int sector = 0; sector < 2; ++sector) {
+      const int ms = sector == 0 ? md : m - md;
+      const int c0 = sector == 0 ? 0 : md;
+      if (ms == 0) continue;
+      ZGemm g;
+      g.M = N;
+      g.N = ms;
+      g.K = m;
+      g.A = static_cast<const double2 *>(U) + k0 * u_stride;
+      g.lda = ldu;
+      g.bA = ZBatch::strided(u_stride);
+      g.B = Q + k0 * mm + int64_t(c0) * m;
+      g.ldb = m;
+      g.bB = ZBatch::strided(mm);
+      g.C = V;
+      g.ldc = N;
+      g.bC = ZBatch::strided(int64_t(N) * ms);
+      g.batch = nk;
+      BE_RET_IF(zgemm(ctx, g, stream));
+      Grid gv{V, N, int64_t(N) * ms};
+      double *th = (sector == 0 ? theta_dn : theta_up) + l0 * m;
+      uint32_t *ls = lst + sector * n_lines + l0;
+      BE_RET_IF(wilson_core(ctx, gv, N, ms, nl, n_par, mode, th, m, nullptr, nullptr, ls, nullptr, stream));
+      hipLaunchKernelGGL(k_or_lines, dim3(static_cast<uint32_t>((nl + 255) / 256)), dim3(256), 0, stream, ls, nl, n_perp,
+                         status + s0);
+      hipLaunchKernelGGL(k_winding, dim3((s1 - s0 + 63) / 64), dim3(64), 0, stream, th, m, ms, s1 - s0, n_perp, nullptr,
+                         (sector == 0 ? C_dn : C_up) + s0, status + s0);
+      BE_RET_IF(check_launch(ctx, "spin winding"));
+    }
+    s0 = s1;
+  }
+  hipLaunchKernelGGL(k_spin_chern, dim3((n_sys + 255) / 256), dim3(256), 0, stream, C_dn, C_up, n_sys, C_s);
+  return check_launch(ctx, "spin_chern");
+}

@@ -1,0 +1,133 @@
+"""Whole-plane drivers over the C ABI (orchestration only, no arithmetic).
+
+These chain the library calls the way the paper's functions are used:
+``wsurf`` (hybrid Wannier centres over a plane, Sec. II), ``wnwl`` (nested
+Wilson loop, Sec. III) and ``wspinsurf`` (spin-resolved Wilson loop, Sec. IV).
+Every step runs in the HIP library; torch only allocates device memory.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise L.BerryError("berryhip needs a HIP GPU (torch.cuda is not available)")
+    return torch
+
+
+@dataclass
+class EigGrid:
+    """Selected eigenvectors of every k-point of a plane for n_sys systems.
+
+    U has shape (n_sys * n_perp * n_par, m, ldu): matrix q is column-major N x m.
+    evals: (n_mat, m + 2), status: (n_mat,) int32.
+    """
+    U: "object"
+    evals: "object"
+    status: "object"
+    N: int
+    m: int
+    ldu: int
+    n_sys: int
+    n_par: int
+    n_perp: int
+
+
+def eig_grid(ctx: L.Context, plan: L.HkPlan, sys_first: int, n_sys: int, kappa_grid: np.ndarray, lo: int, hi: int,
+             precision: int = L.BE_FP64, chunk: int = 4096) -> EigGrid:
+    """build_hk + eigh_batched over a k-plane (n_perp, n_par, 3) for consecutive systems."""
+    torch = _torch()
+    n_perp, n_par = kappa_grid.shape[:2]
+    N = plan.N[sys_first]
+    m = hi - lo
+    n_k = n_perp * n_par
+    kap = torch.from_numpy(np.ascontiguousarray(kappa_grid.reshape(-1, 3), dtype=np.float64)).cuda()
+    n_mat = n_sys * n_k
+    ldu = N
+    U = torch.empty((n_mat, max(m, 1), ldu), dtype=torch.complex128, device="cuda")
+    ev = torch.empty((n_mat, m + 2), dtype=torch.float64, device="cuda")
+    st = torch.empty(n_mat, dtype=torch.int32, device="cuda")
+    cdt = torch.complex128 if precision == L.BE_FP64 else torch.complex64
+    dt = L.BE_C128 if precision == L.BE_FP64 else L.BE_C64
+    per = max(1, chunk // n_k)  # systems per chunk
+    H = torch.empty((min(per, n_sys) * n_k, N, N), dtype=cdt, device="cuda")
+    for s0 in range(0, n_sys, per):
+        ns = min(per, n_sys - s0)
+        ctx.build_hk(plan, sys_first + s0, ns, kap, H, N * N, N, dt)
+        q0 = s0 * n_k
+        ctx.eigh_batched(H, dt, N, N, N * N, ns * n_k, lo, hi, precision, ev[q0:], U[q0:], ldu, U.stride(0), st[q0:])
+    return EigGrid(U, ev, st, N, m, ldu, n_sys, n_par, n_perp)
+
+
+def wilson(ctx: L.Context, g: EigGrid, mode: int = L.BE_OVL_POLAR):
+    torch = _torch()
+    theta = torch.empty((g.n_sys, g.n_perp, max(g.m, 1)), dtype=torch.float64, device="cuda")
+    phi = torch.empty((g.n_sys, g.n_perp), dtype=torch.float64, device="cuda")
+    wind = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    st = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    ctx.wilson_loop(g.U, g.N, g.m, g.ldu, g.U.stride(0), g.n_sys, g.n_par, g.n_perp, mode, theta, phi, wind, st)
+    return {"theta": theta[..., :g.m], "phi": phi, "winding": wind, "status": st}
+
+
+def nested(ctx: L.Context, g: EigGrid, window=(0.0, 0.5), mode: int = L.BE_OVL_POLAR):
+    torch = _torch()
+    m = max(g.m, 1)
+    nth = torch.empty((g.n_sys, g.n_par, m), dtype=torch.float64, device="cuda")
+    p = torch.empty((g.n_sys, g.n_par), dtype=torch.float64, device="cuda")
+    pm = torch.empty(g.n_sys, dtype=torch.float64, device="cuda")
+    st = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    s = ctx.nested_wilson(g.U, g.N, g.m, g.ldu, g.U.stride(0), g.n_sys, g.n_par, g.n_perp, mode, window[0], window[1],
+                          nth, p, pm, st)
+    return {"theta": nth, "s": s, "p": p, "p_mean": pm, "status": st}
+
+
+def spin(ctx: L.Context, g: EigGrid, spin_diag, mode: int = L.BE_OVL_POLAR):
+    """spin_diag: (n_sys, N) float64 (numpy or torch)."""
+    torch = _torch()
+    m = max(g.m, 1)
+    sd = torch.as_tensor(np.asarray(spin_diag, dtype=np.float64).reshape(g.n_sys, g.N)).cuda()
+    pso = torch.empty((g.n_sys, g.n_perp, g.n_par, m), dtype=torch.float64, device="cuda")
+    tdn = torch.empty((g.n_sys, g.n_perp, m), dtype=torch.float64, device="cuda")
+    tup = torch.empty((g.n_sys, g.n_perp, m), dtype=torch.float64, device="cuda")
+    cdn = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    cup = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    cs = torch.empty(g.n_sys, dtype=torch.float64, device="cuda")
+    st = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    mdn = ctx.spin_resolved_wilson(g.U, g.N, g.m, g.ldu, g.U.stride(0), g.n_sys, g.n_par, g.n_perp, mode, sd, pso,
+                                   tdn, tup, cdn, cup, cs, st)
+    return {"mu": pso, "theta_dn": tdn, "theta_up": tup, "m_dn": mdn, "C_dn": cdn, "C_up": cup, "C_s": cs,
+            "status": st}
+
+
+def wsurf(ctx, hoplists: Sequence, kappa_grid, lo, hi, mode=L.BE_OVL_POLAR, precision=L.BE_FP64):
+    """Hybrid WCCs over a plane for systems of equal N (paper's WSurf)."""
+    plan = ctx.hk_plan(list(hoplists))
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision)
+    out = wilson(ctx, g, mode)
+    out["eig"] = g
+    return out
+
+
+def wnwl(ctx, hoplists: Sequence, kappa_grid, lo, hi, window=(0.0, 0.5), mode=L.BE_OVL_POLAR):
+    """Nested Wilson loop over a plane (paper's WNWL)."""
+    plan = ctx.hk_plan(list(hoplists))
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi)
+    out = nested(ctx, g, window, mode)
+    out["eig"] = g
+    return out
+
+
+def wspinsurf(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, mode=L.BE_OVL_POLAR):
+    """Spin-resolved WCCs over a plane (paper's WSpinSurf)."""
+    plan = ctx.hk_plan(list(hoplists))
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi)
+    out = spin(ctx, g, spin_diag, mode)
+    out["eig"] = g
+    return out

@@ -1,0 +1,108 @@
+"""GPU parity of the batched Hermitian eigensolver against the oracle.
+
+Eigenvalues are compared with LAPACK (through the oracle) to 1e-12 ||H||,
+the occupied projector U U^H to 1e-10, and U must be orthonormal.
+"""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import berry as orc
+from tests import gpu_util as gu
+
+torch = gu.torch
+pytestmark = pytest.mark.gpu
+
+
+def run_eigh(c, Hs, lo, hi, ld_pad=0):
+    """Hs: numpy (n, N, N). Returns evals (n, m+2), U (n, N, m), status."""
+    n, N, _ = Hs.shape
+    m = hi - lo
+    ld = N + ld_pad
+    dH = gu.from_np(Hs, ld)
+    ldu = N + 1
+    U = gu.colmajor(n, N, max(m, 1), ldu, fill=0)
+    ev = torch.empty((n, m + 2), dtype=torch.float64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    c.eigh_batched(dH, 0, N, ld, dH.stride(0), n, lo, hi, 0, ev, U, ldu, U.stride(0), st)
+    torch.cuda.synchronize()
+    return ev.cpu().numpy(), gu.to_np(U, N)[:, :, :m], st.cpu().numpy()
+
+
+def check(Hs, lo, hi, ev, U, st, expect_status=0):
+    for q in range(Hs.shape[0]):
+        H = Hs[q]
+        w, V = np.linalg.eigh(H)
+        nrm = max(1.0, np.max(np.abs(w)))
+        m = hi - lo
+        assert np.max(np.abs(ev[q, 1:m + 1] - w[lo:hi])) <= 1e-12 * nrm, q
+        if lo > 0:
+            assert abs(ev[q, 0] - w[lo - 1]) <= 1e-12 * nrm
+        else:
+            assert np.isnan(ev[q, 0])
+        if hi < H.shape[0]:
+            assert abs(ev[q, m + 1] - w[hi]) <= 1e-12 * nrm
+        else:
+            assert np.isnan(ev[q, m + 1])
+        if m:
+            Uq = U[q]
+            # inverse iteration keeps vectors of clusters more than 1e-3 ||T|| apart
+            # orthogonal to about eps ||T|| / gap, i.e. ~1e-12 with a small constant
+            assert np.max(np.abs(Uq.conj().T @ Uq - np.eye(m))) < 2e-11
+            P = Uq @ Uq.conj().T
+            Pref = V[:, lo:hi] @ V[:, lo:hi].conj().T
+            assert np.max(np.abs(P - Pref)) < 1e-10, (q, np.max(np.abs(P - Pref)))
+            assert np.max(np.abs(H @ Uq - Uq @ np.diag(ev[q, 1:m + 1]))) < 1e-11 * nrm
+        assert st[q] == expect_status, (q, st[q])
+
+
+@pytest.mark.parametrize("N,lo,hi", [(1, 0, 1), (2, 0, 1), (3, 1, 2), (5, 0, 5), (31, 3, 17), (32, 0, 16),
+                                     (33, 0, 16), (70, 10, 45), (100, 0, 50), (129, 64, 129)])
+def test_eigh_random_hermitian(N, lo, hi):
+    gu.need_gpu()
+    rng = np.random.default_rng(N)
+    A = rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))
+    Hs = A + np.conj(np.swapaxes(A, 1, 2))
+    c = gu.ctx()
+    ev, U, st = run_eigh(c, Hs, lo, hi, ld_pad=2)
+    check(Hs, lo, hi, ev, U, st)
+
+
+@pytest.mark.parametrize("name", ["qwz", "bbh", "bhz_clean_L3", "bhz_L10_W2", "bhz_vac_L6", "wannier96"])
+def test_eigh_model_hamiltonians(name):
+    gu.need_gpu()
+    hl = {"qwz": lambda: syn.qwz(-1.0), "bbh": lambda: syn.bbh(0.5, 1.0),
+          "bhz_clean_L3": lambda: syn.supercell(syn.bhz(), 3),
+          "bhz_L10_W2": lambda: syn.bhz_disordered(10, 2.0, [3, 2, 1]),
+          "bhz_vac_L6": lambda: syn.bhz_vacancies(6, 0.05, [4, 1, 3]),
+          "wannier96": lambda: syn.wannier_like(96, [5, 2, 1])}[name]()
+    kap = syn.kplane(3, 2).reshape(-1, 3)
+    Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in kap])
+    c = gu.ctx()
+    m = hl.N // 2
+    ev, U, st = run_eigh(c, Hs, 0, m)
+    check(Hs, 0, m, ev, U, st)
+
+
+def test_eigh_degenerate_clusters_and_gap_flag():
+    """Clean supercell at kappa = 0 has large degenerate clusters; the atomic
+    model with a degenerate Fermi level must raise GAP_CLOSED."""
+    gu.need_gpu()
+    hl = syn.supercell(syn.bhz(), 4)
+    Hs = np.stack([orc.bloch_hamiltonian(hl, [0.0, 0.0, 0.0]), orc.bloch_hamiltonian(hl, [0.5, 0.5, 0.0])])
+    c = gu.ctx()
+    ev, U, st = run_eigh(c, Hs, 0, hl.N // 2)
+    check(Hs, 0, hl.N // 2, ev, U, st)
+    Ha = np.stack([orc.bloch_hamiltonian(syn.atomic([0.0, 0.0, 1.0, 2.0]), [0, 0])])
+    ev, U, st = run_eigh(c, Ha, 0, 1)
+    assert st[0] & 1
+
+
+def test_eigh_nan_input_flagged():
+    gu.need_gpu()
+    H = np.eye(6, dtype=complex)[None]
+    H[0, 2, 3] = np.nan
+    H[0, 3, 2] = np.nan
+    c = gu.ctx()
+    ev, U, st = run_eigh(c, H, 0, 3)
+    assert st[0] & 64
