@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark of the Wilson-loop hot path on one MI355X.
+
+Workload: BHZ model (eq. 7) on a 10 x 10 supercell (N = 400 orbitals) with
+on-site Anderson disorder W in {0, 1, 2, 3}, 16 seeded realizations each
+(64 systems), a 24 x 24 supercell k-grid, half filling (m = 200), and the
+spin-resolved Wilson loop with S_z = diag(1, -1, -1, 1) per site. One step is
+the whole hot path for all 64 systems: Bloch Hamiltonians, batched
+eigensolver, projected spin operator and its eigensolver, sector overlaps,
+polar factors, ordered products, eigenphases and windings. Inputs (packed
+hopping lists, k-points) are resident on the device before timing starts.
+
+Metric: Wilson-loop k-point solves per second (k-points of the grid taken
+through the whole path per second of wall time).
+
+Prints one JSON line. Also reports the dominant kernel's roofline (its
+duration measured with HIP events recorded by the library around each of its
+launches during the timed steps) and the FP64 CPU oracle's rate on a bounded
+sample of the same workload (a baseline, not the target).
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synthetic as syn  # noqa: E402
+
+METRIC = "Wilson-loop k-point solves/s at ≤1e-6 phase err vs FP64; p50/p99 latency"
+L_SC, N_PAR, N_PERP = 10, 24, 24
+W_VALUES = (0.0, 1.0, 2.0, 3.0)
+REALIZATIONS = 16
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+NB = 32  # panel width of the Householder reduction
+
+
+def systems():
+    hls, tags = [], []
+    for w_idx, W in enumerate(W_VALUES):
+        for r in range(REALIZATIONS):
+            hls.append(syn.bhz_disordered(L_SC, W, [3, w_idx, r]))
+            tags.append((w_idx, r))
+    return hls, tags
+
+
+# ---------------------------------------------------------------- CPU oracle leg
+def _oracle_line(args):
+    """Spin-resolved Wilson loop of one transverse line with the FP64 oracle."""
+    w_idx, r, i = args
+    from oracle import berry as orc
+    hl = syn.bhz_disordered(L_SC, W_VALUES[w_idx], [3, w_idx, r])
+    kg = syn.kplane(N_PAR, N_PERP)
+    m = hl.N // 2
+    sd = syn.bhz_spin_diag(hl)
+    ev, U, st = orc.eigh_grid(hl, kg[i], 0, m)
+    vm, vp = [], []
+    for j in range(N_PAR):
+        mu, a, b = orc.spin_sectors(U[j], sd)
+        vm.append(a)
+        vp.append(b)
+    out = []
+    for V in (vm, vp):
+        if min(x.shape[1] for x in V) != max(x.shape[1] for x in V):
+            out.append(None)
+            continue
+        W, _ = orc.wilson_matrix(np.stack(V))
+        out.append(orc.eigphases(W))
+    return (w_idx, r, i, out[0], out[1])
+
+
+def cpu_baseline(sample, workers):
+    ctx = mp.get_context("spawn")
+    old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        with ctx.Pool(workers) as pool:
+            pool.map(_oracle_line, sample[:workers])  # warm the workers (imports)
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_line, sample)
+            dt = time.perf_counter() - t0
+    finally:
+        if old is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = old
+        os.environ.pop("OPENBLAS_NUM_THREADS", None)
+    return res, dt
+
+
+# ---------------------------------------------------------------- algorithmic work
+def hetrd_panel_bytes(N, n_mat):
+    """Algorithmic HBM bytes of all panel launches: one read of the trailing
+    Hermitian matrix (16 B per c128 element) per reflector column."""
+    return n_mat * sum(16.0 * (N - j - 1) ** 2 for j in range(N - 1))
+
+
+def gemm_flops(name, N, m, n_mat):
+    """Algorithmic flops (8 per complex multiply-add) of a GEMM call site."""
+    P = (N + NB - 1) // NB
+    if name == "her2k":   # Hermitian rank-2nb update, one triangle
+        return n_mat * sum(8.0 * (N - p * NB - NB) ** 2 * NB for p in range(P) if N - p * NB - NB > 0)
+    if name == "unmtr":   # X = V^H U, Y = T X (T triangular), U -= V Y
+        tot = 0.0
+        for p in range(P):
+            p0 = p * NB
+            nbp, K = min(NB, N - p0), N - p0 - 1
+            if K > 0:
+                tot += 16.0 * K * nbp * m + 4.0 * nbp * nbp * m
+        return n_mat * tot
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chunk-systems", type=int, default=8)
+    ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample size (transverse lines)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    hls, tags = systems()
+    n_sys = len(hls)
+    N = hls[0].N
+    m = N // 2
+    kg = syn.kplane(N_PAR, N_PERP)
+    n_k = N_PAR * N_PERP
+
+    # ---- CPU oracle on a bounded sample (before the GPU is touched)
+    sample = []
+    rng = np.random.default_rng([9, 9])
+    for w_idx in range(len(W_VALUES)):
+        for r in rng.choice(REALIZATIONS, size=2, replace=False):
+            for i in rng.choice(N_PERP, size=max(1, args.cpu_lines // 8), replace=False):
+                sample.append((w_idx, int(r), int(i)))
+    cpu = None
+    oracle_res = []
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1, len(sample)))
+        oracle_res, cdt = cpu_baseline(sample, workers)
+        cpu = {"value": len(sample) * N_PAR / cdt, "unit": "k-point solves/s", "cores": workers, "kind": "oracle",
+               "sample": f"{len(sample)} transverse lines ({len(sample) * N_PAR} k-points) of the same workload, "
+                         f"NumPy/LAPACK FP64, one worker process per core, OMP_NUM_THREADS=1, wall {cdt:.2f} s"}
+
+    import torch
+    from paper_2312_13051_amd import _lib as L
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    ctx = L.Context(0)
+    plan = ctx.hk_plan(hls)
+    kap = torch.from_numpy(np.ascontiguousarray(kg.reshape(-1, 3))).to(dev)
+    spin = torch.from_numpy(np.stack([syn.bhz_spin_diag(h) for h in hls])).to(dev)
+    cs = args.chunk_systems
+    nmat = cs * n_k
+    H = torch.empty((nmat, N, N), dtype=torch.complex128, device=dev)
+    U = torch.empty((nmat, m, N), dtype=torch.complex128, device=dev)
+    ev = torch.empty((nmat, m + 2), dtype=torch.float64, device=dev)
+    est = torch.empty(nmat, dtype=torch.int32, device=dev)
+    pso = torch.empty((n_sys, N_PERP, N_PAR, m), dtype=torch.float64, device=dev)
+    tdn = torch.empty((n_sys, N_PERP, m), dtype=torch.float64, device=dev)
+    tup = torch.empty((n_sys, N_PERP, m), dtype=torch.float64, device=dev)
+    cdn = torch.empty(n_sys, dtype=torch.int32, device=dev)
+    cup = torch.empty(n_sys, dtype=torch.int32, device=dev)
+    csp = torch.empty(n_sys, dtype=torch.float64, device=dev)
+    sst = torch.empty(n_sys, dtype=torch.int32, device=dev)
+    eig_bad = torch.zeros(n_sys, dtype=torch.int32, device=dev)
+    mdn_all = [0] * n_sys
+    chunk_lat = []
+
+    def step(record=False):
+        for s0 in range(0, n_sys, cs):
+            ns = min(cs, n_sys - s0)
+            t0 = time.perf_counter()
+            ctx.build_hk(plan, s0, ns, kap, H, N * N, N, L.BE_C128)
+            ctx.eigh_batched(H, L.BE_C128, N, N, N * N, ns * n_k, 0, m, L.BE_FP64, ev, U, N, U.stride(0), est)
+            eig_bad[s0:s0 + ns] = est[:ns * n_k].view(ns, n_k).ne(0).any(dim=1).to(torch.int32)
+            md = ctx.spin_resolved_wilson(U, N, m, N, U.stride(0), ns, N_PAR, N_PERP, L.BE_OVL_POLAR, spin[s0:],
+                                          pso[s0:], tdn[s0:], tup[s0:], cdn[s0:], cup[s0:], csp[s0:], sst[s0:])
+            mdn_all[s0:s0 + ns] = md
+            if record:
+                torch.cuda.synchronize()
+                chunk_lat.append(time.perf_counter() - t0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile()
+    ctx.profile_enable(False)
+    step(record=True)  # latency of each chunk (systems finish together per chunk)
+    torch.cuda.synchronize()
+
+    total_k = n_sys * n_k
+    sec = (t1 - t0) / args.steps
+    value = total_k / sec
+
+    # ---- dominant kernel and its roofline
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    name, (ms_tot, launches) = dom
+    steps = args.steps
+    roof = None
+    if name == "hetrd_panel":
+        byts = hetrd_panel_bytes(N, total_k) * steps
+        ach = byts / (ms_tot * 1e-3) / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+    else:
+        fl = gemm_flops(name, N, m, total_k)
+        if fl is not None:
+            ach = fl * steps / (ms_tot * 1e-3) / 1e12
+            roof = {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                    "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+        else:
+            roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+    kernels = {k: {"ms_per_step": round(v[0] / steps, 2), "launches_per_step": v[1] // steps} for k, v in
+               sorted(prof.items(), key=lambda kv: -kv[1][0])}
+
+    # ---- phase error of the sampled lines against the FP64 oracle
+    max_err = None
+    if oracle_res:
+        from tests.phase_metrics import phase_set_error
+        tdn_h, tup_h = tdn.cpu().numpy(), tup.cpu().numpy()
+        errs = []
+        for (w_idx, r, i, a, b) in oracle_res:
+            s = w_idx * REALIZATIONS + r
+            md = mdn_all[s]
+            if a is not None and a.size == md:
+                errs.append(phase_set_error(tdn_h[s, i, :md], a))
+            if b is not None and b.size == m - md:
+                errs.append(phase_set_error(tup_h[s, i, :m - md], b))
+        max_err = float(max(errs)) if errs else None
+
+    st = sst.cpu().numpy() | eig_bad.cpu().numpy()
+    lat = np.array(chunk_lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "k-point solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "BHZ 10x10 supercell (N=400) with Anderson disorder W in {0,1,2,3} x 16 seeded "
+                               "realizations, 24x24 supercell k-grid, half filling, spin-resolved Wilson loop "
+                               "(eig of P S_z P), FP64 path",
+                   "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                       "unit": f"per chunk of {cs} systems ({cs * n_k} k-points)"},
+        "phase_err_vs_fp64_oracle_rad": max_err,
+        "valid_systems": int((st == 0).sum()),
+        "spin_chern_W0": [float(x) for x in csp.cpu().numpy()[:REALIZATIONS]][:4],
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -203,6 +203,17 @@ int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, in
                             double *pso_evals, double *theta_dn, double *theta_up, int32_t *C_dn, int32_t *C_up,
                             double *C_s, int32_t *m_dn_h, uint32_t *status, hipStream_t stream);
 
+/* Launch timing (tracing aid). While enabled, every library launch is
+ * bracketed by a pair of hipEvents recorded on its own stream, keyed by the
+ * kernel or GEMM call-site name ("hk_scatter", "hetrd_panel", "her2k",
+ * "tridiag_eig", "unmtr", "overlap", "polar", "chain", "unitary_eig", ...).
+ * be_profile_enable resets all counters. Queries synchronize on the
+ * recorded events and return the summed duration and the launch count.
+ * be_profile_names writes the comma-separated list of names seen so far. */
+int be_profile_enable(be_ctx *ctx, int on);
+int be_profile_query(be_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+int be_profile_names(be_ctx *ctx, char *buf, size_t len);
+
 /* Utility kernel exposed for tests: batched complex GEMM on MFMA,
  *   C_q = alpha op(A_q) op(B_q) + beta C_q,   op = 'N' (none) or 'C'
  * (conjugate transpose), c128, strided batches (element strides). */

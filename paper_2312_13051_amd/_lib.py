@@ -28,6 +28,7 @@ EXPORTS = [
     "be_hk_plan_create", "be_hk_plan_destroy", "be_hk_plan_N",
     "be_build_hk", "be_eigh_batched", "be_wilson_loop", "be_nested_wilson",
     "be_spin_resolved_wilson", "be_zgemm_strided",
+    "be_profile_enable", "be_profile_query", "be_profile_names",
 ]
 
 
@@ -71,6 +72,9 @@ def load():
                                             vp, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.be_zgemm_strided.argtypes = [vp, C.c_char, C.c_char, i32, i32, i32, f64p, vp, i32, i64, vp, i32, i64,
                                      f64p, vp, i32, i64, i32, vp]
+    lib.be_profile_enable.argtypes = [vp, C.c_int]
+    lib.be_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.be_profile_names.argtypes = [vp, C.c_char_p, C.c_size_t]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
             "be_last_error", "be_workspace_bytes", "be_hk_plan_N") else C.c_int
@@ -180,6 +184,20 @@ class Context:
                                                      _ptr(theta_up), _ptr(C_dn), _ptr(C_up), _ptr(C_s), m_dn,
                                                      _ptr(status), _stream()))
         return [int(x) for x in m_dn]
+
+    def profile_enable(self, on=True):
+        self._check(self.lib.be_profile_enable(self.handle, 1 if on else 0))
+
+    def profile(self):
+        """{name: (total_ms, launches)} of the launches recorded since profile_enable."""
+        buf = C.create_string_buffer(8192)
+        self._check(self.lib.be_profile_names(self.handle, buf, 8192))
+        out = {}
+        for name in filter(None, buf.value.decode().split(",")):
+            ms, n = C.c_double(), C.c_int64()
+            self._check(self.lib.be_profile_query(self.handle, name.encode(), C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def zgemm_strided(self, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cm, ldc, sC, batch):
         a = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -18,8 +19,19 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // so a stage may call another stage without their scratch overlapping.
 enum { WS_EIGH = 0, WS_WILSON = 1, WS_OUTER = 2, WS_MISC = 3, WS_SLOTS = 4 };
 
+// Per-name launch timer: hipEvent pairs recorded around launches while
+// profiling is on; resolved (synchronously) when queried.
+struct ProfEntry {
+  double total_ms = 0.0;
+  int64_t launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
 struct be_ctx {
   int device = 0;
+  bool prof_on = false;
+  std::map<std::string, ProfEntry> prof;
+  std::vector<hipEvent_t> event_pool;
   void *ws[WS_SLOTS] = {nullptr, nullptr, nullptr, nullptr};  // device workspaces (grow on demand)
   size_t ws_bytes[WS_SLOTS] = {0, 0, 0, 0};
   void *pinned = nullptr;  // small pinned host buffer for scalar read-backs
@@ -70,6 +82,23 @@ class Carve {
   std::vector<size_t> offs_;
   size_t total_ = 0;
 };
+
+// ---------------------------------------------------------------- profiling
+// RAII scope recording a start/stop event pair on `stream` under `name`
+// when profiling is enabled on the context.
+class ProfScope {
+ public:
+  ProfScope(be_ctx *ctx, const char *name, hipStream_t stream);
+  ~ProfScope();
+
+ private:
+  be_ctx *ctx_;
+  const char *name_;
+  hipStream_t stream_;
+  hipEvent_t start_ = nullptr;
+};
+
+void prof_resolve_all(be_ctx *ctx);
 
 // ---------------------------------------------------------------- launches
 // Kernel launch error check (after hipLaunchKernelGGL).
@@ -150,6 +179,7 @@ struct ZGemm {
   double2 alpha = {1.0, 0.0};
   double2 beta = {0.0, 0.0};
   int64_t batch = 0;
+  const char *tag = "zgemm";  // profiling label of the call site
 };
 
 // C = alpha op(A) op(B) + beta C, FP64 MFMA. C must not alias A or B.
@@ -171,8 +201,29 @@ struct CGemm {
   float2 alpha = {1.0f, 0.0f};
   float2 beta = {0.0f, 0.0f};
   int64_t batch = 0;
+  const char *tag = "cgemm";
 };
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
+
+// Real FP64 batched GEMM, op in {0: none, 1: transpose}.
+struct DGemm {
+  int M = 0, N = 0, K = 0;
+  int opA = 0, opB = 0;
+  const double *A = nullptr;
+  int lda = 0;
+  ZBatch bA;
+  const double *B = nullptr;
+  int ldb = 0;
+  ZBatch bB;
+  double *C = nullptr;
+  int ldc = 0;
+  ZBatch bC;
+  double alpha = 1.0;
+  double beta = 0.0;
+  int64_t batch = 0;
+  const char *tag = "dgemm";
+};
+int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream);
 
 // FP64 batched eigensolver for bands [band_lo, band_hi) (uses slot WS_EIGH).
 int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,

@@ -34,11 +34,53 @@ int Carve::commit(be_ctx *ctx, hipStream_t stream, int slot) {
   return BE_OK;
 }
 
+static hipEvent_t take_event(be_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(be_ctx *ctx, const char *name, hipStream_t stream) : ctx_(ctx), name_(name), stream_(stream) {
+  if (!ctx_ || !ctx_->prof_on) return;
+  start_ = take_event(ctx_);
+  if (start_) (void)hipEventRecord(start_, stream_);
+}
+
+ProfScope::~ProfScope() {
+  if (!start_) return;
+  hipEvent_t stop = take_event(ctx_);
+  if (!stop) return;
+  (void)hipEventRecord(stop, stream_);
+  ctx_->prof[name_].pending.emplace_back(start_, stop);
+}
+
+static void prof_resolve(be_ctx *ctx) {
+  for (auto &kv : ctx->prof) {
+    for (auto &pr : kv.second.pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        kv.second.total_ms += ms;
+        kv.second.launches += 1;
+      }
+      ctx->event_pool.push_back(pr.first);
+      ctx->event_pool.push_back(pr.second);
+    }
+    kv.second.pending.clear();
+  }
+}
+
 int check_launch(be_ctx *ctx, const char *what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, BE_EHIP, std::string("launch of ") + what + ": " + hipGetErrorString(e));
   return BE_OK;
 }
+
+void prof_resolve_all(be_ctx *ctx) { prof_resolve(ctx); }
 
 }  // namespace be
 
@@ -66,6 +108,8 @@ int be_destroy(be_ctx *ctx) {
   if (!ctx) return BE_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  be::prof_resolve_all(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   for (int k = 0; k < WS_SLOTS; ++k)
     if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -80,6 +124,37 @@ size_t be_workspace_bytes(const be_ctx *ctx) {
   size_t t = 0;
   for (int k = 0; k < WS_SLOTS; ++k) t += ctx->ws_bytes[k];
   return t;
+}
+
+int be_profile_enable(be_ctx *ctx, int on) {
+  if (!ctx) return BE_EINVAL;
+  be::prof_resolve(ctx);
+  ctx->prof.clear();
+  ctx->prof_on = on != 0;
+  return BE_OK;
+}
+
+int be_profile_query(be_ctx *ctx, const char *name, double *total_ms, int64_t *launches) {
+  if (!ctx || !name || !total_ms || !launches) return BE_EINVAL;
+  be::prof_resolve(ctx);
+  auto it = ctx->prof.find(name);
+  *total_ms = it == ctx->prof.end() ? 0.0 : it->second.total_ms;
+  *launches = it == ctx->prof.end() ? 0 : it->second.launches;
+  return BE_OK;
+}
+
+int be_profile_names(be_ctx *ctx, char *buf, size_t len) {
+  if (!ctx || !buf || len == 0) return BE_EINVAL;
+  be::prof_resolve(ctx);
+  std::string s;
+  for (auto &kv : ctx->prof) {
+    if (!s.empty()) s += ",";
+    s += kv.first;
+  }
+  size_t n = std::min(len - 1, s.size());
+  std::copy(s.begin(), s.begin() + n, buf);
+  buf[n] = 0;
+  return BE_OK;
 }
 
 }  // extern "C"

@@ -12,9 +12,11 @@
 //    the same dot products.
 // 2. FP64 tridiagonal eigensolver (tridiag_eig): bisection with Sturm counts,
 //    one lane per eigenvalue, for the selected indices and their neighbours;
-//    inverse iteration with partial pivoting, one lane per eigenvector;
-//    modified Gram-Schmidt (two passes) inside clusters of close eigenvalues,
-//    one wave per cluster.
+//    inverse iteration with partial pivoting, one lane per eigenvector, from
+//    independent pseudo-random starts (inside an exactly degenerate cluster
+//    they converge to independent vectors of the cluster's space). The
+//    vectors are then made orthonormal by FP64 Cholesky-QR, twice, as MFMA
+//    DGEMMs (Gram matrix, L^{-1} Z) around a per-matrix Cholesky kernel.
 // 3. Back-transformation U = Q Z by panels in reverse order with three MFMA
 //    GEMMs each: X = V^H U, Y = T X, U -= V Y.
 // 4. Mixed precision only: FP64 Cholesky-QR re-orthonormalization of U.
@@ -325,7 +327,6 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
   double *se2 = se + N;      // N
   double *slam = se2 + N;    // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
   const int m = hi - lo;
-  int *sclu = reinterpret_cast<int *>(slam + m + 4);  // cluster start flags (m)
   __shared__ double red[2 * (PT / 64)];
   __shared__ int s_bad;
 
@@ -490,42 +491,6 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
     }
   }
   if (lane_bad) st |= BE_ST_NONCONVERGED;
-  // ---- clusters of close eigenvalues: start flags
-  const double ortol = 1e-3 * tnorm;
-  for (int c = tid; c < m; c += PT) sclu[c] = (c == 0) || (lam[c] - lam[c - 1] > ortol);
-  __syncthreads();
-  // ---- MGS (two passes) inside each cluster, one wave per cluster
-  for (int c0 = wave; c0 < m; c0 += nw) {
-    // find clusters whose start index is congruent to this wave's turn: walk starts
-    if (!sclu[c0]) continue;
-    int c1 = c0 + 1;
-    while (c1 < m && !sclu[c1]) ++c1;
-    if (c1 - c0 < 2) continue;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int t = c0; t < c1; ++t) {
-        for (int s = c0; s < t; ++s) {
-          double dt = 0.0;
-          for (int i = lane; i < N; i += 64) dt = fma(X[int64_t(i) * mp + s], X[int64_t(i) * mp + t], dt);
-          dt = wave_sum(dt);
-          for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] -= dt * X[int64_t(i) * mp + s];
-        }
-        double nr = 0.0;
-        for (int i = lane; i < N; i += 64) {
-          double v = X[int64_t(i) * mp + t];
-          nr = fma(v, v, nr);
-        }
-        nr = wave_sum(nr);
-        double inv = 1.0 / sqrt(nr);
-        for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] *= inv;
-      }
-    }
-  }
-  __syncthreads();
-  // ---- Z -> U (complex, column-major)
-  for (int64_t k = tid; k < int64_t(N) * m; k += PT) {
-    int c = int(k / N), r = int(k % N);
-    U[q * sU + r + int64_t(c) * ldu] = make_double2(X[int64_t(r) * mp + c], 0.0);
-  }
   // status: OR of lane flags
   {
     __shared__ unsigned int sst;
@@ -534,6 +499,59 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
     if (st) atomicOr(&sst, st);
     __syncthreads();
     if (tid == 0) status[q] |= sst;
+  }
+}
+
+// Cholesky G = L L^T of each m x m Gram matrix (in place, lower triangle),
+// then Li = L^{-1} (lower triangular, zeros above). One workgroup per matrix.
+// A non-positive pivot (rank-deficient basis) sets NONCONVERGED.
+__global__ __launch_bounds__(PT) void chol_inv(double *G, int m, double *Li, uint32_t *status) {
+  const int64_t q = blockIdx.x;
+  double *Gq = G + q * int64_t(m) * m;
+  double *Lq = Li + q * int64_t(m) * m;
+  const int tid = threadIdx.x;
+  __shared__ double s_piv;
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) {
+      double dk = Gq[k + int64_t(k) * m];
+      if (!(dk > 0.0)) {
+        s_bad = 1;
+        dk = 1.0;
+      }
+      s_piv = sqrt(dk);
+      Gq[k + int64_t(k) * m] = s_piv;
+    }
+    __syncthreads();
+    const double piv = s_piv;
+    for (int i = k + 1 + tid; i < m; i += PT) Gq[i + int64_t(k) * m] /= piv;
+    __syncthreads();
+    const int n2 = m - k - 1;
+    for (int e = tid; e < n2 * n2; e += PT) {
+      const int i = k + 1 + e % n2, j = k + 1 + e / n2;
+      if (i >= j) Gq[i + int64_t(j) * m] -= Gq[i + int64_t(k) * m] * Gq[j + int64_t(k) * m];
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < m; j += PT) {
+    for (int i = 0; i < j; ++i) Lq[i + int64_t(j) * m] = 0.0;
+    Lq[j + int64_t(j) * m] = 1.0 / Gq[j + int64_t(j) * m];
+    for (int i = j + 1; i < m; ++i) {
+      double sacc = 0.0;
+      for (int k = j; k < i; ++k) sacc = fma(Gq[i + int64_t(k) * m], Lq[k + int64_t(j) * m], sacc);
+      Lq[i + int64_t(j) * m] = -sacc / Gq[i + int64_t(i) * m];
+    }
+  }
+  if (tid == 0 && s_bad) status[q] |= BE_ST_NONCONVERGED;
+}
+
+// U[q](r, c) = X[q](c, r) as complex (X: m x N column-major, leading dimension mp)
+__global__ void z_to_u(const double *X, int64_t sX, int mp, int N, int m, double2 *U, int ldu, int64_t sU) {
+  const int64_t q = blockIdx.y;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < int64_t(N) * m; k += int64_t(gridDim.x) * blockDim.x) {
+    int c = int(k / N), r = int(k % N);
+    U[q * sU + r + int64_t(c) * ldu] = make_double2(X[q * sX + int64_t(r) * mp + c], 0.0);
   }
 }
 
@@ -564,6 +582,9 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
   cv.add(&dd, size_t(nb_mat) * N);
   cv.add(&ee, size_t(nb_mat) * N);
   cv.add(&Zs, size_t(nb_mat) * 4 * N * mp);
+  double *Gm = nullptr, *Li = nullptr;
+  cv.add(&Gm, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
+  cv.add(&Li, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
   cv.add(&Xb, size_t(nb_mat) * NB * std::max(m, 1));
   cv.add(&Yb, size_t(nb_mat) * NB * std::max(m, 1));
   BE_RET_IF(cv.commit(ctx, stream, WS_EIGH));
@@ -578,8 +599,11 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
   // ---- Householder reduction
   for (int p = 0; p < P; ++p) {
     const int p0 = p * NB, nbp = std::min(NB, N - p0);
-    hipLaunchKernelGGL(hetrd_panel<double>, dim3(nb_mat), dim3(PT), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
+    {
+      ProfScope prof(ctx, "hetrd_panel", stream);
+      hipLaunchKernelGGL(hetrd_panel<double>, dim3(nb_mat), dim3(PT), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
                        Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
+    }
     BE_RET_IF(check_launch(ctx, "hetrd_panel"));
     const int n2 = N - p0 - NB;
     if (n2 > 0) {
@@ -601,6 +625,7 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
       g.alpha = make_double2(-1.0, 0.0);
       g.beta = make_double2(1.0, 0.0);
       g.batch = nb_mat;
+      g.tag = "her2k";
       BE_RET_IF(zgemm(ctx, g, stream));
     }
   }
@@ -609,10 +634,62 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
   if (tsm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tridiag_eig),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(tsm)));
-  hipLaunchKernelGGL(tridiag_eig, dim3(nb_mat), dim3(PT), tsm, stream, dd, ee, int64_t(N), N, lo, hi, evals, Zs,
+  {
+    ProfScope prof(ctx, "tridiag_eig", stream);
+    hipLaunchKernelGGL(tridiag_eig, dim3(nb_mat), dim3(PT), tsm, stream, dd, ee, int64_t(N), N, lo, hi, evals, Zs,
                      int64_t(4) * N * mp, mp, U, ldu, us, status);
+  }
   BE_RET_IF(check_launch(ctx, "tridiag_eig"));
   if (m == 0) return BE_OK;
+  // ---- Cholesky-QR (twice) of Z, held as X = Z^T (m x N, leading dim mp)
+  {
+    const int64_t sZ = int64_t(4) * N * mp;
+    double *Xa = Zs + int64_t(3) * N * mp, *Xt = Zs;
+    for (int pass = 0; pass < 2; ++pass) {
+      double *src = pass == 0 ? Xa : Xt, *dst = pass == 0 ? Xt : Xa;
+      DGemm g;  // G = X X^T
+      g.M = m;
+      g.N = m;
+      g.K = N;
+      g.opA = 0;
+      g.opB = 1;
+      g.A = src;
+      g.lda = mp;
+      g.bA = ZBatch::strided(sZ);
+      g.B = src;
+      g.ldb = mp;
+      g.bB = ZBatch::strided(sZ);
+      g.C = Gm;
+      g.ldc = m;
+      g.bC = ZBatch::strided(int64_t(m) * m);
+      g.batch = nb_mat;
+      g.tag = "reorth";
+      BE_RET_IF(dgemm(ctx, g, stream));
+      {
+        ProfScope prof(ctx, "chol_inv", stream);
+        hipLaunchKernelGGL(chol_inv, dim3(nb_mat), dim3(PT), 0, stream, Gm, m, Li, status);
+      }
+      BE_RET_IF(check_launch(ctx, "chol_inv"));
+      DGemm h;  // X <- L^{-1} X
+      h.M = m;
+      h.N = N;
+      h.K = m;
+      h.A = Li;
+      h.lda = m;
+      h.bA = ZBatch::strided(int64_t(m) * m);
+      h.B = src;
+      h.ldb = mp;
+      h.bB = ZBatch::strided(sZ);
+      h.C = dst;
+      h.ldc = mp;
+      h.bC = ZBatch::strided(sZ);
+      h.batch = nb_mat;
+      h.tag = "reorth";
+      BE_RET_IF(dgemm(ctx, h, stream));
+    }
+    hipLaunchKernelGGL(z_to_u, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream, Xa, sZ, mp, N, m, U, ldu, us);
+    BE_RET_IF(check_launch(ctx, "z_to_u"));
+  }
   // ---- back-transformation, panels in reverse order
   for (int p = P - 1; p >= 0; --p) {
     const int p0 = p * NB, nbp = std::min(NB, N - p0);
@@ -634,6 +711,7 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     g1.ldc = NB;
     g1.bC = ZBatch::strided(int64_t(NB) * m);
     g1.batch = nb_mat;
+    g1.tag = "unmtr";
     BE_RET_IF(zgemm(ctx, g1, stream));
     ZGemm g2;  // Y = T X
     g2.M = nbp;
@@ -649,6 +727,7 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     g2.ldc = NB;
     g2.bC = ZBatch::strided(int64_t(NB) * m);
     g2.batch = nb_mat;
+    g2.tag = "unmtr";
     BE_RET_IF(zgemm(ctx, g2, stream));
     ZGemm g3;  // U -= V Y
     g3.M = K;
@@ -666,6 +745,7 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     g3.alpha = make_double2(-1.0, 0.0);
     g3.beta = make_double2(1.0, 0.0);
     g3.batch = nb_mat;
+    g3.tag = "unmtr";
     BE_RET_IF(zgemm(ctx, g3, stream));
   }
   return BE_OK;
@@ -679,7 +759,8 @@ int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
   const size_t per = sizeof(double2) * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1)) +
-                     sizeof(double) * (2 * size_t(N) + 4 * size_t(N) * mp) + 7 * 256;
+                     sizeof(double) * (2 * size_t(N) + 4 * size_t(N) * mp + 2 * size_t(std::max(m, 1)) * std::max(m, 1)) +
+                     9 * 256;
   const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);

@@ -224,11 +224,158 @@ int dispatch(be_ctx *ctx, GP<T> p, int opA, int opB, hipStream_t s) {
   return launch_cfg<T, 16, 16, 1, 1>(ctx, p, opA, opB, s);
 }
 
+// ---------------------------------------------------------------- real FP64 GEMM
+// C = alpha op(A) op(B) + beta C with op in {none, transpose}; one MFMA per
+// 16x16 tile and k-step, same staging and epilogue as the complex kernel.
+struct DP {
+  int M, N, K;
+  const double *A;
+  int lda;
+  be::ZBatch bA;
+  const double *B;
+  int ldb;
+  be::ZBatch bB;
+  double *C;
+  int ldc;
+  be::ZBatch bC;
+  double alpha, beta;
+  int64_t batch;
+  int tiles_m, tiles_n;
+};
+
+template <int BM, int BN, int WM, int WN, int OPA, int OPB>
+__global__ __launch_bounds__(64 * WM * WN) void dgemm_kernel(DP p) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  constexpr int DKB = 32;
+  constexpr int PA = BM + 2;
+  constexpr int PB = BN + 2;
+  __shared__ double sA[DKB * PA], sB[DKB * PB];
+  const int64_t tiles = int64_t(p.tiles_m) * p.tiles_n;
+  const int64_t total = tiles * p.batch;
+  const int64_t w = be::xcd_work_id(total);
+  if (w >= total) return;
+  const int64_t q = w / tiles;
+  const int t2 = static_cast<int>(w - q * tiles);
+  const int tm = t2 % p.tiles_m, tn = t2 / p.tiles_m;
+  const int i0 = tm * BM, j0 = tn * BN;
+  const double *A = p.A + be::zbatch_off(p.bA, q);
+  const double *B = p.B + be::zbatch_off(p.bB, q);
+  double *C = p.C + be::zbatch_off(p.bC, q);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  for (int k0 = 0; k0 < p.K; k0 += DKB) {
+    for (int e = tid; e < BM * DKB; e += NT) {
+      int i, k;
+      if (OPA == 0) {
+        i = e % BM;
+        k = e / BM;
+      } else {
+        k = e % DKB;
+        i = e / DKB;
+      }
+      int gi = i0 + i, gk = k0 + k;
+      double v = 0.0;
+      if (gi < p.M && gk < p.K) v = OPA == 0 ? A[gi + int64_t(gk) * p.lda] : A[gk + int64_t(gi) * p.lda];
+      sA[k * PA + i] = v;
+    }
+    for (int e = tid; e < BN * DKB; e += NT) {
+      int j, k;
+      if (OPB == 0) {
+        k = e % DKB;
+        j = e / DKB;
+      } else {
+        j = e % BN;
+        k = e / BN;
+      }
+      int gj = j0 + j, gk = k0 + k;
+      double v = 0.0;
+      if (gj < p.N && gk < p.K) v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
+      sB[k * PB + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < DKB; kk += 4) {
+      double av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = sA[(kk + lk) * PA + wm * (BM / WM) + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = sB[(kk + lk) * PB + wn * (BN / WN) + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = MF<double>::mfma(bv[b], av[a], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      int gi = i0 + wm * (BM / WM) + a * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gj = j0 + wn * (BN / WN) + b * 16 + MF<double>::row(lk, r);
+        if (gi < p.M && gj < p.N) {
+          int64_t idx = gi + int64_t(gj) * p.ldc;
+          double out = p.alpha * acc[a][b][r];
+          if (p.beta != 0.0) out += p.beta * C[idx];
+          C[idx] = out;
+        }
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN>
+int dlaunch(be_ctx *ctx, DP p, int opA, int opB, hipStream_t s) {
+  p.tiles_m = (p.M + BM - 1) / BM;
+  p.tiles_n = (p.N + BN - 1) / BN;
+  int64_t total = int64_t(p.tiles_m) * p.tiles_n * p.batch;
+  dim3 grid(be::xcd_grid(total)), block(64 * WM * WN);
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((dgemm_kernel<BM, BN, WM, WN, 0, 0>), grid, block, 0, s, p);
+  if (opA == 0 && opB == 1) hipLaunchKernelGGL((dgemm_kernel<BM, BN, WM, WN, 0, 1>), grid, block, 0, s, p);
+  if (opA == 1 && opB == 0) hipLaunchKernelGGL((dgemm_kernel<BM, BN, WM, WN, 1, 0>), grid, block, 0, s, p);
+  if (opA == 1 && opB == 1) hipLaunchKernelGGL((dgemm_kernel<BM, BN, WM, WN, 1, 1>), grid, block, 0, s, p);
+  return be::check_launch(ctx, "dgemm");
+}
+
 }  // namespace
 
 namespace be {
 
+int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream) {
+  ProfScope prof(ctx, g.tag, stream);
+  DP p;
+  p.M = g.M;
+  p.N = g.N;
+  p.K = g.K;
+  p.A = g.A;
+  p.lda = g.lda;
+  p.bA = g.bA;
+  p.B = g.B;
+  p.ldb = g.ldb;
+  p.bB = g.bB;
+  p.C = g.C;
+  p.ldc = g.ldc;
+  p.bC = g.bC;
+  p.alpha = g.alpha;
+  p.beta = g.beta;
+  p.batch = g.batch;
+  if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
+  if (p.M >= 48 && p.N >= 48) return dlaunch<64, 64, 2, 2>(ctx, p, g.opA, g.opB, stream);
+  if (p.M >= 24 && p.N >= 24) return dlaunch<32, 32, 2, 2>(ctx, p, g.opA, g.opB, stream);
+  return dlaunch<16, 16, 1, 1>(ctx, p, g.opA, g.opB, stream);
+}
+
 int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
+  ProfScope prof(ctx, g.tag, stream);
   GP<double> p;
   p.M = g.M;
   p.N = g.N;
@@ -249,6 +396,7 @@ int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
 }
 
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
+  ProfScope prof(ctx, g.tag, stream);
   GP<float> p;
   p.M = g.M;
   p.N = g.N;

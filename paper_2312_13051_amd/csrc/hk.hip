@@ -286,6 +286,7 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *P, int32_t sys_first, int32_t n_s
   dim3 zb(256), zg(static_cast<uint32_t>(std::min<int64_t>((per + 255) / 256, 4096)),
                    static_cast<uint32_t>(std::min<int64_t>(n_mat, 65535)));
   dim3 sb(256), sg(static_cast<uint32_t>(std::max(1, (maxp + 255) / 256)), static_cast<uint32_t>(std::min<int64_t>(n_mat, 65535)));
+  ProfScope prof(ctx, "hk_build", stream);
   if (dtype == BE_C128) {
     hipLaunchKernelGGL(hk_zero_c128, zg, zb, 0, stream, static_cast<double2 *>(H), mat_stride, ld, N, n_mat);
     BE_RET_IF(check_launch(ctx, "hk_zero"));

@@ -407,6 +407,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
     g.ldc = m;
     g.bC = ZBatch::strided(mm);
     g.batch = nm;
+    g.tag = "overlap";
     BE_RET_IF(zgemm(ctx, g, stream));
   }
   // ---- polar factors (Newton-Schulz)
@@ -432,6 +433,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       g.ldc = m;
       g.bC = ZBatch::strided(mm);
       g.batch = nm;
+      g.tag = "polar";
       BE_RET_IF(zgemm(ctx, g, stream));
       hipLaunchKernelGGL(k_ns_prep, dim3(static_cast<uint32_t>(nm)), dim3(256), 0, stream, B1, m, nm, err, gmax);
       BE_RET_IF(check_launch(ctx, "ns_prep"));
@@ -452,6 +454,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       h.ldc = m;
       h.bC = ZBatch::strided(mm);
       h.batch = nm;
+      h.tag = "polar";
       if (e < 1e-30) break;  // already unitary to working precision
       BE_RET_IF(zgemm(ctx, h, stream));
       std::swap(X, Xn);
@@ -499,6 +502,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
     g.ldc = m;
     g.bC = ZBatch::cyclic(mm, half, 0, int64_t(n2) * mm);
     g.batch = n_lines * half;
+    g.tag = "chain";
     BE_RET_IF(zgemm(ctx, g, stream));
     if (n & 1) {
       hipLaunchKernelGGL(k_carry_last, dim3(16, static_cast<uint32_t>(std::min<int64_t>(n_lines, 65535))), dim3(256), 0,
@@ -515,6 +519,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
   if (esm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
+  ProfScope prof(ctx, "unitary_eig", stream);
   hipLaunchKernelGGL(k_unitary_eig, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs,
                      Zout, theta_sorted, ldt, theta_raw, line_status, 1);
   return check_launch(ctx, "unitary_eig");
@@ -734,6 +739,7 @@ extern "C" int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m
       t.ldc = m;
       t.bC = ZBatch::strided(int64_t(n_par) * nus);
       t.batch = nl;
+      t.tag = "transport";
       BE_RET_IF(zgemm(ctx, t, stream));
     }
     // w[s][j][i] = U[s][i][j] nu[(s,i)][j]   (N x sc, ld N)
@@ -758,6 +764,7 @@ extern "C" int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m
     bc.s2 = int64_t(n_par) * n_perp * ws;
     t.bC = bc;
     t.batch = nl * n_par;
+    t.tag = "wannier_states";
     BE_RET_IF(zgemm(ctx, t, stream));
     s0 = s1;
   }
@@ -899,6 +906,7 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
     g.ldc = m;
     g.bC = ZBatch::strided(mm);
     g.batch = n_k;
+    g.tag = "pso";
     BE_RET_IF(zgemm(ctx, g, stream));
   }
   // ---- eigh of the m x m projected spin operator (all bands)
@@ -943,6 +951,7 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
       g.ldc = N;
       g.bC = ZBatch::strided(int64_t(N) * ms);
       g.batch = nk;
+      g.tag = "spin_sector";
       BE_RET_IF(zgemm(ctx, g, stream));
       Grid gv{V, N, int64_t(N) * ms};
       double *th = (sector == 0 ? theta_dn : theta_up) + l0 * m;
