@@ -38,6 +38,7 @@ W_VALUES = (0.0, 1.0, 2.0, 3.0)
 REALIZATIONS = 16
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 NB = 32  # panel width of the Householder reduction
 
 
@@ -96,10 +97,10 @@ def cpu_baseline(sample, workers):
 
 
 # ---------------------------------------------------------------- algorithmic work
-def hetrd_panel_bytes(N, n_mat):
+def hetrd_panel_bytes(N, n_mat, elem_bytes=16):
     """Algorithmic HBM bytes of all panel launches: one read of the trailing
-    Hermitian matrix (16 B per c128 element) per reflector column."""
-    return n_mat * sum(16.0 * (N - j - 1) ** 2 for j in range(N - 1))
+    Hermitian matrix (16 B per c128 element, 8 B per c64) per reflector column."""
+    return n_mat * sum(elem_bytes * (N - j - 1) ** 2 for j in range(N - 1))
 
 
 def gemm_flops(name, N, m, n_mat):
@@ -126,12 +127,19 @@ def main():
     ap.add_argument("--chunk-systems", type=int, default=8)
     ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample size (transverse lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere)")
+    ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one plain device copy of this size (calibrates rocprof byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     hls, tags = systems()
+    if args.systems:
+        hls, tags = hls[:args.systems], tags[:args.systems]
     n_sys = len(hls)
     N = hls[0].N
     m = N // 2
@@ -160,13 +168,23 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda", 0)
+    if args.copy_calibration_mb:
+        nb = args.copy_calibration_mb << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = L.Context(0)
     plan = ctx.hk_plan(hls)
     kap = torch.from_numpy(np.ascontiguousarray(kg.reshape(-1, 3))).to(dev)
     spin = torch.from_numpy(np.stack([syn.bhz_spin_diag(h) for h in hls])).to(dev)
     cs = args.chunk_systems
     nmat = cs * n_k
-    H = torch.empty((nmat, N, N), dtype=torch.complex128, device=dev)
+    mixed = args.precision == "mixed"
+    hdt, hcode = (torch.complex64, L.BE_C64) if mixed else (torch.complex128, L.BE_C128)
+    prec = L.BE_MIXED_FP32 if mixed else L.BE_FP64
+    H = torch.empty((nmat, N, N), dtype=hdt, device=dev)
     U = torch.empty((nmat, m, N), dtype=torch.complex128, device=dev)
     ev = torch.empty((nmat, m + 2), dtype=torch.float64, device=dev)
     est = torch.empty(nmat, dtype=torch.int32, device=dev)
@@ -185,8 +203,8 @@ def main():
         for s0 in range(0, n_sys, cs):
             ns = min(cs, n_sys - s0)
             t0 = time.perf_counter()
-            ctx.build_hk(plan, s0, ns, kap, H, N * N, N, L.BE_C128)
-            ctx.eigh_batched(H, L.BE_C128, N, N, N * N, ns * n_k, 0, m, L.BE_FP64, ev, U, N, U.stride(0), est)
+            ctx.build_hk(plan, s0, ns, kap, H, N * N, N, hcode)
+            ctx.eigh_batched(H, hcode, N, N, N * N, ns * n_k, 0, m, prec, ev, U, N, U.stride(0), est)
             eig_bad[s0:s0 + ns] = est[:ns * n_k].view(ns, n_k).ne(0).any(dim=1).to(torch.int32)
             md = ctx.spin_resolved_wilson(U, N, m, N, U.stride(0), ns, N_PAR, N_PERP, L.BE_OVL_POLAR, spin[s0:],
                                           pso[s0:], tdn[s0:], tup[s0:], cdn[s0:], cup[s0:], csp[s0:], sst[s0:])
@@ -195,15 +213,22 @@ def main():
                 torch.cuda.synchronize()
                 chunk_lat.append(time.perf_counter() - t0)
 
-    for _ in range(args.warmup):
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        note(f"warmup step {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step()
+        note(f"timed step {k + 1}/{args.steps} issued")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    note(f"timed region {t1 - t0:.2f} s")
     prof = ctx.profile()
     ctx.profile_enable(False)
     step(record=True)  # latency of each chunk (systems finish together per chunk)
@@ -219,7 +244,7 @@ def main():
     steps = args.steps
     roof = None
     if name == "hetrd_panel":
-        byts = hetrd_panel_bytes(N, total_k) * steps
+        byts = hetrd_panel_bytes(N, total_k, 8 if mixed else 16) * steps
         ach = byts / (ms_tot * 1e-3) / 1e9
         roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
@@ -228,8 +253,9 @@ def main():
         fl = gemm_flops(name, N, m, total_k)
         if fl is not None:
             ach = fl * steps / (ms_tot * 1e-3) / 1e12
-            roof = {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            pk = FP32_PEAK_TFLOPS if (mixed and name in ("her2k", "unmtr")) else FP64_PEAK_TFLOPS
+            roof = {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": pk,
+                    "unit": "TFLOP/s", "frac": round(ach / pk, 4), "traffic": None,
                     "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
         else:
             roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
@@ -265,17 +291,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "BHZ 10x10 supercell (N=400) with Anderson disorder W in {0,1,2,3} x 16 seeded "
                                "realizations, 24x24 supercell k-grid, half filling, spin-resolved Wilson loop "
-                               "(eig of P S_z P), FP64 path",
+                               "(eig of P S_z P), " + ("mixed path: FP32 Householder reduction and "
+                               "back-transformation on MFMA, FP64 elsewhere" if mixed else "FP64 path"),
                    "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs},
         "roofline": roof,
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
                        "unit": f"per chunk of {cs} systems ({cs * n_k} k-points)"},
         "phase_err_vs_fp64_oracle_rad": max_err,
+        "phase_gate_1e-6_ok": (max_err is not None and max_err <= 1e-6),
         "valid_systems": int((st == 0).sum()),
         "spin_chern_W0": [float(x) for x in csp.cpu().numpy()[:REALIZATIONS]][:4],
         "kernels": kernels,

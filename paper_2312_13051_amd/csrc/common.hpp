@@ -180,6 +180,7 @@ struct ZGemm {
   double2 beta = {0.0, 0.0};
   int64_t batch = 0;
   const char *tag = "zgemm";  // profiling label of the call site
+  bool lower = false;         // only tiles on or below the diagonal of C are needed
 };
 
 // C = alpha op(A) op(B) + beta C, FP64 MFMA. C must not alias A or B.
@@ -202,6 +203,7 @@ struct CGemm {
   float2 beta = {0.0f, 0.0f};
   int64_t batch = 0;
   const char *tag = "cgemm";
+  bool lower = false;
 };
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
 

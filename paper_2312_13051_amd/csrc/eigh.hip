@@ -43,7 +43,7 @@ struct CT<float> {
 };
 
 template <typename C>
-__device__ __forceinline__ C mk(double x, double y) {
+__host__ __device__ __forceinline__ C mk(double x, double y) {
   C r;
   r.x = x;
   r.y = y;
@@ -190,36 +190,61 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
         v = mk<C>(a.x * scal.x - a.y * scal.y, a.x * scal.y + a.y * scal.x);
       }
       sv[r] = v;
+      sy[r] = mk<C>(0, 0);
       Aq[r + int64_t(j) * lda] = v;
       V[r + int64_t(jj) * N] = v;
       V2[r + int64_t(jj) * N] = v;
     }
     __syncthreads();
-    // ---- (3) y = A(j+1:N, j+1:N) v : one wave per 64-row block
+    // ---- (3) y = A(j+1:N, j+1:N) v from the lower triangle only.
+    // 32x32 tiles (I >= J) are dealt to waves; in a wave the low 32 lanes
+    // take the tile's rows (y_I += A_IJ v_J, one column of 32 consecutive
+    // rows per load) and the high 32 lanes its columns (y_J += A_IJ^H v_I);
+    // diagonal tiles use their lower part only. Partial sums are added into
+    // LDS atomically (sy was zeroed with v).
     const int r0 = j + 1;
     const int nrow = N - r0;
-    const int nrb = (nrow + 63) / 64;
-    for (int rb = wave; rb < nrb; rb += nw) {
-      const int r = r0 + rb * 64 + lane;
+    const int nb32 = (nrow + 31) / 32;
+    const int ntile = nb32 * (nb32 + 1) / 2;
+    const int half = lane >> 5, l32 = lane & 31;
+    for (int t = wave; t < ntile; t += nw) {
+      // tile t -> (I, J), J-major over the lower triangle
+      int J = 0, rem = t;
+      while (rem >= nb32 - J) {
+        rem -= nb32 - J;
+        ++J;
+      }
+      const int I = J + rem;
       T yr = 0, yi = 0;
-      if (r < N) {
-        const C *col = Aq + r;
-        int c = r0;
-        for (; c + 4 <= N; c += 4) {
-          C a0 = col[int64_t(c) * lda], a1 = col[int64_t(c + 1) * lda];
-          C a2 = col[int64_t(c + 2) * lda], a3 = col[int64_t(c + 3) * lda];
-          C v0 = sv[c], v1 = sv[c + 1], v2 = sv[c + 2], v3 = sv[c + 3];
-          yr += a0.x * v0.x - a0.y * v0.y + a1.x * v1.x - a1.y * v1.y;
-          yi += a0.x * v0.y + a0.y * v0.x + a1.x * v1.y + a1.y * v1.x;
-          yr += a2.x * v2.x - a2.y * v2.y + a3.x * v3.x - a3.y * v3.y;
-          yi += a2.x * v2.y + a2.y * v2.x + a3.x * v3.y + a3.y * v3.x;
+      if (half == 0) {
+        const int r = r0 + 32 * I + l32;
+        if (r < N) {
+          const int cmax = min(32, N - (r0 + 32 * J));
+          const int clim = (I == J) ? min(cmax, l32 + 1) : cmax;
+          const C *row = Aq + r + int64_t(r0 + 32 * J) * lda;
+          for (int c = 0; c < clim; ++c) {
+            C a = row[int64_t(c) * lda], v = sv[r0 + 32 * J + c];
+            yr += a.x * v.x - a.y * v.y;
+            yi += a.x * v.y + a.y * v.x;
+          }
+          atomicAdd(&sy[r].x, yr);
+          atomicAdd(&sy[r].y, yi);
         }
-        for (; c < N; ++c) {
-          C a = col[int64_t(c) * lda], v = sv[c];
-          yr += a.x * v.x - a.y * v.y;
-          yi += a.x * v.y + a.y * v.x;
+      } else {
+        const int c = r0 + 32 * J + l32;
+        if (c < N) {
+          const int rmax = min(32, N - (r0 + 32 * I));
+          const int rlo = (I == J) ? l32 + 1 : 0;
+          const C *col = Aq + (r0 + 32 * I) + int64_t(c) * lda;
+          for (int rr = rlo; rr < rmax; ++rr) {
+            C a = col[rr], v = sv[r0 + 32 * I + rr];
+            // conj(a) * v
+            yr += a.x * v.x + a.y * v.y;
+            yi += a.x * v.y - a.y * v.x;
+          }
+          atomicAdd(&sy[c].x, yr);
+          atomicAdd(&sy[c].y, yi);
         }
-        sy[r] = mk<C>(yr, yi);
       }
     }
     // ---- (4) t1 = W^H v, t2 = V^H v over rows j+1..N-1 (one wave per column c)
@@ -547,11 +572,22 @@ __global__ __launch_bounds__(PT) void chol_inv(double *G, int m, double *Li, uin
 }
 
 // U[q](r, c) = X[q](c, r) as complex (X: m x N column-major, leading dimension mp)
-__global__ void z_to_u(const double *X, int64_t sX, int mp, int N, int m, double2 *U, int ldu, int64_t sU) {
+template <typename C>
+__global__ void z_to_u(const double *X, int64_t sX, int mp, int N, int m, C *U, int ldu, int64_t sU) {
   const int64_t q = blockIdx.y;
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < int64_t(N) * m; k += int64_t(gridDim.x) * blockDim.x) {
     int c = int(k / N), r = int(k % N);
-    U[q * sU + r + int64_t(c) * ldu] = make_double2(X[q * sX + int64_t(r) * mp + c], 0.0);
+    U[q * sU + r + int64_t(c) * ldu] = mk<C>(X[q * sX + int64_t(r) * mp + c], 0.0);
+  }
+}
+
+// c64 (N x m, leading dim N) -> c128 output
+__global__ void widen_u(const float2 *Uw, int64_t sW, int N, int m, double2 *U, int ldu, int64_t sU) {
+  const int64_t q = blockIdx.y;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < int64_t(N) * m; k += int64_t(gridDim.x) * blockDim.x) {
+    int c = int(k / N), r = int(k % N);
+    float2 v = Uw[q * sW + k];
+    U[q * sU + r + int64_t(c) * ldu] = make_double2(double(v.x), double(v.y));
   }
 }
 
@@ -568,13 +604,33 @@ size_t panel_smem(int N, size_t csize) {
 
 namespace be {
 
-// FP64 path for one sub-batch of nb_mat matrices.
-static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, int64_t nb_mat, int lo, int hi,
-                           double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream) {
+template <typename T>
+struct GemmOf;
+template <>
+struct GemmOf<double> {
+  typedef ZGemm type;
+  static int run(be_ctx *ctx, const ZGemm &g, hipStream_t s) { return zgemm(ctx, g, s); }
+};
+template <>
+struct GemmOf<float> {
+  typedef CGemm type;
+  static int run(be_ctx *ctx, const CGemm &g, hipStream_t s) { return cgemm(ctx, g, s); }
+};
+
+// One sub-batch of nb_mat matrices. T is the working precision of the
+// Householder reduction and back-transformation (double: FP64 path, float:
+// mixed path); the tridiagonal solve and the re-orthonormalization are FP64.
+// Hin: nb_mat matrices of CT<T>::c; U: c128 output.
+template <typename T>
+static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ms, int64_t nb_mat, int lo, int hi,
+                      double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream) {
+  typedef typename CT<T>::c C;
+  typedef typename GemmOf<T>::type G;
   const int m = hi - lo;
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
-  double2 *VW = nullptr, *Tm = nullptr, *Xb = nullptr, *Yb = nullptr;
+  const bool mixed = sizeof(T) == sizeof(float);
+  C *VW = nullptr, *Tm = nullptr, *Xb = nullptr, *Yb = nullptr, *Uw = nullptr;
   double *dd = nullptr, *ee = nullptr, *Zs = nullptr;
   Carve cv;
   cv.add(&VW, size_t(nb_mat) * N * 3 * NB);
@@ -587,27 +643,28 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
   cv.add(&Li, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
   cv.add(&Xb, size_t(nb_mat) * NB * std::max(m, 1));
   cv.add(&Yb, size_t(nb_mat) * NB * std::max(m, 1));
+  if (mixed) cv.add(&Uw, size_t(nb_mat) * N * std::max(m, 1));
   BE_RET_IF(cv.commit(ctx, stream, WS_EIGH));
   hipLaunchKernelGGL(zero_u32, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, status, nb_mat);
   BE_RET_IF(check_launch(ctx, "zero_u32"));
   const int64_t sVW = int64_t(N) * 3 * NB;
   const int64_t sT = int64_t(P) * NB * NB;
-  const size_t psm = panel_smem(N, sizeof(double2));
+  const size_t psm = panel_smem(N, sizeof(C));
   if (psm > 65536)
-    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&hetrd_panel<double>),
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&hetrd_panel<T>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)));
   // ---- Householder reduction
   for (int p = 0; p < P; ++p) {
     const int p0 = p * NB, nbp = std::min(NB, N - p0);
     {
       ProfScope prof(ctx, "hetrd_panel", stream);
-      hipLaunchKernelGGL(hetrd_panel<double>, dim3(nb_mat), dim3(PT), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
-                       Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
+      hipLaunchKernelGGL(hetrd_panel<T>, dim3(nb_mat), dim3(PT), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
+                         Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
     }
     BE_RET_IF(check_launch(ctx, "hetrd_panel"));
     const int n2 = N - p0 - NB;
     if (n2 > 0) {
-      ZGemm g;
+      G g;
       g.M = n2;
       g.N = n2;
       g.K = 2 * NB;
@@ -622,25 +679,30 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
       g.C = H + (p0 + NB) + int64_t(p0 + NB) * ld;
       g.ldc = ld;
       g.bC = ZBatch::strided(ms);
-      g.alpha = make_double2(-1.0, 0.0);
-      g.beta = make_double2(1.0, 0.0);
+      g.alpha = mk<C>(-1.0, 0.0);
+      g.beta = mk<C>(1.0, 0.0);
       g.batch = nb_mat;
       g.tag = "her2k";
-      BE_RET_IF(zgemm(ctx, g, stream));
+      g.lower = true;  // the reduction reads only the lower triangle
+      BE_RET_IF(GemmOf<T>::run(ctx, g, stream));
     }
   }
   // ---- tridiagonal eigenpairs
-  const size_t tsm = (3 * size_t(N) + m + 4) * sizeof(double) + size_t(std::max(m, 1)) * sizeof(int) + 64;
+  const size_t tsm = (3 * size_t(N) + m + 4) * sizeof(double) + 64;
   if (tsm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tridiag_eig),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(tsm)));
   {
     ProfScope prof(ctx, "tridiag_eig", stream);
     hipLaunchKernelGGL(tridiag_eig, dim3(nb_mat), dim3(PT), tsm, stream, dd, ee, int64_t(N), N, lo, hi, evals, Zs,
-                     int64_t(4) * N * mp, mp, U, ldu, us, status);
+                       int64_t(4) * N * mp, mp, U, ldu, us, status);
   }
   BE_RET_IF(check_launch(ctx, "tridiag_eig"));
   if (m == 0) return BE_OK;
+  // back-transformation target: the output itself (FP64) or an FP32 copy (mixed)
+  C *Ut = mixed ? Uw : reinterpret_cast<C *>(U);
+  const int ldt = mixed ? N : ldu;
+  const int64_t ust = mixed ? int64_t(N) * m : us;
   // ---- Cholesky-QR (twice) of Z, held as X = Z^T (m x N, leading dim mp)
   {
     const int64_t sZ = int64_t(4) * N * mp;
@@ -687,7 +749,8 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
       h.tag = "reorth";
       BE_RET_IF(dgemm(ctx, h, stream));
     }
-    hipLaunchKernelGGL(z_to_u, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream, Xa, sZ, mp, N, m, U, ldu, us);
+    hipLaunchKernelGGL(z_to_u<C>, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream, Xa, sZ, mp, N, m, Ut, ldt,
+                       ust);
     BE_RET_IF(check_launch(ctx, "z_to_u"));
   }
   // ---- back-transformation, panels in reverse order
@@ -695,7 +758,7 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     const int p0 = p * NB, nbp = std::min(NB, N - p0);
     const int K = N - p0 - 1;
     if (K <= 0) continue;
-    ZGemm g1;  // X = V^H U(p0+1:, :)
+    G g1;  // X = V^H U(p0+1:, :)
     g1.M = nbp;
     g1.N = m;
     g1.K = K;
@@ -704,16 +767,16 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     g1.A = H + (p0 + 1) + int64_t(p0) * ld;
     g1.lda = ld;
     g1.bA = ZBatch::strided(ms);
-    g1.B = U + (p0 + 1);
-    g1.ldb = ldu;
-    g1.bB = ZBatch::strided(us);
+    g1.B = Ut + (p0 + 1);
+    g1.ldb = ldt;
+    g1.bB = ZBatch::strided(ust);
     g1.C = Xb;
     g1.ldc = NB;
     g1.bC = ZBatch::strided(int64_t(NB) * m);
     g1.batch = nb_mat;
     g1.tag = "unmtr";
-    BE_RET_IF(zgemm(ctx, g1, stream));
-    ZGemm g2;  // Y = T X
+    BE_RET_IF(GemmOf<T>::run(ctx, g1, stream));
+    G g2;  // Y = T X
     g2.M = nbp;
     g2.N = m;
     g2.K = nbp;
@@ -728,8 +791,8 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     g2.bC = ZBatch::strided(int64_t(NB) * m);
     g2.batch = nb_mat;
     g2.tag = "unmtr";
-    BE_RET_IF(zgemm(ctx, g2, stream));
-    ZGemm g3;  // U -= V Y
+    BE_RET_IF(GemmOf<T>::run(ctx, g2, stream));
+    G g3;  // U -= V Y
     g3.M = K;
     g3.N = m;
     g3.K = nbp;
@@ -739,36 +802,49 @@ static int eigh_fp64_chunk(be_ctx *ctx, double2 *H, int N, int ld, int64_t ms, i
     g3.B = Yb;
     g3.ldb = NB;
     g3.bB = ZBatch::strided(int64_t(NB) * m);
-    g3.C = U + (p0 + 1);
-    g3.ldc = ldu;
-    g3.bC = ZBatch::strided(us);
-    g3.alpha = make_double2(-1.0, 0.0);
-    g3.beta = make_double2(1.0, 0.0);
+    g3.C = Ut + (p0 + 1);
+    g3.ldc = ldt;
+    g3.bC = ZBatch::strided(ust);
+    g3.alpha = mk<C>(-1.0, 0.0);
+    g3.beta = mk<C>(1.0, 0.0);
     g3.batch = nb_mat;
     g3.tag = "unmtr";
-    BE_RET_IF(zgemm(ctx, g3, stream));
+    BE_RET_IF(GemmOf<T>::run(ctx, g3, stream));
+  }
+  if (mixed) {
+    hipLaunchKernelGGL(widen_u, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream,
+                       reinterpret_cast<const float2 *>(Uw), int64_t(N) * m, N, m, U, ldu, us);
+    BE_RET_IF(check_launch(ctx, "widen_u"));
+  }
+  return BE_OK;
+}
+
+template <typename T>
+static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo,
+                    int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
+                    hipStream_t stream) {
+  const int m = band_hi - band_lo;
+  if (n_mat == 0) return BE_OK;
+  // sub-batches bounded to ~4 GiB of workspace
+  const int P = (N + NB - 1) / NB;
+  const int mp = std::max(64, (m + 63) / 64 * 64);
+  const size_t cs = sizeof(typename CT<T>::c);
+  const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1) +
+                           size_t(N) * std::max(m, 1)) +
+                     sizeof(double) * (2 * size_t(N) + 4 * size_t(N) * mp + 2 * size_t(std::max(m, 1)) * std::max(m, 1)) +
+                     10 * 256;
+  const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
+  for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
+    const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
+    BE_RET_IF(eigh_chunk<T>(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo, band_hi, evals + b0 * (m + 2),
+                            U + b0 * u_stride, ldu, u_stride, status + b0, stream));
   }
   return BE_OK;
 }
 
 int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream) {
-  const int m = band_hi - band_lo;
-  if (n_mat == 0) return BE_OK;
-  // sub-batches bounded to ~4 GiB of workspace
-  const int P = (N + NB - 1) / NB;
-  const int mp = std::max(64, (m + 63) / 64 * 64);
-  const size_t per = sizeof(double2) * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1)) +
-                     sizeof(double) * (2 * size_t(N) + 4 * size_t(N) * mp + 2 * size_t(std::max(m, 1)) * std::max(m, 1)) +
-                     9 * 256;
-  const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
-  for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
-    const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
-    BE_RET_IF(eigh_fp64_chunk(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo,
-                              band_hi, evals + b0 * (m + 2), U + b0 * u_stride, ldu, u_stride,
-                              status + b0, stream));
-  }
-  return BE_OK;
+  return eigh_run<double>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream);
 }
 
 }  // namespace be
@@ -785,9 +861,13 @@ extern "C" int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, i
   BE_CHECK_ARG(ctx, ldu >= N && u_stride >= int64_t(ldu) * std::max(m, 1), "be_eigh_batched: ldu < N or u_stride too small");
   if (precision == BE_FP64) {
     BE_CHECK_ARG(ctx, dtype == BE_C128, "be_eigh_batched: BE_FP64 needs BE_C128 matrices");
-  } else {
-    return set_err(ctx, BE_ENOTIMPL, "be_eigh_batched: precision not implemented");
+    return eigh_run<double>(ctx, static_cast<double2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
+                            static_cast<double2 *>(U), ldu, u_stride, status, stream);
   }
-  return eigh_fp64(ctx, static_cast<double2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
-                   static_cast<double2 *>(U), ldu, u_stride, status, stream);
+  if (precision == BE_MIXED_FP32) {
+    BE_CHECK_ARG(ctx, dtype == BE_C64, "be_eigh_batched: BE_MIXED_FP32 needs BE_C64 matrices");
+    return eigh_run<float>(ctx, static_cast<float2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
+                           static_cast<double2 *>(U), ldu, u_stride, status, stream);
+  }
+  return set_err(ctx, BE_EINVAL, "be_eigh_batched: unknown precision");
 }

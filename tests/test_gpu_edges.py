@@ -1,0 +1,113 @@
+"""GPU edge cases, argument errors and physics status flags of the C ABI."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import berry as orc
+from tests import gpu_util as gu
+from tests.phase_metrics import phase_set_error
+
+torch = gu.torch
+pytestmark = pytest.mark.gpu
+
+
+def pipe():
+    from paper_2312_13051_amd import pipeline
+    return pipeline
+
+
+def test_empty_batches_are_noops():
+    gu.need_gpu()
+    c = gu.ctx()
+    z = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    d = torch.zeros(16, dtype=torch.float64, device="cuda")
+    i = torch.zeros(16, dtype=torch.int32, device="cuda")
+    c.eigh_batched(z, 0, 2, 2, 4, 0, 0, 1, 0, d, z, 2, 2, i)
+    c.wilson_loop(z, 2, 1, 2, 2, 0, 4, 4, 0, d, d, i, i)
+    plan = c.hk_plan([syn.qwz(1.0)])
+    kap = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    c.build_hk(plan, 0, 0, kap, z, 4, 2, 0)   # no systems
+    torch.cuda.synchronize()
+
+
+def test_no_selected_bands_and_single_point_loops():
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    hl = syn.bhz()
+    plan = c.hk_plan([hl])
+    kg = syn.kplane(4, 3)
+    g = P.eig_grid(c, plan, 0, 1, kg, 1, 1)       # m = 0
+    ev = g.evals.cpu().numpy()
+    ref = np.stack([np.linalg.eigvalsh(orc.bloch_hamiltonian(hl, k)) for k in kg.reshape(-1, 3)])
+    assert np.max(np.abs(ev[:, 0] - ref[:, 0])) < 1e-12 and np.max(np.abs(ev[:, 1] - ref[:, 1])) < 1e-12
+    # a loop of one point: the only overlap is U^H U = I, so every phase is 0
+    kg1 = syn.kplane(1, 5)
+    g1 = P.eig_grid(c, plan, 0, 1, kg1, 0, 2)
+    out = P.wilson(c, g1)
+    assert np.max(np.abs(out["theta"].cpu().numpy())) < 1e-12
+
+
+def test_argument_errors():
+    gu.need_gpu()
+    from paper_2312_13051_amd import BerryError
+    c = gu.ctx()
+    z = torch.zeros(64, dtype=torch.complex128, device="cuda")
+    d = torch.zeros(64, dtype=torch.float64, device="cuda")
+    i = torch.zeros(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(BerryError):
+        c.eigh_batched(z, 0, 4, 4, 16, 1, 3, 2, 0, d, z, 4, 16, i)      # lo > hi
+    with pytest.raises(BerryError):
+        c.eigh_batched(z, 1, 4, 4, 16, 1, 0, 2, 0, d, z, 4, 16, i)      # FP64 needs c128
+    with pytest.raises(BerryError):
+        c.eigh_batched(z, 0, 4, 3, 16, 1, 0, 2, 0, d, z, 4, 16, i)      # ld < N
+    with pytest.raises(BerryError):
+        c.wilson_loop(z, 4, 2, 4, 8, 1, 4, 4, 7, d, d, i, i)            # bad mode
+    with pytest.raises(BerryError):
+        c.wilson_loop(z, 4, 5, 4, 20, 1, 4, 4, 0, d, d, i, i)           # m > N
+    with pytest.raises(BerryError):
+        c.wilson_loop(z, 4, 2, 4, 8, 1, 0, 4, 0, d, d, i, i)            # n_par = 0
+
+
+def test_pso_gap_flag_with_zero_spin_operator():
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    out = P.wspinsurf(c, [syn.bhz()], np.zeros((1, 4)), syn.kplane(6, 4), 0, 2)
+    assert int(out["status"][0]) & 8
+
+
+def test_wannier_gap_flag_on_window_edge():
+    """Atomic limit: every Wilson phase is exactly 0, on the edge of (0, 1/2)."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    out = P.wnwl(c, [syn.atomic([-1.0, -0.5, 2.0])], syn.kplane(6, 4), 0, 2)
+    assert int(out["status"][0]) & 16
+
+
+def test_gap_closed_and_nan_flags_in_wilson_chain():
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    # degenerate Fermi level: bands 0,1 at -1 and band 2 also at -1
+    g = P.eig_grid(c, c.hk_plan([syn.atomic([-1.0, -1.0, -1.0, 2.0])]), 0, 1, syn.kplane(4, 2), 0, 2)
+    assert np.all(g.status.cpu().numpy() & 1)
+
+
+def test_uneven_sizes_one_call_per_size():
+    """Uneven batches (vacancy supercells of several L): each size runs as its
+    own call; results equal the oracle for every system."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    kg = syn.kplane(6, 4)
+    for L in (3, 4):
+        hls = [syn.bhz_vacancies(L, 0.12, [4, 1, s]) for s in range(2)]
+        Ns = {h.N for h in hls}
+        for N in Ns:
+            group = [h for h in hls if h.N == N]
+            out = P.wsurf(c, group, kg, 0, N // 2)
+            for r, h in enumerate(group):
+                ref = orc.wilson_surface(h, kg, 0, N // 2)
+                assert phase_set_error(out["theta"][r].cpu().numpy(), ref["theta"]) < 1e-10

@@ -106,3 +106,39 @@ def test_eigh_nan_input_flagged():
     c = gu.ctx()
     ev, U, st = run_eigh(c, H, 0, 3)
     assert st[0] & 64
+
+
+def run_eigh_mixed(c, Hs, lo, hi):
+    n, N, _ = Hs.shape
+    m = hi - lo
+    dH = gu.from_np(Hs, N, dtype=torch.complex64)
+    U = gu.colmajor(n, N, max(m, 1), N, fill=0)
+    ev = torch.empty((n, m + 2), dtype=torch.float64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    c.eigh_batched(dH, 1, N, N, dH.stride(0), n, lo, hi, 1, ev, U, N, U.stride(0), st)
+    torch.cuda.synchronize()
+    return ev.cpu().numpy(), gu.to_np(U, N)[:, :, :m], st.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["bhz_L10_W2", "bhz_vac_L6", "wannier96"])
+def test_eigh_mixed_precision_bounds(name):
+    """FP32 reduction + FP64 tridiagonal solve and re-orthonormalization:
+    eigenvalues within 2e-5 ||H||, U orthonormal to FP64 level in Z and FP32
+    level after the FP32 back-transformation, projector within 1e-4."""
+    gu.need_gpu()
+    hl = {"bhz_L10_W2": lambda: syn.bhz_disordered(10, 2.0, [3, 2, 1]),
+          "bhz_vac_L6": lambda: syn.bhz_vacancies(6, 0.05, [4, 1, 3]),
+          "wannier96": lambda: syn.wannier_like(96, [5, 2, 1])}[name]()
+    kap = syn.kplane(2, 2).reshape(-1, 3)
+    Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in kap])
+    c = gu.ctx()
+    m = hl.N // 2
+    ev, U, st = run_eigh_mixed(c, Hs, 0, m)
+    for q in range(Hs.shape[0]):
+        w, V = np.linalg.eigh(Hs[q])
+        nrm = max(1.0, np.max(np.abs(w)))
+        assert np.max(np.abs(ev[q, 1:m + 1] - w[:m])) <= 2e-5 * nrm
+        assert np.max(np.abs(U[q].conj().T @ U[q] - np.eye(m))) < 1e-5
+        P = U[q] @ U[q].conj().T
+        assert np.max(np.abs(P - V[:, :m] @ V[:, :m].conj().T)) < 1e-4
+        assert st[q] == 0

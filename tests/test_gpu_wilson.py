@@ -183,3 +183,29 @@ def test_choti_spin_nonconserved():
     assert int(out["status"][0]) == ref["status"] == 0
     assert abs(float(out["C_s"][0])) == 1.0 and float(out["C_s"][0]) == ref["C_s"]
     assert phase_set_error(out["theta_dn"][0, :, :1].cpu().numpy(), ref["theta_dn"]) < TOL
+
+
+@pytest.mark.parametrize("name", ["bhz_L3_W2", "bhz_L4_vac", "bhz_L10_W3"])
+def test_mixed_precision_phases_within_gate(name):
+    """Mixed path (FP32 reduction and back-transformation, FP64 elsewhere):
+    Wilson phases within the 1e-6 rad gate of the FP64 oracle, integers exact."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    hl = {"bhz_L3_W2": lambda: syn.bhz_disordered(3, 2.0, [3, 1, 5]),
+          "bhz_L4_vac": lambda: syn.bhz_vacancies(4, 0.1, [4, 1, 2]),
+          "bhz_L10_W3": lambda: syn.bhz_disordered(10, 3.0, [3, 3, 0])}[name]()
+    kg = syn.kplane(8, 3) if hl.N > 100 else syn.kplane(12, 7)
+    m = hl.N // 2
+    out = P.wsurf(c, [hl], kg, 0, m, precision=1)
+    ref = orc.wilson_surface(hl, kg, 0, m)
+    assert phase_set_error(out["theta"][0].cpu().numpy(), ref["theta"]) < 1e-6
+    sd = syn.bhz_spin_diag(hl)
+    plan = c.hk_plan([hl])
+    g = P.eig_grid(c, plan, 0, 1, kg, 0, m, precision=1)
+    sp = P.spin(c, g, sd[None])
+    sref = orc.spin_resolved_wilson(hl, sd, kg, 0, m)
+    md = sp["m_dn"][0]
+    assert md == sref["m_minus"]
+    assert phase_set_error(sp["theta_dn"][0, :, :md].cpu().numpy(), sref["theta_dn"]) < 1e-6
+    assert phase_set_error(sp["theta_up"][0, :, :m - md].cpu().numpy(), sref["theta_up"]) < 1e-6
