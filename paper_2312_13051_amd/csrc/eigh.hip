@@ -5,21 +5,25 @@
 //    One workgroup per matrix runs a panel of nb columns (hetrd_panel): for
 //    each column it applies the panel's earlier reflectors to that column,
 //    builds the reflector, forms the matrix-vector product with the trailing
-//    matrix (one wave per 64-row block, v broadcast from LDS) and the
+//    matrix (full square, one wave per 64-row block, v broadcast from LDS) and the
 //    symmetric rank-2 correction vector w. The trailing matrix is then updated
 //    once per panel by a rank-2nb MFMA GEMM, C -= [V W] [W V]^H. The panel's
 //    compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the fly from
 //    the same dot products.
 // 2. FP64 tridiagonal eigensolver (tridiag_eig): bisection with Sturm counts,
 //    one lane per eigenvalue, for the selected indices and their neighbours;
-//    inverse iteration with partial pivoting, one lane per eigenvector, from
-//    independent pseudo-random starts (inside an exactly degenerate cluster
-//    they converge to independent vectors of the cluster's space). The
-//    vectors are then made orthonormal by FP64 Cholesky-QR, twice, as MFMA
-//    DGEMMs (Gram matrix, L^{-1} Z) around a per-matrix Cholesky kernel.
+//    T is split where an off-diagonal is negligible (an eigenvalue of
+//    multiplicity k forces k-1 such splits), and the k lanes of a k-fold
+//    eigenvalue run inverse iteration (partial pivoting, pseudo-random start)
+//    on k distinct blocks that hold it, so their vectors have disjoint
+//    supports; lanes that must share a block fall back to Gram-Schmidt. The
+//    vectors are then orthonormalized in FP64 by Newton-Schulz steps on the
+//    Gram matrix (symmetric orthonormalization, MFMA DGEMMs) until
+//    max |Z^T Z - I| < 1e-14.
 // 3. Back-transformation U = Q Z by panels in reverse order with three MFMA
 //    GEMMs each: X = V^H U, Y = T X, U -= V Y.
-// 4. Mixed precision only: FP64 Cholesky-QR re-orthonormalization of U.
+// 4. Mixed precision: the reduction and back-transformation run in FP32 on
+//    FP32 MFMA; the tridiagonal solve and the orthonormalization stay FP64.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -29,7 +33,8 @@
 namespace {
 
 constexpr int NB = 32;   // panel width
-constexpr int PT = 256;  // threads of the panel and tridiagonal kernels
+constexpr int PT = 256;   // threads of the tridiagonal and small kernels
+constexpr int PP = 1024;  // threads of the panel kernel (one matrix per CU)
 
 template <typename T>
 struct CT;
@@ -85,7 +90,7 @@ __device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
 // leading dimension N), Tm: per-matrix NB x NB compact-WY factor of each
 // panel, d/e: FP64 tridiagonal output.
 template <typename T>
-__global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
+__global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
                                                   typename CT<T>::c *VW, int64_t sVW, typename CT<T>::c *Tm,
                                                   int64_t sTm, double *d, double *e, int64_t sDE, uint32_t *status) {
   typedef typename CT<T>::c C;
@@ -97,7 +102,8 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
   C *st1 = sWr + NB;                        // W^H v (NB)
   C *st2 = st1 + NB;                        // V^H v (NB)
   C *sT = st2 + NB;                         // NB x NB, column-major
-  T *red = reinterpret_cast<T *>(sT + NB * NB);  // 2 * waves
+  C *spart = sT + NB * NB;                  // per-lane partial sums of H v (PP)
+  T *red = reinterpret_cast<T *>(spart + PP);  // 2 * waves
   __shared__ C s_tau, s_scal;
   __shared__ T s_beta;
 
@@ -106,20 +112,20 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
   C *V = VW + q * sVW;
   C *W = V + int64_t(NB) * N;
   C *V2 = W + int64_t(NB) * N;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PP / 64;
 
-  for (int e2 = tid; e2 < NB * NB; e2 += PT) sT[e2] = mk<C>(0, 0);
+  for (int e2 = tid; e2 < NB * NB; e2 += PP) sT[e2] = mk<C>(0, 0);
   __syncthreads();
 
   for (int jj = 0; jj < nbp; ++jj) {
     const int j = p0 + jj;
     // ---- (1) apply the panel's earlier reflectors to column j
-    for (int c = tid; c < jj; c += PT) {
+    for (int c = tid; c < jj; c += PP) {
       sVr[c] = V[j + int64_t(c) * N];
       sWr[c] = W[j + int64_t(c) * N];
     }
     __syncthreads();
-    for (int r = j + tid; r < N; r += PT) {
+    for (int r = j + tid; r < N; r += PP) {
       C a = Aq[r + int64_t(j) * lda];
       T ar = a.x, ai = a.y;
       for (int c = 0; c < jj; ++c) {
@@ -138,7 +144,7 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
     __syncthreads();
     if (j == N - 1) {
       // last column: no reflector. Column j of V and W is zero.
-      for (int r = tid; r < N; r += PT) {
+      for (int r = tid; r < N; r += PP) {
         Aq[r + int64_t(j) * lda] = mk<C>(0, 0);
         V[r + int64_t(jj) * N] = mk<C>(0, 0);
         W[r + int64_t(jj) * N] = mk<C>(0, 0);
@@ -149,7 +155,7 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
     }
     // ---- (2) reflector from A(j+1:N, j)
     T xn = 0, dummy = 0;
-    for (int r = j + 2 + tid; r < N; r += PT) {
+    for (int r = j + 2 + tid; r < N; r += PP) {
       C a = Aq[r + int64_t(j) * lda];
       xn += a.x * a.x + a.y * a.y;
     }
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
     __syncthreads();
     const C tau = s_tau, scal = s_scal;
     // v: zero above j+1, one at j+1, scaled x below; into LDS, A's column j, V and V2
-    for (int r = tid; r < N; r += PT) {
+    for (int r = tid; r < N; r += PP) {
       C v;
       if (r <= j) {
         v = mk<C>(0, 0);
@@ -196,55 +202,65 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
       V2[r + int64_t(jj) * N] = v;
     }
     __syncthreads();
-    // ---- (3) y = A(j+1:N, j+1:N) v from the lower triangle only.
-    // 32x32 tiles (I >= J) are dealt to waves; in a wave the low 32 lanes
-    // take the tile's rows (y_I += A_IJ v_J, one column of 32 consecutive
-    // rows per load) and the high 32 lanes its columns (y_J += A_IJ^H v_I);
-    // diagonal tiles use their lower part only. Partial sums are added into
-    // LDS atomically (sy was zeroed with v).
+    // ---- (3) y = A(j+1:N, j+1:N) v over the full trailing square. Work items
+    // are (64-row block, column slice) pairs, enough of them to give every
+    // wave one; each lane owns one row, v is broadcast from LDS and every load
+    // is one coalesced 64-row column segment. With several slices each wave
+    // holds at most one item; the slices' partial sums are combined in a fixed
+    // order through LDS, so the result does not depend on scheduling.
     const int r0 = j + 1;
     const int nrow = N - r0;
-    const int nb32 = (nrow + 31) / 32;
-    const int ntile = nb32 * (nb32 + 1) / 2;
-    const int half = lane >> 5, l32 = lane & 31;
-    for (int t = wave; t < ntile; t += nw) {
-      // tile t -> (I, J), J-major over the lower triangle
-      int J = 0, rem = t;
-      while (rem >= nb32 - J) {
-        rem -= nb32 - J;
-        ++J;
+    const int nrb = (nrow + 63) / 64;
+    const int ncs = max(1, nw / nrb);
+    const int clen = (nrow + ncs - 1) / ncs;
+    auto slice_dot = [&](int rb, int cs, T &yr, T &yi) {
+      const int r = r0 + rb * 64 + lane;
+      const int cb = r0 + cs * clen, ce = min(N, cb + clen);
+      yr = 0;
+      yi = 0;
+      if (r >= N) return;
+      const C *col = Aq + r;
+      int c = cb;
+      // UN independent column loads in flight per lane (128 B per lane)
+      constexpr int UN = 128 / sizeof(C);
+      for (; c + UN <= ce; c += UN) {
+        C a[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) a[u] = col[int64_t(c + u) * lda];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          const C v = sv[c + u];
+          yr += a[u].x * v.x - a[u].y * v.y;
+          yi += a[u].x * v.y + a[u].y * v.x;
+        }
       }
-      const int I = J + rem;
+      for (; c < ce; ++c) {
+        C a = col[int64_t(c) * lda], v = sv[c];
+        yr += a.x * v.x - a.y * v.y;
+        yi += a.x * v.y + a.y * v.x;
+      }
+    };
+    if (ncs == 1) {
+      for (int rb = wave; rb < nrb; rb += nw) {
+        T yr, yi;
+        slice_dot(rb, 0, yr, yi);
+        const int r = r0 + rb * 64 + lane;
+        if (r < N) sy[r] = mk<C>(yr, yi);
+      }
+    } else {
       T yr = 0, yi = 0;
-      if (half == 0) {
-        const int r = r0 + 32 * I + l32;
-        if (r < N) {
-          const int cmax = min(32, N - (r0 + 32 * J));
-          const int clim = (I == J) ? min(cmax, l32 + 1) : cmax;
-          const C *row = Aq + r + int64_t(r0 + 32 * J) * lda;
-          for (int c = 0; c < clim; ++c) {
-            C a = row[int64_t(c) * lda], v = sv[r0 + 32 * J + c];
-            yr += a.x * v.x - a.y * v.y;
-            yi += a.x * v.y + a.y * v.x;
-          }
-          atomicAdd(&sy[r].x, yr);
-          atomicAdd(&sy[r].y, yi);
+      if (wave < nrb * ncs) slice_dot(wave % nrb, wave / nrb, yr, yi);
+      spart[tid] = mk<C>(yr, yi);
+      __syncthreads();
+      for (int r = r0 + tid; r < N; r += PP) {
+        const int rb = (r - r0) >> 6, l = (r - r0) & 63;
+        T sr = 0, si = 0;
+        for (int cs = 0; cs < ncs; ++cs) {
+          const C pp = spart[(rb + cs * nrb) * 64 + l];
+          sr += pp.x;
+          si += pp.y;
         }
-      } else {
-        const int c = r0 + 32 * J + l32;
-        if (c < N) {
-          const int rmax = min(32, N - (r0 + 32 * I));
-          const int rlo = (I == J) ? l32 + 1 : 0;
-          const C *col = Aq + (r0 + 32 * I) + int64_t(c) * lda;
-          for (int rr = rlo; rr < rmax; ++rr) {
-            C a = col[rr], v = sv[r0 + 32 * I + rr];
-            // conj(a) * v
-            yr += a.x * v.x + a.y * v.y;
-            yi += a.x * v.y - a.y * v.x;
-          }
-          atomicAdd(&sy[c].x, yr);
-          atomicAdd(&sy[c].y, yi);
-        }
+        sy[r] = mk<C>(sr, si);
       }
     }
     // ---- (4) t1 = W^H v, t2 = V^H v over rows j+1..N-1 (one wave per column c)
@@ -268,7 +284,7 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
     }
     __syncthreads();
     // y -= V t1 + W t2
-    for (int r = r0 + tid; r < N; r += PT) {
+    for (int r = r0 + tid; r < N; r += PP) {
       C y = sy[r];
       T yr = y.x, yi = y.y;
       for (int c = 0; c < jj; ++c) {
@@ -294,14 +310,14 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
     __syncthreads();
     // ---- (5) w += alpha v with alpha = -1/2 tau (w^H v)
     T dr = 0, di = 0;
-    for (int r = r0 + tid; r < N; r += PT) {
+    for (int r = r0 + tid; r < N; r += PP) {
       C w = sy[r], v = sv[r];
       dr += w.x * v.x + w.y * v.y;
       di += w.x * v.y - w.y * v.x;
     }
     block_sum2(dr, di, red);
     const T alr = T(-0.5) * (tau.x * dr - tau.y * di), ali = T(-0.5) * (tau.x * di + tau.y * dr);
-    for (int r = tid; r < N; r += PT) {
+    for (int r = tid; r < N; r += PP) {
       C w;
       if (r < r0) {
         w = mk<C>(0, 0);
@@ -315,7 +331,7 @@ __global__ __launch_bounds__(PT) void hetrd_panel(typename CT<T>::c *A, int64_t 
   }
   // ---- write the panel's T factor
   C *Tq = Tm + q * sTm;
-  for (int e2 = tid; e2 < NB * NB; e2 += PT) Tq[e2] = sT[e2];
+  for (int e2 = tid; e2 < NB * NB; e2 += PP) Tq[e2] = sT[e2];
   (void)status;
 }
 
@@ -352,8 +368,10 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
   double *se2 = se + N;      // N
   double *slam = se2 + N;    // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
   const int m = hi - lo;
+  int *sblk = reinterpret_cast<int *>(slam + m + 4);  // block starts (N + 1)
+  int *smark = sblk + N + 1;                           // clusters needing Gram-Schmidt (m)
   __shared__ double red[2 * (PT / 64)];
-  __shared__ int s_bad;
+  __shared__ int s_bad, s_nblk;
 
   const int64_t q = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
@@ -453,21 +471,62 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
     if (hi < N && m > 0) g = fmin(g, slam[3] - lam[m - 1]);
     if (g < 1e-9 * scale) st |= BE_ST_GAP_CLOSED;
   }
-  // ---- inverse iteration, one lane per eigenvector
+  // ---- split T where an off-diagonal is negligible; blocks [sblk[b], sblk[b+1])
+  const double splittol = 16.0 * eps * tnorm;
+  if (tid == 0) {
+    int nb = 0;
+    sblk[nb++] = 0;
+    for (int i = 1; i < N; ++i)
+      if (fabs(se[i - 1]) <= splittol) sblk[nb++] = i;
+    sblk[nb] = N;
+    s_nblk = nb;
+  }
+  for (int c = tid; c < m; c += PT) smark[c] = 0;
+  __syncthreads();
+  const int nblk = s_nblk;
+  // ---- inverse iteration, one lane per eigenvector. The k lanes of a
+  // k-fold eigenvalue (equal within dclu) take k distinct blocks that hold
+  // it, so their vectors have disjoint supports; lanes that must share a
+  // block are orthogonalized below.
   double *Z0 = Zs + q * sZ;
   double *Z1 = Z0 + int64_t(N) * mp;
   double *Z2 = Z1 + int64_t(N) * mp;
   double *X = Z2 + int64_t(N) * mp;
   const double tiny = eps * fmax(tnorm, DBL_MIN);
+  // tolerances: split (above) < block window < cluster gap, so a cluster's
+  // window never reaches the next cluster
+  const double dblk = 32.0 * eps * tnorm, dclu = 64.0 * eps * tnorm;
   bool lane_bad = false;
   for (int c = tid; c < m; c += PT) {
     const double lm = lam[c];
+    int c0 = c, c1 = c + 1;
+    while (c0 > 0 && lam[c0] - lam[c0 - 1] <= dclu) --c0;
+    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+    const double wlo = lam[c0] - dblk, whi = lam[c1 - 1] + dblk;
+    const int jr = c - c0;
+    int bs = 0, bt = N, cnt = 0;
+    bool found = false, shared = false;
+    for (int b = 0; b < nblk && !found; ++b) {
+      const int s0 = sblk[b], t0 = sblk[b + 1];
+      const int nb = sturm_count(sd + s0, se2 + s0, t0 - s0, whi, pivmin) -
+                     sturm_count(sd + s0, se2 + s0, t0 - s0, wlo, pivmin);
+      if (nb > 0 && cnt + nb > jr) {
+        bs = s0;
+        bt = t0;
+        found = true;
+        shared = nb > 1;
+      }
+      cnt += nb;
+    }
+    if (!found || shared) smark[c0] = 1;
+    for (int i = 0; i < N; ++i)
+      if (i < bs || i >= bt) X[int64_t(i) * mp + c] = 0.0;
     for (int it = 0; it < 3; ++it) {
-      // forward elimination with partial pivoting on [T - lm I | rhs]
-      double a = sd[0] - lm, b = N > 1 ? se[0] : 0.0;
-      double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, 0) : X[c];
-      for (int i = 0; i + 1 < N; ++i) {
-        const double ei = se[i], Dn = sd[i + 1] - lm, en = (i + 2 < N) ? se[i + 1] : 0.0;
+      // forward elimination with partial pivoting on [T_block - lm I | rhs]
+      double a = sd[bs] - lm, b = bt - bs > 1 ? se[bs] : 0.0;
+      double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, bs) : X[int64_t(bs) * mp + c];
+      for (int i = bs; i + 1 < bt; ++i) {
+        const double ei = se[i], Dn = sd[i + 1] - lm, en = (i + 2 < bt) ? se[i + 1] : 0.0;
         const double rn = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, i + 1) : X[int64_t(i + 1) * mp + c];
         const int64_t o = int64_t(i) * mp + c;
         if (fabs(a) >= fabs(ei)) {
@@ -494,7 +553,7 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
       }
       if (a == 0.0) a = tiny;
       {
-        const int64_t o = int64_t(N - 1) * mp + c;
+        const int64_t o = int64_t(bt - 1) * mp + c;
         Z0[o] = a;
         Z1[o] = 0.0;
         Z2[o] = 0.0;
@@ -502,7 +561,7 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
       }
       // back substitution
       double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-      for (int i = N - 1; i >= 0; --i) {
+      for (int i = bt - 1; i >= bs; --i) {
         const int64_t o = int64_t(i) * mp + c;
         double xi = (X[o] - Z1[o] * x1 - Z2[o] * x2) / Z0[o];
         X[o] = xi;
@@ -512,10 +571,36 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
       }
       double inv = 1.0 / sqrt(nrm);
       if (!isfinite(inv) || inv == 0.0) lane_bad = true;
-      for (int i = 0; i < N; ++i) X[int64_t(i) * mp + c] *= inv;
+      for (int i = bs; i < bt; ++i) X[int64_t(i) * mp + c] *= inv;
     }
   }
   if (lane_bad) st |= BE_ST_NONCONVERGED;
+  __syncthreads();
+  // ---- clusters whose members share a block: modified Gram-Schmidt (two
+  // passes), one wave per cluster
+  for (int c0 = wave; c0 < m; c0 += nw) {
+    if (!smark[c0]) continue;
+    int c1 = c0 + 1;
+    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int t = c0; t < c1; ++t) {
+        for (int s = c0; s < t; ++s) {
+          double dt = 0.0;
+          for (int i = lane; i < N; i += 64) dt = fma(X[int64_t(i) * mp + s], X[int64_t(i) * mp + t], dt);
+          dt = wave_sum(dt);
+          for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] -= dt * X[int64_t(i) * mp + s];
+        }
+        double nr = 0.0;
+        for (int i = lane; i < N; i += 64) {
+          double v = X[int64_t(i) * mp + t];
+          nr = fma(v, v, nr);
+        }
+        nr = wave_sum(nr);
+        const double inv = 1.0 / sqrt(nr);
+        for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] *= inv;
+      }
+    }
+  }
   // status: OR of lane flags
   {
     __shared__ unsigned int sst;
@@ -527,48 +612,37 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
   }
 }
 
-// Cholesky G = L L^T of each m x m Gram matrix (in place, lower triangle),
-// then Li = L^{-1} (lower triangular, zeros above). One workgroup per matrix.
-// A non-positive pivot (rank-deficient basis) sets NONCONVERGED.
-__global__ __launch_bounds__(PT) void chol_inv(double *G, int m, double *Li, uint32_t *status) {
+// One Newton-Schulz step of the symmetric orthonormalization of X (m x N):
+// G = X X^T is replaced by (3 I - G) / 2; err[q] = max |G - I| (before the
+// update) and, atomically, the maximum over matrices into *gmax (the bit
+// pattern of a non-negative double orders like an integer).
+__global__ __launch_bounds__(PT) void ns_prep_real(double *G, int m, double *err, unsigned long long *gmax) {
   const int64_t q = blockIdx.x;
   double *Gq = G + q * int64_t(m) * m;
-  double *Lq = Li + q * int64_t(m) * m;
-  const int tid = threadIdx.x;
-  __shared__ double s_piv;
-  __shared__ int s_bad;
-  if (tid == 0) s_bad = 0;
-  for (int k = 0; k < m; ++k) {
-    if (tid == 0) {
-      double dk = Gq[k + int64_t(k) * m];
-      if (!(dk > 0.0)) {
-        s_bad = 1;
-        dk = 1.0;
-      }
-      s_piv = sqrt(dk);
-      Gq[k + int64_t(k) * m] = s_piv;
-    }
-    __syncthreads();
-    const double piv = s_piv;
-    for (int i = k + 1 + tid; i < m; i += PT) Gq[i + int64_t(k) * m] /= piv;
-    __syncthreads();
-    const int n2 = m - k - 1;
-    for (int e = tid; e < n2 * n2; e += PT) {
-      const int i = k + 1 + e % n2, j = k + 1 + e / n2;
-      if (i >= j) Gq[i + int64_t(j) * m] -= Gq[i + int64_t(k) * m] * Gq[j + int64_t(k) * m];
-    }
-    __syncthreads();
+  double e = 0.0;
+  for (int k = threadIdx.x; k < m * m; k += PT) {
+    const int r = k % m, c = k / m;
+    const double g = Gq[k];
+    e = fmax(e, fabs(g - (r == c ? 1.0 : 0.0)));
+    Gq[k] = (r == c ? 1.5 : 0.0) - 0.5 * g;
   }
-  for (int j = tid; j < m; j += PT) {
-    for (int i = 0; i < j; ++i) Lq[i + int64_t(j) * m] = 0.0;
-    Lq[j + int64_t(j) * m] = 1.0 / Gq[j + int64_t(j) * m];
-    for (int i = j + 1; i < m; ++i) {
-      double sacc = 0.0;
-      for (int k = j; k < i; ++k) sacc = fma(Gq[i + int64_t(k) * m], Lq[k + int64_t(j) * m], sacc);
-      Lq[i + int64_t(j) * m] = -sacc / Gq[i + int64_t(i) * m];
-    }
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
+  __shared__ double red[PT / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < PT / 64; ++w) t = fmax(t, red[w]);
+    if (!(t == t)) t = INFINITY;
+    err[q] = t;
+    atomicMax(gmax, (unsigned long long)__double_as_longlong(t));
   }
-  if (tid == 0 && s_bad) status[q] |= BE_ST_NONCONVERGED;
+}
+
+// status[q] |= NONCONVERGED where the last orthonormality error stayed above tol
+__global__ void flag_nonorth(const double *err, int64_t n, double tol, uint32_t *status) {
+  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < n && !(err[q] <= tol)) status[q] |= BE_ST_NONCONVERGED;
 }
 
 // U[q](r, c) = X[q](c, r) as complex (X: m x N column-major, leading dimension mp)
@@ -591,13 +665,18 @@ __global__ void widen_u(const float2 *Uw, int64_t sW, int N, int m, double2 *U, 
   }
 }
 
+__global__ void zero_d(double *p, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 __global__ void zero_u32(uint32_t *p, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
 
 size_t panel_smem(int N, size_t csize) {
-  return (2 * size_t(N) + 4 * NB + NB * NB) * csize + 2 * (PT / 64) * (csize / 2) + 64;
+  return (2 * size_t(N) + 4 * NB + NB * NB + PP) * csize + 2 * (PP / 64) * (csize / 2) + 64;
 }
 
 }  // namespace
@@ -638,9 +717,11 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   cv.add(&dd, size_t(nb_mat) * N);
   cv.add(&ee, size_t(nb_mat) * N);
   cv.add(&Zs, size_t(nb_mat) * 4 * N * mp);
-  double *Gm = nullptr, *Li = nullptr;
+  double *Gm = nullptr, *oerr = nullptr;
+  unsigned long long *gmax = nullptr;
   cv.add(&Gm, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
-  cv.add(&Li, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
+  cv.add(&oerr, size_t(nb_mat));
+  cv.add(&gmax, 1);
   cv.add(&Xb, size_t(nb_mat) * NB * std::max(m, 1));
   cv.add(&Yb, size_t(nb_mat) * NB * std::max(m, 1));
   if (mixed) cv.add(&Uw, size_t(nb_mat) * N * std::max(m, 1));
@@ -658,7 +739,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     const int p0 = p * NB, nbp = std::min(NB, N - p0);
     {
       ProfScope prof(ctx, "hetrd_panel", stream);
-      hipLaunchKernelGGL(hetrd_panel<T>, dim3(nb_mat), dim3(PT), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
+      hipLaunchKernelGGL(hetrd_panel<T>, dim3(nb_mat), dim3(PP), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
                          Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
     }
     BE_RET_IF(check_launch(ctx, "hetrd_panel"));
@@ -683,12 +764,11 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.beta = mk<C>(1.0, 0.0);
       g.batch = nb_mat;
       g.tag = "her2k";
-      g.lower = true;  // the reduction reads only the lower triangle
       BE_RET_IF(GemmOf<T>::run(ctx, g, stream));
     }
   }
   // ---- tridiagonal eigenpairs
-  const size_t tsm = (3 * size_t(N) + m + 4) * sizeof(double) + 64;
+  const size_t tsm = (3 * size_t(N) + m + 4) * sizeof(double) + (size_t(N) + 1 + m) * sizeof(int) + 64;
   if (tsm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tridiag_eig),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(tsm)));
@@ -703,22 +783,25 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   C *Ut = mixed ? Uw : reinterpret_cast<C *>(U);
   const int ldt = mixed ? N : ldu;
   const int64_t ust = mixed ? int64_t(N) * m : us;
-  // ---- Cholesky-QR (twice) of Z, held as X = Z^T (m x N, leading dim mp)
+  // ---- symmetric orthonormalization of Z (Newton-Schulz on the Gram matrix),
+  // Z held as X = Z^T (m x N, leading dim mp); iterated until max |X X^T - I|
+  // is below 1e-14 (two steps from inverse-iteration vectors)
   {
     const int64_t sZ = int64_t(4) * N * mp;
     double *Xa = Zs + int64_t(3) * N * mp, *Xt = Zs;
-    for (int pass = 0; pass < 2; ++pass) {
-      double *src = pass == 0 ? Xa : Xt, *dst = pass == 0 ? Xt : Xa;
+    double *hmax = static_cast<double *>(ctx->pinned);
+    for (int it = 0; it < 8; ++it) {
+      BE_HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), stream));
       DGemm g;  // G = X X^T
       g.M = m;
       g.N = m;
       g.K = N;
       g.opA = 0;
       g.opB = 1;
-      g.A = src;
+      g.A = Xa;
       g.lda = mp;
       g.bA = ZBatch::strided(sZ);
-      g.B = src;
+      g.B = Xa;
       g.ldb = mp;
       g.bB = ZBatch::strided(sZ);
       g.C = Gm;
@@ -727,28 +810,36 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.batch = nb_mat;
       g.tag = "reorth";
       BE_RET_IF(dgemm(ctx, g, stream));
-      {
-        ProfScope prof(ctx, "chol_inv", stream);
-        hipLaunchKernelGGL(chol_inv, dim3(nb_mat), dim3(PT), 0, stream, Gm, m, Li, status);
-      }
-      BE_RET_IF(check_launch(ctx, "chol_inv"));
-      DGemm h;  // X <- L^{-1} X
+      hipLaunchKernelGGL(ns_prep_real, dim3(nb_mat), dim3(PT), 0, stream, Gm, m, oerr, gmax);
+      BE_RET_IF(check_launch(ctx, "ns_prep_real"));
+      BE_HIP_TRY(ctx, hipMemcpyAsync(hmax, gmax, sizeof(double), hipMemcpyDeviceToHost, stream));
+      BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+      const double e = *hmax;
+      if (e <= 1e-14) break;
+      DGemm h;  // X <- (3 I - G) X / 2
       h.M = m;
       h.N = N;
       h.K = m;
-      h.A = Li;
+      h.A = Gm;
       h.lda = m;
       h.bA = ZBatch::strided(int64_t(m) * m);
-      h.B = src;
+      h.B = Xa;
       h.ldb = mp;
       h.bB = ZBatch::strided(sZ);
-      h.C = dst;
+      h.C = Xt;
       h.ldc = mp;
       h.bC = ZBatch::strided(sZ);
       h.batch = nb_mat;
       h.tag = "reorth";
       BE_RET_IF(dgemm(ctx, h, stream));
+      std::swap(Xa, Xt);
+      if (e < 1e-8) {  // quadratic convergence: this step brought it below 1e-16
+        hipLaunchKernelGGL(zero_d, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat);
+        BE_RET_IF(check_launch(ctx, "zero_d"));
+        break;
+      }
     }
+    hipLaunchKernelGGL(flag_nonorth, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat, 1e-10, status);
     hipLaunchKernelGGL(z_to_u<C>, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream, Xa, sZ, mp, N, m, Ut, ldt,
                        ust);
     BE_RET_IF(check_launch(ctx, "z_to_u"));
@@ -831,8 +922,8 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   const size_t cs = sizeof(typename CT<T>::c);
   const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1) +
                            size_t(N) * std::max(m, 1)) +
-                     sizeof(double) * (2 * size_t(N) + 4 * size_t(N) * mp + 2 * size_t(std::max(m, 1)) * std::max(m, 1)) +
-                     10 * 256;
+                     sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1)) +
+                     11 * 256;
   const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);

@@ -104,10 +104,15 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
       acci[a][b] = acc_t{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < p.K; k0 += KB) {
-    // ---- stage A tile: element (i, k) of op(A)
+  // Software pipeline: the global loads of k-tile t+1 are issued into
+  // registers before the MFMAs of tile t, and stored to LDS after them.
+  constexpr int EA = (BM * KB + NT - 1) / NT;
+  constexpr int EB = (BN * KB + NT - 1) / NT;
+  cplx ga[EA], gb[EB];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = tid; e < BM * KB; e += NT) {
+    for (int u = 0; u < EA; ++u) {
+      const int e = tid + u * NT;
       int i, k;
       if (OPA == 0) {
         i = e % BM;
@@ -116,19 +121,16 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
         k = e % KB;
         i = e / KB;
       }
-      int gi = i0 + i, gk = k0 + k;
-      T vr = 0, vi = 0;
-      if (gi < p.M && gk < p.K) {
-        cplx v = OPA == 0 ? A[gi + int64_t(gk) * p.lda] : A[gk + int64_t(gi) * p.lda];
-        vr = v.x;
-        vi = OPA == 0 ? v.y : -v.y;
-      }
-      sAr[k * PA + i] = vr;
-      sAi[k * PA + i] = vi;
+      const int gi = i0 + i, gk = k0 + k;
+      cplx v;
+      v.x = 0;
+      v.y = 0;
+      if (e < BM * KB && gi < p.M && gk < p.K) v = OPA == 0 ? A[gi + int64_t(gk) * p.lda] : A[gk + int64_t(gi) * p.lda];
+      ga[u] = v;
     }
-    // ---- stage B tile: element (k, j) of op(B)
 #pragma unroll
-    for (int e = tid; e < BN * KB; e += NT) {
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + u * NT;
       int j, k;
       if (OPB == 0) {
         k = e % KB;
@@ -137,17 +139,38 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
         j = e % BN;
         k = e / BN;
       }
-      int gj = j0 + j, gk = k0 + k;
-      T vr = 0, vi = 0;
-      if (gj < p.N && gk < p.K) {
-        cplx v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
-        vr = v.x;
-        vi = OPB == 0 ? v.y : -v.y;
-      }
-      sBr[k * PB + j] = vr;
-      sBi[k * PB + j] = vi;
+      const int gj = j0 + j, gk = k0 + k;
+      cplx v;
+      v.x = 0;
+      v.y = 0;
+      if (e < BN * KB && gj < p.N && gk < p.K) v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
+      gb[u] = v;
     }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int e = tid + u * NT;
+      if (e >= BM * KB) break;
+      const int i = OPA == 0 ? e % BM : e / KB, k = OPA == 0 ? e / BM : e % KB;
+      sAr[k * PA + i] = ga[u].x;
+      sAi[k * PA + i] = OPA == 0 ? ga[u].y : -ga[u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + u * NT;
+      if (e >= BN * KB) break;
+      const int j = OPB == 0 ? e / KB : e % BN, k = OPB == 0 ? e % KB : e / BN;
+      sBr[k * PB + j] = gb[u].x;
+      sBi[k * PB + j] = OPB == 0 ? gb[u].y : -gb[u].y;
+    }
+  };
+
+  gload(0);
+  for (int k0 = 0; k0 < p.K; k0 += KB) {
+    sstore();
     __syncthreads();
+    if (k0 + KB < p.K) gload(k0 + KB);
 #pragma unroll
     for (int kk = 0; kk < KB; kk += 4) {
       T ar[TM], ai[TM], br[TN], bi[TN], nbi[TN];

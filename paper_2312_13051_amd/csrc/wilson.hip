@@ -808,8 +808,8 @@ __global__ void k_spin_scale(const double2 *U, int ldu, int64_t us, const double
 }
 
 // Projected-spin eigenvalues: copy into the output, count negatives, flag gaps.
-__global__ void k_pso_post(const double *ev, int m, int64_t n_k, int64_t k_per_sys, double *pso, int32_t *cnt,
-                           uint32_t *status) {
+__global__ void k_pso_post(const double *ev, const uint32_t *eig_st, int m, int64_t n_k, int64_t k_per_sys, double *pso,
+                           int32_t *cnt, uint32_t *status) {
   int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n_k) return;
   int c = 0;
@@ -822,6 +822,9 @@ __global__ void k_pso_post(const double *ev, int m, int64_t n_k, int64_t k_per_s
   }
   cnt[k] = c;
   if (!(mn >= 1e-6)) atomicOr(&status[k / k_per_sys], BE_ST_PSO_GAP);
+  // the projected-spin eigensolver's own conditions (its gap bits do not apply)
+  const uint32_t es = eig_st[k] & (BE_ST_NONCONVERGED | BE_ST_NAN_INF);
+  if (es) atomicOr(&status[k / k_per_sys], es);
 }
 
 __global__ void k_pso_sys(const int32_t *cnt, int n_sys, int64_t k_per_sys, int32_t *m_dn, uint32_t *status) {
@@ -911,8 +914,8 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   }
   // ---- eigh of the m x m projected spin operator (all bands)
   BE_RET_IF(eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream));
-  hipLaunchKernelGGL(k_pso_post, dim3(static_cast<uint32_t>((n_k + 255) / 256)), dim3(256), 0, stream, ev, m, n_k, kps,
-                     pso_evals, cnt, status);
+  hipLaunchKernelGGL(k_pso_post, dim3(static_cast<uint32_t>((n_k + 255) / 256)), dim3(256), 0, stream, ev, kst, m, n_k,
+                     kps, pso_evals, cnt, status);
   hipLaunchKernelGGL(k_pso_sys, dim3((n_sys + 63) / 64), dim3(64), 0, stream, cnt, n_sys, kps, mdn, status);
   BE_RET_IF(check_launch(ctx, "pso"));
   int32_t *hm = static_cast<int32_t *>(ctx->pinned);

@@ -115,19 +115,20 @@ def wsurf(ctx, hoplists: Sequence, kappa_grid, lo, hi, mode=L.BE_OVL_POLAR, prec
     return out
 
 
-def wnwl(ctx, hoplists: Sequence, kappa_grid, lo, hi, window=(0.0, 0.5), mode=L.BE_OVL_POLAR):
+def wnwl(ctx, hoplists: Sequence, kappa_grid, lo, hi, window=(0.0, 0.5), mode=L.BE_OVL_POLAR, precision=L.BE_FP64):
     """Nested Wilson loop over a plane (paper's WNWL)."""
     plan = ctx.hk_plan(list(hoplists))
-    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi)
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision)
     out = nested(ctx, g, window, mode)
     out["eig"] = g
     return out
 
 
-def wspinsurf(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, mode=L.BE_OVL_POLAR):
+def wspinsurf(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, mode=L.BE_OVL_POLAR, precision=L.BE_FP64,
+              chunk: int = 4096):
     """Spin-resolved WCCs over a plane (paper's WSpinSurf)."""
     plan = ctx.hk_plan(list(hoplists))
-    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi)
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision, chunk)
     out = spin(ctx, g, spin_diag, mode)
     out["eig"] = g
     return out

@@ -52,7 +52,8 @@ def check(Hs, lo, hi, ev, U, st, expect_status=0):
             P = Uq @ Uq.conj().T
             Pref = V[:, lo:hi] @ V[:, lo:hi].conj().T
             assert np.max(np.abs(P - Pref)) < 1e-10, (q, np.max(np.abs(P - Pref)))
-            assert np.max(np.abs(H @ Uq - Uq @ np.diag(ev[q, 1:m + 1]))) < 1e-11 * nrm
+            # U spans an invariant subspace: H U = U (U^H H U) (gauge invariant)
+            assert np.max(np.abs(H @ Uq - Uq @ (Uq.conj().T @ H @ Uq))) < 1e-11 * nrm
         assert st[q] == expect_status, (q, st[q])
 
 
