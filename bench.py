@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere)")
     ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
+    ap.add_argument("--tune", action="append", default=[], metavar="KNOB=VALUE",
+                    help="set a library tuning knob (be_tune_set) before timing")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device copy of this size (calibrates rocprof byte counters)")
     args = ap.parse_args()
@@ -176,6 +178,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = L.Context(0)
+    tuning = {}
+    for kv in args.tune:
+        k, v = kv.split("=")
+        ctx.tune_set(k, int(v))
+        tuning[k] = int(v)
     plan = ctx.hk_plan(hls)
     kap = torch.from_numpy(np.ascontiguousarray(kg.reshape(-1, 3))).to(dev)
     spin = torch.from_numpy(np.stack([syn.bhz_spin_diag(h) for h in hls])).to(dev)
@@ -297,7 +304,7 @@ def main():
                                "realizations, 24x24 supercell k-grid, half filling, spin-resolved Wilson loop "
                                "(eig of P S_z P), " + ("mixed path: FP32 Householder reduction and "
                                "back-transformation on MFMA, FP64 elsewhere" if mixed else "FP64 path"),
-                   "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs},
+                   "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs, "tuning": tuning},
         "roofline": roof,
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),

@@ -141,9 +141,10 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
  * (its columns hold the Householder vectors afterwards).
  * Steps: blocked Householder reduction to real tridiagonal form (panel
  * kernel + MFMA rank-2k trailing updates), FP64 bisection for eigenvalues
- * [lo-1, hi], FP64 inverse iteration with re-orthogonalization inside
- * clusters for bands [lo, hi), back-transformation with compact-WY blocks on
- * MFMA, and (mixed path) FP64 Cholesky-QR re-orthonormalization.
+ * [lo-1, hi], FP64 inverse iteration for bands [lo, hi) (Cholesky QR inside
+ * clusters of eigenvalues equal within 64 eps ||T||), FP64 Newton-Schulz
+ * orthonormalization of the tridiagonal eigenvectors, back-transformation
+ * with compact-WY blocks on MFMA (FP32 on the mixed path).
  * Outputs:
  *   evals[q*(m+2) + 0]     eigenvalue lo-1 (NaN if lo == 0)
  *   evals[q*(m+2) + 1 + c] eigenvalue lo+c, c < m = hi-lo
@@ -151,8 +152,10 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
  *   U + q*u_stride: N x m eigenvectors (c128), leading dimension ldu >= N;
  *   status[q]: BE_ST_GAP_CLOSED if min gap at lo or hi < 1e-9 max(1, |lambda|max),
  *              BE_ST_NAN_INF, BE_ST_NONCONVERGED.
- * Eigenvectors are unique only up to a unitary inside degenerate sets; the
- * occupied projector U U^H is the gauge-invariant output. */
+ * Inside a cluster of (nearly) degenerate eigenvalues the columns are some
+ * orthonormal basis of the cluster's invariant subspace; the projector U U^H
+ * is the gauge-invariant output. Workspace: the context's, grown on demand;
+ * batches are processed in sub-batches of at most 4 GiB of it. */
 int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, int64_t mat_stride,
                     int32_t n_mat, int32_t band_lo, int32_t band_hi, int32_t precision, double *evals,
                     void *U, int32_t ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
@@ -213,6 +216,20 @@ int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, in
 int be_profile_enable(be_ctx *ctx, int on);
 int be_profile_query(be_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 int be_profile_names(be_ctx *ctx, char *buf, size_t len);
+
+/* Tuning knobs: algorithm variants with identical results up to rounding,
+ * chosen per context (by measurement). Unknown knob names and out-of-range
+ * values return BE_EINVAL. Knobs:
+ *   "hetrd_hemv_lower"  0: the panel kernel's H v reads the full trailing
+ *                       square; 1: it reads the lower block triangle and adds
+ *                       the conjugate-transposed products (half the bytes,
+ *                       cross-lane reductions instead). Default 0.
+ *   "hetrd_panel_threads" threads per matrix of the panel kernel: 256, 512
+ *                       or 1024 (default 512: two matrices per compute
+ *                       unit overlap one's serial reflector steps with the
+ *                       other's matrix-vector product). */
+int be_tune_set(be_ctx *ctx, const char *knob, int32_t value);
+int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value);
 
 /* Utility kernel exposed for tests: batched complex GEMM on MFMA,
  *   C_q = alpha op(A_q) op(B_q) + beta C_q,   op = 'N' (none) or 'C'

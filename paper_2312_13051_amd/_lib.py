@@ -28,7 +28,7 @@ EXPORTS = [
     "be_hk_plan_create", "be_hk_plan_destroy", "be_hk_plan_N",
     "be_build_hk", "be_eigh_batched", "be_wilson_loop", "be_nested_wilson",
     "be_spin_resolved_wilson", "be_zgemm_strided",
-    "be_profile_enable", "be_profile_query", "be_profile_names",
+    "be_profile_enable", "be_profile_query", "be_profile_names", "be_tune_set", "be_tune_get",
 ]
 
 
@@ -75,6 +75,8 @@ def load():
     lib.be_profile_enable.argtypes = [vp, C.c_int]
     lib.be_profile_query.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.be_profile_names.argtypes = [vp, C.c_char_p, C.c_size_t]
+    lib.be_tune_set.argtypes = [vp, C.c_char_p, i32]
+    lib.be_tune_get.argtypes = [vp, C.c_char_p, C.POINTER(i32)]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
             "be_last_error", "be_workspace_bytes", "be_hk_plan_N") else C.c_int
@@ -184,6 +186,14 @@ class Context:
                                                      _ptr(theta_up), _ptr(C_dn), _ptr(C_up), _ptr(C_s), m_dn,
                                                      _ptr(status), _stream()))
         return [int(x) for x in m_dn]
+
+    def tune_set(self, knob: str, value: int):
+        self._check(self.lib.be_tune_set(self.handle, knob.encode(), int(value)))
+
+    def tune_get(self, knob: str) -> int:
+        v = C.c_int32()
+        self._check(self.lib.be_tune_get(self.handle, knob.encode(), C.byref(v)))
+        return v.value
 
     def profile_enable(self, on=True):
         self._check(self.lib.be_profile_enable(self.handle, 1 if on else 0))

@@ -37,6 +37,9 @@ struct be_ctx {
   void *pinned = nullptr;  // small pinned host buffer for scalar read-backs
   std::string err;
   int n_cu = 256;
+  // tuning knobs (be_tune_set)
+  int tune_hemv_lower = 0;       // panel H v over the lower block triangle (1) or the full square (0)
+  int tune_panel_threads = 512;   // threads per matrix of the Householder panel kernel
 };
 
 namespace be {

@@ -10,7 +10,7 @@
 //    once per panel by a rank-2nb MFMA GEMM, C -= [V W] [W V]^H. The panel's
 //    compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the fly from
 //    the same dot products.
-// 2. FP64 tridiagonal eigensolver (tridiag_eig): bisection with Sturm counts,
+// 2. FP64 tridiagonal eigensolver (tri_bisect, tri_invit, tri_gs): bisection with Sturm counts,
 //    one lane per eigenvalue, for the selected indices and their neighbours;
 //    T is split where an off-diagonal is negligible (an eigenvalue of
 //    multiplicity k forces k-1 such splits), and the k lanes of a k-fold
@@ -34,7 +34,6 @@ namespace {
 
 constexpr int NB = 32;   // panel width
 constexpr int PT = 256;   // threads of the tridiagonal and small kernels
-constexpr int PP = 1024;  // threads of the panel kernel (one matrix per CU)
 
 template <typename T>
 struct CT;
@@ -85,12 +84,37 @@ __device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
   __syncthreads();
 }
 
+// Column sums of a wave's register tile. Each lane holds K values x[0..K-1]
+// (K a power of two, at most 64); on return the lane holds the sum over all 64
+// lanes of x[k] with k = (lane >> (6 - log2 K)) & (K - 1). Each halving step
+// exchanges half of the remaining values with the partner lane at distance o
+// and keeps the half selected by that bit of the lane index, so K values cost
+// K - 1 exchanges instead of 6 K for separate reductions.
+template <typename T, int LOGK>
+__device__ __forceinline__ T transpose_reduce(T (&x)[1 << LOGK], int lane) {
+#pragma unroll
+  for (int s = 0; s < LOGK; ++s) {
+    const int o = 32 >> s, half = (1 << LOGK) >> (s + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const T keep = up ? x[i + half] : x[i];
+      const T send = up ? x[i] : x[i + half];
+      x[i] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  T v = x[0];
+#pragma unroll
+  for (int o = 32 >> LOGK; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // ---------------------------------------------------------------- panel kernel
 // A: matrices (full Hermitian storage), VW: [V | W | V] panel buffers (N x 3NB,
 // leading dimension N), Tm: per-matrix NB x NB compact-WY factor of each
 // panel, d/e: FP64 tridiagonal output.
-template <typename T>
-__global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
+template <typename T, bool LOWER, int NT>
+__global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
                                                   typename CT<T>::c *VW, int64_t sVW, typename CT<T>::c *Tm,
                                                   int64_t sTm, double *d, double *e, int64_t sDE, uint32_t *status) {
   typedef typename CT<T>::c C;
@@ -102,8 +126,10 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
   C *st1 = sWr + NB;                        // W^H v (NB)
   C *st2 = st1 + NB;                        // V^H v (NB)
   C *sT = st2 + NB;                         // NB x NB, column-major
-  C *spart = sT + NB * NB;                  // per-lane partial sums of H v (PP)
-  T *red = reinterpret_cast<T *>(spart + PP);  // 2 * waves
+  C *spart = sT + NB * NB;                  // per-lane partial sums of H v (NT)
+  C *szp = spart + NT;                      // lower-triangle H v: per-wave column sums (NT / 2)
+  T *red = reinterpret_cast<T *>(szp + NT / 2);  // 2 * waves
+  __shared__ int s_ry[NT / 64], s_rz[NT / 64];
   __shared__ C s_tau, s_scal;
   __shared__ T s_beta;
 
@@ -112,20 +138,20 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
   C *V = VW + q * sVW;
   C *W = V + int64_t(NB) * N;
   C *V2 = W + int64_t(NB) * N;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PP / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NT / 64;
 
-  for (int e2 = tid; e2 < NB * NB; e2 += PP) sT[e2] = mk<C>(0, 0);
+  for (int e2 = tid; e2 < NB * NB; e2 += NT) sT[e2] = mk<C>(0, 0);
   __syncthreads();
 
   for (int jj = 0; jj < nbp; ++jj) {
     const int j = p0 + jj;
     // ---- (1) apply the panel's earlier reflectors to column j
-    for (int c = tid; c < jj; c += PP) {
+    for (int c = tid; c < jj; c += NT) {
       sVr[c] = V[j + int64_t(c) * N];
       sWr[c] = W[j + int64_t(c) * N];
     }
     __syncthreads();
-    for (int r = j + tid; r < N; r += PP) {
+    for (int r = j + tid; r < N; r += NT) {
       C a = Aq[r + int64_t(j) * lda];
       T ar = a.x, ai = a.y;
       for (int c = 0; c < jj; ++c) {
@@ -144,7 +170,7 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
     __syncthreads();
     if (j == N - 1) {
       // last column: no reflector. Column j of V and W is zero.
-      for (int r = tid; r < N; r += PP) {
+      for (int r = tid; r < N; r += NT) {
         Aq[r + int64_t(j) * lda] = mk<C>(0, 0);
         V[r + int64_t(jj) * N] = mk<C>(0, 0);
         W[r + int64_t(jj) * N] = mk<C>(0, 0);
@@ -155,7 +181,7 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
     }
     // ---- (2) reflector from A(j+1:N, j)
     T xn = 0, dummy = 0;
-    for (int r = j + 2 + tid; r < N; r += PP) {
+    for (int r = j + 2 + tid; r < N; r += NT) {
       C a = Aq[r + int64_t(j) * lda];
       xn += a.x * a.x + a.y * a.y;
     }
@@ -185,7 +211,7 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
     __syncthreads();
     const C tau = s_tau, scal = s_scal;
     // v: zero above j+1, one at j+1, scaled x below; into LDS, A's column j, V and V2
-    for (int r = tid; r < N; r += PP) {
+    for (int r = tid; r < N; r += NT) {
       C v;
       if (r <= j) {
         v = mk<C>(0, 0);
@@ -240,7 +266,83 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
         yi += a.x * v.y + a.y * v.x;
       }
     };
-    if (ncs == 1) {
+    if (LOWER && nrb >= 4) {
+      // Lower-triangle variant: items are (64-row block rb, 32-column half of
+      // column block cb <= rb). An item adds A(rows, cols) v(cols) to y(rows)
+      // and, below the diagonal block, A(rows, cols)^H v(rows) to y(cols)
+      // (A is Hermitian), so only the lower block triangle is read. One item
+      // per wave and round; partial sums go to per-wave LDS slots and are
+      // combined in wave order, so the result does not depend on scheduling.
+      constexpr int UN = 64 / sizeof(C);  // 64 bytes of loads per lane and step
+      static_assert(UN == 4 || UN == 8, "one 64-byte load group per lane");
+      constexpr int LOGK = UN == 8 ? 3 : 2;  // log2 UN
+      const int n_items = nrb * (nrb + 1);  // two halves per block
+      for (int t0 = 0; t0 < n_items; t0 += nw) {
+        const int t = t0 + wave;
+        T yr = 0, yi = 0;
+        int ry = -1, rz = -1;
+        if (t < n_items) {
+          const int tile = t >> 1, hf = t & 1;
+          int rb = int((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+          while (rb * (rb + 1) / 2 > tile) --rb;
+          while ((rb + 1) * (rb + 2) / 2 <= tile) ++rb;
+          const int cb = tile - rb * (rb + 1) / 2;
+          ry = r0 + rb * 64;
+          const int c0 = r0 + cb * 64 + hf * 32, c1 = min(N, c0 + 32);
+          const bool diag = rb == cb;
+          if (!diag) rz = c0;
+          const int R = ry + lane;
+          const bool rok = R < N;
+          const C vR = rok ? sv[R] : mk<C>(0, 0);
+          const C *row = Aq + (rok ? R : r0);
+          for (int c = c0; c < c1; c += UN) {
+            C a[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) a[u] = (rok && c + u < c1) ? row[int64_t(c + u) * lda] : mk<C>(0, 0);
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+              const C v = sv[min(c + u, N - 1)];
+              yr += a[u].x * v.x - a[u].y * v.y;
+              yi += a[u].x * v.y + a[u].y * v.x;
+            }
+            if (!diag) {
+              T x[2 * UN];
+#pragma unroll
+              for (int u = 0; u < UN; ++u) {
+                x[u] = a[u].x * vR.x + a[u].y * vR.y;       // Re conj(a) v(R)
+                x[u + UN] = a[u].x * vR.y - a[u].y * vR.x;  // Im conj(a) v(R)
+              }
+              const T z = transpose_reduce<T, LOGK + 1>(x, lane);
+              const int k = (lane >> (5 - LOGK)) & (2 * UN - 1);
+              if ((lane & ((1 << (5 - LOGK)) - 1)) == 0 && c + (k % UN) < c1)
+                reinterpret_cast<T *>(szp)[wave * 64 + 2 * (c - c0 + (k % UN)) + (k >= UN)] = z;
+            }
+          }
+        }
+        spart[tid] = mk<C>(yr, yi);
+        if (lane == 0) {
+          s_ry[wave] = ry;
+          s_rz[wave] = rz;
+        }
+        __syncthreads();
+        for (int r = r0 + tid; r < N; r += NT) {
+          C acc = t0 == 0 ? mk<C>(0, 0) : sy[r];
+          for (int w = 0; w < nw; ++w) {
+            const int dy = r - s_ry[w], dz = r - s_rz[w];
+            if (s_ry[w] >= 0 && dy >= 0 && dy < 64) {
+              acc.x += spart[w * 64 + dy].x;
+              acc.y += spart[w * 64 + dy].y;
+            }
+            if (s_rz[w] >= 0 && dz >= 0 && dz < 32) {
+              acc.x += szp[w * 32 + dz].x;
+              acc.y += szp[w * 32 + dz].y;
+            }
+          }
+          sy[r] = acc;
+        }
+        __syncthreads();
+      }
+    } else if (ncs == 1) {
       for (int rb = wave; rb < nrb; rb += nw) {
         T yr, yi;
         slice_dot(rb, 0, yr, yi);
@@ -252,7 +354,7 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
       if (wave < nrb * ncs) slice_dot(wave % nrb, wave / nrb, yr, yi);
       spart[tid] = mk<C>(yr, yi);
       __syncthreads();
-      for (int r = r0 + tid; r < N; r += PP) {
+      for (int r = r0 + tid; r < N; r += NT) {
         const int rb = (r - r0) >> 6, l = (r - r0) & 63;
         T sr = 0, si = 0;
         for (int cs = 0; cs < ncs; ++cs) {
@@ -284,7 +386,7 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
     }
     __syncthreads();
     // y -= V t1 + W t2
-    for (int r = r0 + tid; r < N; r += PP) {
+    for (int r = r0 + tid; r < N; r += NT) {
       C y = sy[r];
       T yr = y.x, yi = y.y;
       for (int c = 0; c < jj; ++c) {
@@ -310,14 +412,14 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
     __syncthreads();
     // ---- (5) w += alpha v with alpha = -1/2 tau (w^H v)
     T dr = 0, di = 0;
-    for (int r = r0 + tid; r < N; r += PP) {
+    for (int r = r0 + tid; r < N; r += NT) {
       C w = sy[r], v = sv[r];
       dr += w.x * v.x + w.y * v.y;
       di += w.x * v.y - w.y * v.x;
     }
     block_sum2(dr, di, red);
     const T alr = T(-0.5) * (tau.x * dr - tau.y * di), ali = T(-0.5) * (tau.x * di + tau.y * dr);
-    for (int r = tid; r < N; r += PP) {
+    for (int r = tid; r < N; r += NT) {
       C w;
       if (r < r0) {
         w = mk<C>(0, 0);
@@ -331,7 +433,7 @@ __global__ __launch_bounds__(PP) void hetrd_panel(typename CT<T>::c *A, int64_t 
   }
   // ---- write the panel's T factor
   C *Tq = Tm + q * sTm;
-  for (int e2 = tid; e2 < NB * NB; e2 += PP) Tq[e2] = sT[e2];
+  for (int e2 = tid; e2 < NB * NB; e2 += NT) Tq[e2] = sT[e2];
   (void)status;
 }
 
@@ -358,40 +460,51 @@ __device__ __forceinline__ double hash_unit(uint64_t a, uint64_t b) {
   return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// Zs layout per matrix: 4 arrays [N][mp] (U0, U1, U2, x), lane index fastest.
-__global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double *e, int64_t sDE, int N, int lo, int hi,
-                                                  double *evals, double *Zs, int64_t sZ, int mp, double2 *U, int ldu,
-                                                  int64_t sU, uint32_t *status) {
-  extern __shared__ double tsm[];
-  double *sd = tsm;          // N
-  double *se = sd + N;       // N
-  double *se2 = se + N;      // N
-  double *slam = se2 + N;    // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
-  const int m = hi - lo;
-  int *sblk = reinterpret_cast<int *>(slam + m + 4);  // block starts (N + 1)
-  int *smark = sblk + N + 1;                           // clusters needing Gram-Schmidt (m)
-  __shared__ double red[2 * (PT / 64)];
-  __shared__ int s_bad, s_nblk;
+// Per-matrix scratch of the tridiagonal solver: lam [m + 1] = (||T||, selected
+// eigenvalues), Zs: 4 arrays [N][mp] (U0, U1, U2, x) with the eigenvector
+// index fastest, marks [m] (1 at the first index of a cluster whose vectors
+// share a block of T).
 
-  const int64_t q = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
-  if (tid == 0) s_bad = 0;
+// Loads d, e of matrix q into LDS; returns false (and flags the matrix, with
+// NaN outputs) if an entry is not finite.
+__device__ bool load_tridiag(const double *d, const double *e, int64_t q, int64_t sDE, int N, double *sd, double *se,
+                             double *se2, int *s_bad) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *s_bad = 0;
   __syncthreads();
-  for (int i = tid; i < N; i += PT) {
-    double di = d[q * sDE + i];
-    double ei = i < N - 1 ? e[q * sDE + i] : 0.0;
-    if (!isfinite(di) || !isfinite(ei)) s_bad = 1;
+  for (int i = tid; i < N; i += blockDim.x) {
+    const double di = d[q * sDE + i];
+    const double ei = i < N - 1 ? e[q * sDE + i] : 0.0;
+    if (!isfinite(di) || !isfinite(ei)) *s_bad = 1;
     sd[i] = di;
-    se[i] = ei;
+    if (se) se[i] = ei;
     se2[i] = ei * ei;
   }
   __syncthreads();
-  uint32_t st = 0;
-  if (s_bad) {
+  return *s_bad == 0;
+}
+
+// (a4) eigenvalues by bisection with Sturm counts, one lane per wanted index:
+// the selected [lo, hi), their neighbours lo-1 and hi (for the gap test) and
+// the extremes 0 and N-1 (for the scale).
+__global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *e, int64_t sDE, int N, int lo, int hi,
+                                                 double *evals, double *lamg, double2 *U, int ldu, int64_t sU,
+                                                 uint32_t *status) {
+  extern __shared__ double tsm[];
+  double *sd = tsm;          // N
+  double *se2 = sd + N;      // N
+  double *slam = se2 + N;    // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
+  const int m = hi - lo;
+  __shared__ int s_bad;
+  __shared__ double mm[3 * (PT / 64)];
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
+  if (!load_tridiag(d, e, q, sDE, N, sd, nullptr, se2, &s_bad)) {
     if (tid == 0) status[q] |= BE_ST_NAN_INF;
     for (int c = tid; c < m + 2; c += PT) evals[q * (m + 2) + c] = NAN;
+    for (int c = tid; c <= m; c += PT) lamg[q * (m + 1) + c] = NAN;
     for (int64_t k = tid; k < int64_t(N) * m; k += PT) {
-      int c = int(k / N), r = int(k % N);
+      const int c = int(k / N), r = int(k % N);
       U[q * sU + r + int64_t(c) * ldu] = make_double2(NAN, NAN);
     }
     return;
@@ -399,41 +512,35 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
   // Gershgorin interval and pivot threshold
   double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
   for (int i = tid; i < N; i += PT) {
-    double rad = fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
+    const double rad = sqrt(se2[i]) + (i > 0 ? sqrt(se2[i - 1]) : 0.0);
     gl = fmin(gl, sd[i] - rad);
     gu = fmax(gu, sd[i] + rad);
     emax2 = fmax(emax2, se2[i]);
   }
-  {
-    // min/max reductions via negation trick in block_sum-like code
-    for (int o = 32; o > 0; o >>= 1) {
-      gl = fmin(gl, __shfl_xor(gl, o, 64));
-      gu = fmax(gu, __shfl_xor(gu, o, 64));
-      emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
-    }
-    __shared__ double mm[3 * (PT / 64)];
-    if (lane == 0) {
-      mm[3 * wave] = gl;
-      mm[3 * wave + 1] = gu;
-      mm[3 * wave + 2] = emax2;
-    }
-    __syncthreads();
-    gl = mm[0];
-    gu = mm[1];
-    emax2 = mm[2];
-    for (int w = 1; w < nw; ++w) {
-      gl = fmin(gl, mm[3 * w]);
-      gu = fmax(gu, mm[3 * w + 1]);
-      emax2 = fmax(emax2, mm[3 * w + 2]);
-    }
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+  }
+  if (lane == 0) {
+    mm[3 * wave] = gl;
+    mm[3 * wave + 1] = gu;
+    mm[3 * wave + 2] = emax2;
+  }
+  __syncthreads();
+  gl = mm[0];
+  gu = mm[1];
+  emax2 = mm[2];
+  for (int w = 1; w < nw; ++w) {
+    gl = fmin(gl, mm[3 * w]);
+    gu = fmax(gu, mm[3 * w + 1]);
+    emax2 = fmax(emax2, mm[3 * w + 2]);
   }
   const double tnorm = fmax(fabs(gl), fabs(gu));
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   const double eps = DBL_EPSILON;
   gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm + 2.0 * pivmin;
-  // ---- bisection for the wanted indices
   const int nidx = m + 4;
   for (int t = tid; t < nidx; t += PT) {
     int k;
@@ -446,7 +553,7 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
     if (k >= 0) {
       double a = gl, b = gu;
       for (int it = 0; it < 128; ++it) {
-        double mid = 0.5 * (a + b);
+        const double mid = 0.5 * (a + b);
         if (b - a <= 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin || mid <= a || mid >= b) break;
         if (sturm_count(sd, se2, N, mid, pivmin) > k) b = mid;
         else a = mid;
@@ -457,23 +564,54 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
   }
   __syncthreads();
   const double *lam = slam + 4;
-  for (int c = tid; c < m + 2; c += PT) {
-    double v;
-    if (c == 0) v = slam[2];
-    else if (c == m + 1) v = slam[3];
-    else v = lam[c - 1];
-    evals[q * (m + 2) + c] = v;
-  }
+  for (int c = tid; c < m + 2; c += PT) evals[q * (m + 2) + c] = c == 0 ? slam[2] : (c == m + 1 ? slam[3] : lam[c - 1]);
+  for (int c = tid; c <= m; c += PT) lamg[q * (m + 1) + c] = c == 0 ? tnorm : lam[c - 1];
   if (tid == 0) {
-    double scale = fmax(1.0, fmax(fabs(slam[0]), fabs(slam[1])));
+    const double scale = fmax(1.0, fmax(fabs(slam[0]), fabs(slam[1])));
     double g = INFINITY;
     if (lo > 0 && m > 0) g = fmin(g, lam[0] - slam[2]);
     if (hi < N && m > 0) g = fmin(g, slam[3] - lam[m - 1]);
-    if (g < 1e-9 * scale) st |= BE_ST_GAP_CLOSED;
+    if (g < 1e-9 * scale) status[q] |= BE_ST_GAP_CLOSED;
   }
-  // ---- split T where an off-diagonal is negligible; blocks [sblk[b], sblk[b+1])
-  const double splittol = 16.0 * eps * tnorm;
+}
+
+// Tolerances relative to eps ||T||: split < block window < cluster gap, so a
+// cluster's window never reaches the next cluster.
+__device__ __forceinline__ double tol_split(double tnorm) { return 16.0 * DBL_EPSILON * tnorm; }
+__device__ __forceinline__ double tol_window(double tnorm) { return 32.0 * DBL_EPSILON * tnorm; }
+__device__ __forceinline__ double tol_cluster(double tnorm) { return 64.0 * DBL_EPSILON * tnorm; }
+
+// (a4) eigenvectors by inverse iteration, one lane per eigenvector. T is
+// split where an off-diagonal is negligible; the k lanes of a k-fold
+// eigenvalue (equal within the cluster tolerance) take k distinct blocks that
+// hold it, so their vectors have disjoint supports; clusters whose lanes must
+// share a block are marked for Gram-Schmidt (tri_gs).
+__global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e, int64_t sDE, int N, int m,
+                                                const double *lamg, double *Zs, int64_t sZ, int mp, int *marks,
+                                                uint32_t *status) {
+  extern __shared__ double tsm[];
+  double *sd = tsm;        // N
+  double *se = sd + N;     // N
+  double *se2 = se + N;    // N
+  double *lam = se2 + N;   // m
+  int *sblk = reinterpret_cast<int *>(lam + m);  // block starts (N + 1)
+  int *smark = sblk + N + 1;                     // m
+  __shared__ int s_bad, s_nblk;
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (status[q] & BE_ST_NAN_INF) return;
+  if (!load_tridiag(d, e, q, sDE, N, sd, se, se2, &s_bad)) return;
+  for (int c = tid; c < m; c += PT) {
+    lam[c] = lamg[q * (m + 1) + 1 + c];
+    smark[c] = 0;
+  }
+  const double tnorm = lamg[q * (m + 1)];
+  const double eps = DBL_EPSILON;
+  double emax2 = 0.0;
+  for (int i = 0; i < N; ++i) emax2 = fmax(emax2, se2[i]);
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
   if (tid == 0) {
+    const double splittol = tol_split(tnorm);
     int nb = 0;
     sblk[nb++] = 0;
     for (int i = 1; i < N; ++i)
@@ -481,24 +619,16 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
     sblk[nb] = N;
     s_nblk = nb;
   }
-  for (int c = tid; c < m; c += PT) smark[c] = 0;
   __syncthreads();
   const int nblk = s_nblk;
-  // ---- inverse iteration, one lane per eigenvector. The k lanes of a
-  // k-fold eigenvalue (equal within dclu) take k distinct blocks that hold
-  // it, so their vectors have disjoint supports; lanes that must share a
-  // block are orthogonalized below.
   double *Z0 = Zs + q * sZ;
   double *Z1 = Z0 + int64_t(N) * mp;
   double *Z2 = Z1 + int64_t(N) * mp;
   double *X = Z2 + int64_t(N) * mp;
   const double tiny = eps * fmax(tnorm, DBL_MIN);
-  // tolerances: split (above) < block window < cluster gap, so a cluster's
-  // window never reaches the next cluster
-  const double dblk = 32.0 * eps * tnorm, dclu = 64.0 * eps * tnorm;
+  const double dblk = tol_window(tnorm), dclu = tol_cluster(tnorm);
   bool lane_bad = false;
   for (int c = tid; c < m; c += PT) {
-    const double lm = lam[c];
     int c0 = c, c1 = c + 1;
     while (c0 > 0 && lam[c0] - lam[c0 - 1] <= dclu) --c0;
     while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
@@ -519,6 +649,12 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
       cnt += nb;
     }
     if (!found || shared) smark[c0] = 1;
+    // Lanes that share a block with other members of their cluster take
+    // shifts a few eps ||T|| apart: far larger than the splitting of a
+    // degenerate pair (so neither member dominates a lane's solve and each
+    // lane returns an independent combination of the cluster's vectors),
+    // far smaller than the distance to the next cluster.
+    const double lm = (!found || shared) ? lam[c] + (jr - 0.5 * (c1 - c0 - 1)) * 2.0 * eps * tnorm : lam[c];
     for (int i = 0; i < N; ++i)
       if (i < bs || i >= bt) X[int64_t(i) * mp + c] = 0.0;
     for (int it = 0; it < 3; ++it) {
@@ -563,52 +699,250 @@ __global__ __launch_bounds__(PT) void tridiag_eig(const double *d, const double 
       double x1 = 0.0, x2 = 0.0, nrm = 0.0;
       for (int i = bt - 1; i >= bs; --i) {
         const int64_t o = int64_t(i) * mp + c;
-        double xi = (X[o] - Z1[o] * x1 - Z2[o] * x2) / Z0[o];
+        const double xi = (X[o] - Z1[o] * x1 - Z2[o] * x2) / Z0[o];
         X[o] = xi;
         x2 = x1;
         x1 = xi;
         nrm = fma(xi, xi, nrm);
       }
-      double inv = 1.0 / sqrt(nrm);
+      const double inv = 1.0 / sqrt(nrm);
       if (!isfinite(inv) || inv == 0.0) lane_bad = true;
       for (int i = bs; i < bt; ++i) X[int64_t(i) * mp + c] *= inv;
     }
   }
-  if (lane_bad) st |= BE_ST_NONCONVERGED;
   __syncthreads();
-  // ---- clusters whose members share a block: modified Gram-Schmidt (two
-  // passes), one wave per cluster
-  for (int c0 = wave; c0 < m; c0 += nw) {
-    if (!smark[c0]) continue;
-    int c1 = c0 + 1;
-    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int t = c0; t < c1; ++t) {
-        for (int s = c0; s < t; ++s) {
-          double dt = 0.0;
-          for (int i = lane; i < N; i += 64) dt = fma(X[int64_t(i) * mp + s], X[int64_t(i) * mp + t], dt);
-          dt = wave_sum(dt);
-          for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] -= dt * X[int64_t(i) * mp + s];
+  for (int c = tid; c < m; c += PT) marks[q * m + c] = smark[c];
+  if (lane_bad) atomicOr(&status[q], uint32_t(BE_ST_NONCONVERGED));
+}
+
+// Clusters whose members share a block of T are orthonormalized by two
+// passes of Cholesky QR (G = V^T V = R^T R, V <- V R^-1), done in lanes: the
+// marked clusters are packed into 64-lane bins (no cluster straddles a bin),
+// a bin is one wave, vector c sits on one lane, and the rows of X are swept
+// with coalesced loads (the eigenvector index is the fastest dimension of X).
+// A Gram sweep reads the other members of a lane's cluster by cross-lane
+// permutes; the first member of each cluster factors G in LDS; an apply sweep
+// solves y R = x row by row, the members finalizing y in order and passing it
+// on by permutes. Clusters larger than GK run the same passes with the whole
+// workgroup; a breakdown of the Cholesky factorization falls back to modified
+// Gram-Schmidt with one wave per cluster.
+constexpr int GK = 32;
+
+__host__ __device__ inline int gs_bins_max(int m) { return m / (64 - GK + 1) + 2; }
+
+size_t gs_smem(int m) {
+  return size_t(PT) * GK * sizeof(double) + (3 * size_t(gs_bins_max(m)) * 64 + size_t(std::max(m, 1))) * sizeof(int);
+}
+
+__global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, double *Zs, int64_t sZ, int mp,
+                                             const int *marks, double *Gm, const uint32_t *status) {
+  extern __shared__ double gsm[];
+  const int nbmax = gs_bins_max(m);
+  int *sv = reinterpret_cast<int *>(gsm + PT * GK);  // bin lane -> vector (-1: idle)
+  int *sb = sv + nbmax * 64;                         // bin lane -> lane of its cluster's first member
+  int *sk = sb + nbmax * 64;                         // bin lane -> cluster size
+  int *sfl = sk + nbmax * 64;                        // cluster start -> Cholesky breakdown
+  __shared__ int s_nbins;
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
+  if (status[q] & BE_ST_NAN_INF) return;
+  const double *lam = lamg + q * (m + 1) + 1;
+  const double dclu = tol_cluster(lamg[q * (m + 1)]);
+  double *X = Zs + q * sZ + int64_t(3) * N * mp;
+  const int *mk_q = marks + q * m;
+  for (int c = tid; c < m; c += PT) sfl[c] = 0;
+  if (tid == 0) {
+    int nb = 0, fill = 0;
+    for (int c0 = 0; c0 < m;) {
+      int c1 = c0 + 1;
+      while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+      const int k = c1 - c0;
+      if (mk_q[c0] && k > 1 && k <= GK) {
+        if (fill + k > 64) {
+          for (int l = fill; l < 64; ++l) sv[nb * 64 + l] = -1;
+          ++nb;
+          fill = 0;
         }
-        double nr = 0.0;
-        for (int i = lane; i < N; i += 64) {
-          double v = X[int64_t(i) * mp + t];
-          nr = fma(v, v, nr);
+        for (int t = 0; t < k; ++t) {
+          sv[nb * 64 + fill + t] = c0 + t;
+          sb[nb * 64 + fill + t] = fill;
+          sk[nb * 64 + fill + t] = k;
         }
-        nr = wave_sum(nr);
-        const double inv = 1.0 / sqrt(nr);
-        for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] *= inv;
+        fill += k;
       }
+      c0 = c1;
+    }
+    if (fill > 0) {
+      for (int l = fill; l < 64; ++l) sv[nb * 64 + l] = -1;
+      ++nb;
+    }
+    s_nbins = nb;
+  }
+  __syncthreads();
+  const int nbins = s_nbins;
+  double *G = gsm + wave * 64 * GK;  // this wave's Gram rows, G[lane][t]
+  for (int j0 = 0; j0 < nbins; j0 += nw) {
+    const int j = j0 + wave;
+    const int c = j < nbins ? sv[j * 64 + lane] : -1;
+    const bool act = c >= 0;
+    const int b = act ? sb[j * 64 + lane] : lane;
+    const int k = act ? sk[j * 64 + lane] : 1;
+    const int rel = lane - b;
+    int kmax = k;
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    for (int pass = 0; pass < 2; ++pass) {
+      // Gram sweep: g[t] = <x_c, x_{b+t}>
+      double g[GK];
+#pragma unroll
+      for (int t = 0; t < GK; ++t) g[t] = 0.0;
+      for (int i = 0; i < N; ++i) {
+        const double x = act ? X[int64_t(i) * mp + c] : 0.0;
+#pragma unroll
+        for (int t = 0; t < GK; ++t)
+          if (t < kmax) g[t] = fma(x, __shfl(x, min(63, b + t), 64), g[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < GK; ++t) G[lane * GK + t] = g[t];
+      __syncthreads();
+      // Cholesky G = R^T R in place (upper triangle), by the cluster's first lane
+      if (act && rel == 0 && !sfl[c]) {
+        for (int jj = 0; jj < k; ++jj) {
+          double dg = G[(b + jj) * GK + jj];
+          const double g0 = dg;
+          for (int p = 0; p < jj; ++p) dg -= G[(b + p) * GK + jj] * G[(b + p) * GK + jj];
+          if (!(dg > 1e-12 * g0)) {
+            sfl[c] = 1;
+            break;
+          }
+          const double rjj = sqrt(dg);
+          G[(b + jj) * GK + jj] = rjj;
+          for (int t = jj + 1; t < k; ++t) {
+            double v = G[(b + jj) * GK + t];
+            for (int p = 0; p < jj; ++p) v -= G[(b + p) * GK + jj] * G[(b + p) * GK + t];
+            G[(b + jj) * GK + t] = v / rjj;
+          }
+        }
+      }
+      __syncthreads();
+      const bool ok = act && !sfl[c - rel];
+      // column rel of R: rcol[s] = R[s][rel] for s < rel; inverse of R[rel][rel]
+      double rcol[GK];
+#pragma unroll
+      for (int t = 0; t < GK; ++t) rcol[t] = (ok && t < rel) ? G[(b + t) * GK + rel] : 0.0;
+      const double rinv = ok ? 1.0 / G[lane * GK + rel] : 0.0;
+      // apply sweep: y R = x, row by row
+      for (int i = 0; i < N; ++i) {
+        const int64_t o = int64_t(i) * mp + (act ? c : 0);
+        const double x = act ? X[o] : 0.0;
+        double y = 0.0, acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < GK; ++t) {
+          if (t < kmax) {
+            if (rel == t) y = (x - acc) * rinv;
+            const double yt = __shfl(y, min(63, b + t), 64);
+            if (rel > t) acc = fma(yt, rcol[t], acc);
+          }
+        }
+        if (ok) X[o] = y;
+      }
+      __syncthreads();
     }
   }
-  // status: OR of lane flags
-  {
-    __shared__ unsigned int sst;
-    if (tid == 0) sst = 0;
-    __syncthreads();
-    if (st) atomicOr(&sst, st);
-    __syncthreads();
-    if (tid == 0) status[q] |= sst;
+  // clusters larger than GK: the same two Cholesky-QR passes by the whole
+  // workgroup. The Gram matrix is accumulated from LDS tiles of rows, the
+  // factorization runs one column per step in the matrix's m x m scratch
+  // (Gq, row-major k x k), and each thread solves y R = x for whole rows of
+  // the cluster, in place.
+  double *Gq = Gm + q * int64_t(m) * m;
+  double *tile = gsm;
+  for (int c0 = 0; c0 < m;) {
+    int c1 = c0 + 1;
+    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+    const int k = c1 - c0;
+    if (mk_q[c0] && k > GK) {
+      const int RB = (PT * GK) / k;  // rows per LDS tile
+      for (int pass = 0; pass < 2 && !sfl[c0]; ++pass) {
+        for (int e = tid; e < k * k; e += PT) Gq[e] = 0.0;
+        for (int i0 = 0; i0 < N; i0 += RB) {
+          const int nr = min(RB, N - i0);
+          __syncthreads();
+          for (int e = tid; e < nr * k; e += PT) {
+            const int r = e / k, col = e - r * k;
+            tile[e] = X[int64_t(i0 + r) * mp + c0 + col];
+          }
+          __syncthreads();
+          for (int e = tid; e < k * k; e += PT) {
+            const int s2 = e / k, t = e - s2 * k;
+            if (t < s2) continue;
+            double acc = 0.0;
+            for (int r = 0; r < nr; ++r) acc = fma(tile[r * k + s2], tile[r * k + t], acc);
+            Gq[e] += acc;
+          }
+        }
+        __syncthreads();
+        // right-looking Cholesky on the upper triangle
+        for (int j = 0; j < k; ++j) {
+          if (tid == 0) {
+            const double dg = Gq[j * k + j];
+            if (!(dg > 1e-12) || !isfinite(dg)) sfl[c0] = 1;  // columns enter with unit norm
+            Gq[j * k + j] = sqrt(fmax(dg, DBL_MIN));
+          }
+          __syncthreads();
+          if (sfl[c0]) break;
+          const double rjj = Gq[j * k + j];
+          for (int t = j + 1 + tid; t < k; t += PT) Gq[j * k + t] /= rjj;
+          __syncthreads();
+          const int nt = k - j - 1;
+          for (int e = tid; e < nt * nt; e += PT) {
+            const int s2 = j + 1 + e / nt, t = j + 1 + e % nt;
+            if (t >= s2) Gq[s2 * k + t] -= Gq[j * k + s2] * Gq[j * k + t];
+          }
+          __syncthreads();
+        }
+        if (sfl[c0]) break;
+        // X_c <- X_c R^-1, row by row
+        for (int i = tid; i < N; i += PT) {
+          double *xr = X + int64_t(i) * mp + c0;
+          for (int j = 0; j < k; ++j) {
+            double v = xr[j];
+            for (int p = 0; p < j; ++p) v = fma(-xr[p], Gq[p * k + j], v);
+            xr[j] = v / Gq[j * k + j];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    c0 = c1;
+  }
+  __syncthreads();
+  // clusters left to the fallback: a Cholesky breakdown
+  for (int c0 = 0, w = 0; c0 < m;) {
+    int c1 = c0 + 1;
+    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+    const int k = c1 - c0;
+    if (mk_q[c0] && k > 1 && sfl[c0]) {
+      if (w++ % nw == wave) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int t = c0; t < c1; ++t) {
+            for (int s2 = c0; s2 < t; ++s2) {
+              double dt = 0.0;
+              for (int i = lane; i < N; i += 64) dt = fma(X[int64_t(i) * mp + s2], X[int64_t(i) * mp + t], dt);
+              dt = wave_sum(dt);
+              for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] -= dt * X[int64_t(i) * mp + s2];
+            }
+            double nr = 0.0;
+            for (int i = lane; i < N; i += 64) {
+              const double v = X[int64_t(i) * mp + t];
+              nr = fma(v, v, nr);
+            }
+            nr = wave_sum(nr);
+            const double inv = 1.0 / sqrt(nr);
+            for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] *= inv;
+          }
+        }
+      }
+    }
+    c0 = c1;
   }
 }
 
@@ -675,8 +1009,8 @@ __global__ void zero_u32(uint32_t *p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-size_t panel_smem(int N, size_t csize) {
-  return (2 * size_t(N) + 4 * NB + NB * NB + PP) * csize + 2 * (PP / 64) * (csize / 2) + 64;
+size_t panel_smem(int N, size_t csize, int nt) {
+  return (2 * size_t(N) + 4 * NB + NB * NB + nt + nt / 2) * csize + 2 * (nt / 64) * (csize / 2) + 64;
 }
 
 }  // namespace
@@ -717,6 +1051,10 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   cv.add(&dd, size_t(nb_mat) * N);
   cv.add(&ee, size_t(nb_mat) * N);
   cv.add(&Zs, size_t(nb_mat) * 4 * N * mp);
+  double *lamg = nullptr;
+  int *marks = nullptr;
+  cv.add(&lamg, size_t(nb_mat) * (m + 1));
+  cv.add(&marks, size_t(nb_mat) * std::max(m, 1));
   double *Gm = nullptr, *oerr = nullptr;
   unsigned long long *gmax = nullptr;
   cv.add(&Gm, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
@@ -730,16 +1068,25 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   BE_RET_IF(check_launch(ctx, "zero_u32"));
   const int64_t sVW = int64_t(N) * 3 * NB;
   const int64_t sT = int64_t(P) * NB * NB;
-  const size_t psm = panel_smem(N, sizeof(C));
+  // panel kernel variant: H v over the full square or the lower block triangle,
+  // 256, 512 or 1024 threads per matrix
+  const int pnt = ctx->tune_panel_threads;
+  const size_t psm = panel_smem(N, sizeof(C), pnt);
+  void (*panel)(C *, int64_t, int, int, int, int, C *, int64_t, C *, int64_t, double *, double *, int64_t, uint32_t *);
+  if (ctx->tune_hemv_lower)
+    panel = pnt == 256 ? &hetrd_panel<T, true, 256> : pnt == 512 ? &hetrd_panel<T, true, 512> : &hetrd_panel<T, true, 1024>;
+  else
+    panel = pnt == 256 ? &hetrd_panel<T, false, 256>
+                       : pnt == 512 ? &hetrd_panel<T, false, 512> : &hetrd_panel<T, false, 1024>;
   if (psm > 65536)
-    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&hetrd_panel<T>),
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)));
   // ---- Householder reduction
   for (int p = 0; p < P; ++p) {
     const int p0 = p * NB, nbp = std::min(NB, N - p0);
     {
       ProfScope prof(ctx, "hetrd_panel", stream);
-      hipLaunchKernelGGL(hetrd_panel<T>, dim3(nb_mat), dim3(PP), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
+      hipLaunchKernelGGL(panel, dim3(nb_mat), dim3(pnt), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
                          Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
     }
     BE_RET_IF(check_launch(ctx, "hetrd_panel"));
@@ -767,18 +1114,38 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       BE_RET_IF(GemmOf<T>::run(ctx, g, stream));
     }
   }
-  // ---- tridiagonal eigenpairs
-  const size_t tsm = (3 * size_t(N) + m + 4) * sizeof(double) + (size_t(N) + 1 + m) * sizeof(int) + 64;
-  if (tsm > 65536)
-    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tridiag_eig),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(tsm)));
+  // ---- tridiagonal eigenpairs: bisection, inverse iteration, Gram-Schmidt of shared-block clusters
   {
-    ProfScope prof(ctx, "tridiag_eig", stream);
-    hipLaunchKernelGGL(tridiag_eig, dim3(nb_mat), dim3(PT), tsm, stream, dd, ee, int64_t(N), N, lo, hi, evals, Zs,
-                       int64_t(4) * N * mp, mp, U, ldu, us, status);
+    const size_t smb = (2 * size_t(N) + m + 4) * sizeof(double);
+    if (smb > 65536)
+      BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tri_bisect),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(smb)));
+    ProfScope prof(ctx, "tri_bisect", stream);
+    hipLaunchKernelGGL(tri_bisect, dim3(nb_mat), dim3(PT), smb, stream, dd, ee, int64_t(N), N, lo, hi, evals, lamg, U,
+                       ldu, us, status);
   }
-  BE_RET_IF(check_launch(ctx, "tridiag_eig"));
+  BE_RET_IF(check_launch(ctx, "tri_bisect"));
   if (m == 0) return BE_OK;
+  {
+    const size_t smi = (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + m) * sizeof(int);
+    if (smi > 65536)
+      BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tri_invit),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(smi)));
+    ProfScope prof(ctx, "tri_invit", stream);
+    hipLaunchKernelGGL(tri_invit, dim3(nb_mat), dim3(PT), smi, stream, dd, ee, int64_t(N), N, m, lamg, Zs,
+                       int64_t(4) * N * mp, mp, marks, status);
+  }
+  BE_RET_IF(check_launch(ctx, "tri_invit"));
+  {
+    const size_t smg = gs_smem(m);
+    if (smg > 65536)
+      BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tri_gs),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(smg)));
+    ProfScope prof(ctx, "tri_gs", stream);
+    hipLaunchKernelGGL(tri_gs, dim3(nb_mat), dim3(PT), smg, stream, N, m, lamg, Zs, int64_t(4) * N * mp, mp, marks, Gm,
+                       status);
+  }
+  BE_RET_IF(check_launch(ctx, "tri_gs"));
   // back-transformation target: the output itself (FP64) or an FP32 copy (mixed)
   C *Ut = mixed ? Uw : reinterpret_cast<C *>(U);
   const int ldt = mixed ? N : ldu;
@@ -922,8 +1289,9 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   const size_t cs = sizeof(typename CT<T>::c);
   const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1) +
                            size_t(N) * std::max(m, 1)) +
-                     sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1)) +
-                     11 * 256;
+                     sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) +
+                                       size_t(m) + 1) +
+                     sizeof(int) * size_t(std::max(m, 1)) + 13 * 256;
   const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);

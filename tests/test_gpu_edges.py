@@ -67,6 +67,11 @@ def test_argument_errors():
         c.wilson_loop(z, 4, 5, 4, 20, 1, 4, 4, 0, d, d, i, i)           # m > N
     with pytest.raises(BerryError):
         c.wilson_loop(z, 4, 2, 4, 8, 1, 0, 4, 0, d, d, i, i)            # n_par = 0
+    with pytest.raises(BerryError):
+        c.tune_set("no_such_knob", 1)
+    with pytest.raises(BerryError):
+        c.tune_set("hetrd_panel_threads", 300)
+    assert c.tune_get("hetrd_panel_threads") == 512 and c.tune_get("hetrd_hemv_lower") == 0
 
 
 def test_pso_gap_flag_with_zero_spin_operator():

@@ -143,3 +143,52 @@ def test_eigh_mixed_precision_bounds(name):
         P = U[q] @ U[q].conj().T
         assert np.max(np.abs(P - V[:, :m] @ V[:, :m].conj().T)) < 1e-4
         assert st[q] == 0
+
+
+@pytest.mark.parametrize("hemv_lower,threads", [(0, 1024), (1, 1024), (0, 512), (0, 256), (1, 256)])
+@pytest.mark.parametrize("N,lo,hi", [(257, 0, 128), (400, 7, 203), (463, 100, 300)])
+def test_eigh_panel_variants(N, lo, hi, hemv_lower, threads):
+    """The panel kernel's variants: H v over the full square or the lower
+    block triangle (taken for trailing matrices of more than three 64-row
+    blocks), 256 to 1024 threads per matrix."""
+    gu.need_gpu()
+    rng = np.random.default_rng([N, 7])
+    A = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
+    Hs = A + np.conj(np.swapaxes(A, 1, 2))
+    c = gu.ctx()
+    c.tune_set("hetrd_hemv_lower", hemv_lower)
+    c.tune_set("hetrd_panel_threads", threads)
+    assert c.tune_get("hetrd_hemv_lower") == hemv_lower and c.tune_get("hetrd_panel_threads") == threads
+    ev, U, st = run_eigh(c, Hs, lo, hi, ld_pad=1)
+    check(Hs, lo, hi, ev, U, st)
+    hl = syn.bhz_disordered(10, 2.0, [3, 2, 4])
+    Hm = np.stack([orc.bloch_hamiltonian(hl, k) for k in syn.kplane(2, 1).reshape(-1, 3)])
+    ev, U, st = run_eigh_mixed(c, Hm, 0, 200)
+    for q in range(Hm.shape[0]):
+        w = np.linalg.eigvalsh(Hm[q])
+        assert np.max(np.abs(ev[q, 1:201] - w[:200])) <= 2e-5 * max(1.0, np.abs(w).max())
+        assert np.max(np.abs(U[q].conj().T @ U[q] - np.eye(200))) < 1e-5
+        assert st[q] == 0
+
+
+@pytest.mark.parametrize("N,n_minus", [(200, 100), (96, 40)])
+def test_eigh_large_degenerate_clusters(N, n_minus):
+    """Eigenvalues exactly -1 and +1 with large multiplicities (the projected
+    spin operator of a spin-conserving model): clusters far larger than a
+    wave's lane group go through the workgroup-wide orthonormalization."""
+    gu.need_gpu()
+    rng = np.random.default_rng([N, n_minus])
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    lam = np.r_[-np.ones(n_minus), np.ones(N - n_minus)]
+    Hs = np.stack([(Q * lam) @ Q.conj().T for _ in range(2)])
+    Hs = 0.5 * (Hs + np.conj(np.swapaxes(Hs, 1, 2)))
+    c = gu.ctx()
+    ev, U, st = run_eigh(c, Hs, 0, N)
+    for q in range(2):
+        assert np.max(np.abs(ev[q, 1:N + 1] - lam)) < 1e-12
+        Uq = U[q]
+        assert np.max(np.abs(Uq.conj().T @ Uq - np.eye(N))) < 1e-12
+        Pm = Uq[:, :n_minus] @ Uq[:, :n_minus].conj().T
+        Pref = Q[:, :n_minus] @ Q[:, :n_minus].conj().T
+        assert np.max(np.abs(Pm - Pref)) < 1e-10
+        assert st[q] == 0
