@@ -98,13 +98,14 @@ def cpu_baseline(sample, workers):
 
 # ---------------------------------------------------------------- algorithmic work
 def hetrd_panel_bytes(N, n_mat, elem_bytes=16):
-    """Algorithmic HBM bytes of all panel launches: one read of the trailing
-    Hermitian matrix (16 B per c128 element, 8 B per c64) per reflector column."""
+    """Algorithmic HBM bytes of all panel launches of one eigensolver call: one
+    read of the trailing matrix (16 B per c128 element, 8 B per c64) per
+    reflector column, the full square as it is stored."""
     return n_mat * sum(elem_bytes * (N - j - 1) ** 2 for j in range(N - 1))
 
 
-def gemm_flops(name, N, m, n_mat):
-    """Algorithmic flops (8 per complex multiply-add) of a GEMM call site."""
+def eigh_gemm_flops(name, N, m, n_mat):
+    """Algorithmic flops (8 per complex multiply-add) of the eigensolver's GEMMs."""
     P = (N + NB - 1) // NB
     if name == "her2k":   # Hermitian rank-2nb update, one triangle
         return n_mat * sum(8.0 * (N - p * NB - NB) ** 2 * NB for p in range(P) if N - p * NB - NB > 0)
@@ -116,7 +117,44 @@ def gemm_flops(name, N, m, n_mat):
             if K > 0:
                 tot += 16.0 * K * nbp * m + 4.0 * nbp * nbp * m
         return n_mat * tot
-    return None
+    raise KeyError(name)
+
+
+def gemm_phase_flops(N, m, n_par, n_k_sys, m_dn):
+    """Algorithmic GEMM flops per call-site tag for one pass over the systems
+    (spin-resolved loop). m_dn: spin-down sector size per system."""
+    nk = n_k_sys * len(m_dn)
+    md = np.asarray(m_dn, dtype=np.float64)
+    mu = m - md
+    return {
+        "her2k": eigh_gemm_flops("her2k", N, m, nk),
+        "unmtr": eigh_gemm_flops("unmtr", N, m, nk),
+        "pso": 8.0 * m * m * N * nk,                       # U^H (S U)
+        "pso_her2k": eigh_gemm_flops("her2k", m, m, nk),   # eigensolver of P S P (order m, all bands)
+        "pso_unmtr": eigh_gemm_flops("unmtr", m, m, nk),
+        "spin_sector": 8.0 * N * m * m * nk,               # U [Q- Q+]
+        "overlap": float(np.sum(8.0 * N * (md ** 2 + mu ** 2))) * n_k_sys,
+        "chain": float(np.sum(8.0 * (md ** 3 + mu ** 3))) * (n_par - 1) / n_par * n_k_sys,
+    }
+
+
+def traffic_from_profile(path, source, precision):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    counter summary, if it was taken with the current kernel source."""
+    import hashlib
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("<!-- ") and ":" in line:
+            k, v = line[5:].rstrip(" ->").split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != sha or vals.get("precision") != precision:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def main():
@@ -127,8 +165,9 @@ def main():
     ap.add_argument("--chunk-systems", type=int, default=8)
     ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample size (transverse lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
+                    help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere; "
+                         "its phases are checked against the FP64 oracle at 1e-6 rad)")
     ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
     ap.add_argument("--tune", action="append", default=[], metavar="KNOB=VALUE",
                     help="set a library tuning knob (be_tune_set) before timing")
@@ -246,29 +285,43 @@ def main():
     value = total_k / sec
 
     # ---- dominant kernel and its roofline
+    steps = args.steps
     dom = max(prof.items(), key=lambda kv: kv[1][0])
     name, (ms_tot, launches) = dom
-    steps = args.steps
-    roof = None
+    roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+    flops = gemm_phase_flops(N, m, N_PAR, n_k, mdn_all)
+    fp32_tags = ("her2k", "unmtr") if mixed else ()
     if name == "hetrd_panel":
-        byts = hetrd_panel_bytes(N, total_k, 8 if mixed else 16) * steps
+        elem = 8 if mixed else 16
+        byts = hetrd_panel_bytes(N, total_k, elem) * steps
         ach = byts / (ms_tot * 1e-3) / 1e9
-        roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
-    else:
-        fl = gemm_flops(name, N, m, total_k)
-        if fl is not None:
-            ach = fl * steps / (ms_tot * 1e-3) / 1e12
-            pk = FP32_PEAK_TFLOPS if (mixed and name in ("her2k", "unmtr")) else FP64_PEAK_TFLOPS
-            roof = {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": pk,
-                    "unit": "TFLOP/s", "frac": round(ach / pk, 4), "traffic": None,
-                    "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
-        else:
-            roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
-                    "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+        traffic = traffic_from_profile(os.path.join(ROOT, "profiles", f"hetrd_panel_bhz400_{args.precision}.md"),
+                                       os.path.join(ROOT, "paper_2312_13051_amd", "csrc", "eigh.hip"), args.precision)
+        roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": round(byts / launches, 1)})
+    elif name in flops:
+        pk = FP32_PEAK_TFLOPS if name in fp32_tags else FP64_PEAK_TFLOPS
+        ach = flops[name] * steps / (ms_tot * 1e-3) / 1e12
+        roof.update({"bound": "mfma", "achieved": round(ach, 2), "peak": pk, "unit": "TFLOP/s",
+                     "frac": round(ach / pk, 4)})
     kernels = {k: {"ms_per_step": round(v[0] / steps, 2), "launches_per_step": v[1] // steps} for k, v in
                sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    # GEMM phases against the MFMA peak of their arithmetic type
+    gemm = {}
+    w_sum = t_sum = 0.0
+    for tag, fl in flops.items():
+        if tag not in prof:
+            continue
+        t = prof[tag][0] / steps * 1e-3
+        pk = FP32_PEAK_TFLOPS if tag in fp32_tags else FP64_PEAK_TFLOPS
+        gemm[tag] = {"tflops": round(fl / t / 1e12, 2), "peak": pk, "frac": round(fl / t / 1e12 / pk, 4)}
+        w_sum += fl / (pk * 1e12)
+        t_sum += t
+    gemm_phases = {"per_tag": gemm, "frac_of_mfma_peak": round(w_sum / t_sum, 4) if t_sum else None,
+                   "note": "algorithmic flops (one triangle for her2k, 8 per complex multiply-add); "
+                           "FP64 extras (polar, reorth) are timed but not counted"}
 
     # ---- phase error of the sampled lines against the FP64 oracle
     max_err = None
@@ -306,6 +359,7 @@ def main():
                                "back-transformation on MFMA, FP64 elsewhere" if mixed else "FP64 path"),
                    "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs, "tuning": tuning},
         "roofline": roof,
+        "gemm_phases": gemm_phases,
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
                        "unit": f"per chunk of {cs} systems ({cs * n_k} k-points)"},

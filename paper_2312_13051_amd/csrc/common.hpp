@@ -40,6 +40,7 @@ struct be_ctx {
   // tuning knobs (be_tune_set)
   int tune_hemv_lower = 0;       // panel H v over the lower block triangle (1) or the full square (0)
   int tune_panel_threads = 512;   // threads per matrix of the Householder panel kernel
+  std::string prof_scope;         // prefix of launch-timer names (nested calls)
 };
 
 namespace be {
@@ -96,7 +97,7 @@ class ProfScope {
 
  private:
   be_ctx *ctx_;
-  const char *name_;
+  std::string name_;
   hipStream_t stream_;
   hipEvent_t start_ = nullptr;
 };

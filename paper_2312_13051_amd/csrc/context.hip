@@ -45,8 +45,9 @@ static hipEvent_t take_event(be_ctx *ctx) {
   return e;
 }
 
-ProfScope::ProfScope(be_ctx *ctx, const char *name, hipStream_t stream) : ctx_(ctx), name_(name), stream_(stream) {
+ProfScope::ProfScope(be_ctx *ctx, const char *name, hipStream_t stream) : ctx_(ctx), stream_(stream) {
   if (!ctx_ || !ctx_->prof_on) return;
+  name_ = ctx_->prof_scope + name;
   start_ = take_event(ctx_);
   if (start_) (void)hipEventRecord(start_, stream_);
 }

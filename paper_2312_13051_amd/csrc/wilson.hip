@@ -913,7 +913,10 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
     BE_RET_IF(zgemm(ctx, g, stream));
   }
   // ---- eigh of the m x m projected spin operator (all bands)
-  BE_RET_IF(eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream));
+  ctx->prof_scope = "pso_";  // launch-timer names of the inner eigensolver
+  const int erc = eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream);
+  ctx->prof_scope.clear();
+  BE_RET_IF(erc);
   hipLaunchKernelGGL(k_pso_post, dim3(static_cast<uint32_t>((n_k + 255) / 256)), dim3(256), 0, stream, ev, kst, m, n_k,
                      kps, pso_evals, cnt, status);
   hipLaunchKernelGGL(k_pso_sys, dim3((n_sys + 63) / 64), dim3(64), 0, stream, cnt, n_sys, kps, mdn, status);
