@@ -200,9 +200,13 @@ int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t l
  *   m_dn_h[s] resp. m - m_dn_h[s] entries valid), C_dn, C_up [n_sys] (int32),
  *   C_s [n_sys] = (C_up - C_dn)/2, m_dn_h [n_sys] (host), status [n_sys]
  *   (PSO_GAP if min |mu| < 1e-6 or the count of mu < 0 varies).
+ * precision selects the eigensolver of A: BE_FP64, or BE_MIXED_FP32 (A
+ * rounded to c64, FP32 reduction and back-transformation, FP64 tridiagonal
+ * solve and orthonormalization); A, U and everything after are FP64.
  * Synchronizes the stream once (the sector sizes are read back). */
 int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
-                            int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, const double *spin_diag,
+                            int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, int32_t precision,
+                            const double *spin_diag,
                             double *pso_evals, double *theta_dn, double *theta_up, int32_t *C_dn, int32_t *C_up,
                             double *C_s, int32_t *m_dn_h, uint32_t *status, hipStream_t stream);
 

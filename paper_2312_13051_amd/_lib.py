@@ -68,7 +68,7 @@ def load():
     lib.be_wilson_loop.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.be_nested_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, C.c_double, C.c_double,
                                      vp, vp, vp, C.POINTER(i32), vp, vp]
-    lib.be_spin_resolved_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, vp,
+    lib.be_spin_resolved_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.be_zgemm_strided.argtypes = [vp, C.c_char, C.c_char, i32, i32, i32, f64p, vp, i32, i64, vp, i32, i64,
                                      f64p, vp, i32, i64, i32, vp]
@@ -179,10 +179,10 @@ class Context:
         return [int(x) for x in s_out]
 
     def spin_resolved_wilson(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, spin_diag, pso_evals,
-                             theta_dn, theta_up, C_dn, C_up, C_s, status):
+                             theta_dn, theta_up, C_dn, C_up, C_s, status, precision=BE_FP64):
         m_dn = (C.c_int32 * n_sys)()
         self._check(self.lib.be_spin_resolved_wilson(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
-                                                     mode, _ptr(spin_diag), _ptr(pso_evals), _ptr(theta_dn),
+                                                     mode, precision, _ptr(spin_diag), _ptr(pso_evals), _ptr(theta_dn),
                                                      _ptr(theta_up), _ptr(C_dn), _ptr(C_up), _ptr(C_s), m_dn,
                                                      _ptr(status), _stream()))
         return [int(x) for x in m_dn]

@@ -231,8 +231,12 @@ struct DGemm {
 };
 int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream);
 
-// FP64 batched eigensolver for bands [band_lo, band_hi) (uses slot WS_EIGH).
+// Batched eigensolver for bands [band_lo, band_hi) (uses slot WS_EIGH): FP64,
+// or mixed (c64 input, FP32 reduction and back-transformation, FP64
+// tridiagonal solve and orthonormalization, c128 eigenvectors out).
 int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
+int eigh_mixed(be_ctx *ctx, float2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
+               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
 
 }  // namespace be

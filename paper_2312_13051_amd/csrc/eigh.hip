@@ -1306,6 +1306,11 @@ int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_
   return eigh_run<double>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream);
 }
 
+int eigh_mixed(be_ctx *ctx, float2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
+               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream) {
+  return eigh_run<float>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream);
+}
+
 }  // namespace be
 
 extern "C" int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, int64_t mat_stride,

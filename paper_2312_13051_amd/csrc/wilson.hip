@@ -795,6 +795,12 @@ extern "C" int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m
 // ---------------------------------------------------------------- spin-resolved Wilson loop
 namespace {
 
+// c128 -> c64 (rounded), n elements
+__global__ void k_narrow(const double2 *a, int64_t n, float2 *b) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = make_float2(float(a[i].x), float(a[i].y));
+}
+
 // SU[k] = diag(spin) U[k] for every k of every system (N x m, ld N)
 __global__ void k_spin_scale(const double2 *U, int ldu, int64_t us, const double *spin, int N, int m, int64_t k_per_sys,
                              int64_t n_k, double2 *SU) {
@@ -852,7 +858,7 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 }  // namespace
 
 extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
-                                       int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode,
+                                       int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, int32_t precision,
                                        const double *spin_diag, double *pso_evals, double *theta_dn, double *theta_up,
                                        int32_t *C_dn, int32_t *C_up, double *C_s, int32_t *m_dn_h, uint32_t *status,
                                        hipStream_t stream) {
@@ -861,6 +867,7 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   BE_CHECK_ARG(ctx, spin_diag && pso_evals && theta_dn && theta_up && C_dn && C_up && C_s && m_dn_h && status,
                "be_spin_resolved_wilson: null argument");
   BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_resolved_wilson: at most 1024 systems per call");
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32, "be_spin_resolved_wilson: bad precision");
   if (n_sys == 0) return BE_OK;
   const int64_t kps = int64_t(n_par) * n_perp;
   const int64_t n_k = int64_t(n_sys) * kps;
@@ -914,7 +921,17 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   }
   // ---- eigh of the m x m projected spin operator (all bands)
   ctx->prof_scope = "pso_";  // launch-timer names of the inner eigensolver
-  const int erc = eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream);
+  int erc;
+  if (precision == BE_MIXED_FP32) {
+    // c64 copy of the projected operator in the (now free) S U buffer
+    float2 *A32 = reinterpret_cast<float2 *>(SU);
+    hipLaunchKernelGGL(k_narrow, dim3(static_cast<uint32_t>(std::min<int64_t>((n_k * mm + 255) / 256, 65535))),
+                       dim3(256), 0, stream, A, n_k * mm, A32);
+    erc = check_launch(ctx, "k_narrow");
+    if (erc == BE_OK) erc = eigh_mixed(ctx, A32, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream);
+  } else {
+    erc = eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream);
+  }
   ctx->prof_scope.clear();
   BE_RET_IF(erc);
   hipLaunchKernelGGL(k_pso_post, dim3(static_cast<uint32_t>((n_k + 255) / 256)), dim3(256), 0, stream, ev, kst, m, n_k,

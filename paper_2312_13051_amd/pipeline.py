@@ -88,7 +88,7 @@ def nested(ctx: L.Context, g: EigGrid, window=(0.0, 0.5), mode: int = L.BE_OVL_P
     return {"theta": nth, "s": s, "p": p, "p_mean": pm, "status": st}
 
 
-def spin(ctx: L.Context, g: EigGrid, spin_diag, mode: int = L.BE_OVL_POLAR):
+def spin(ctx: L.Context, g: EigGrid, spin_diag, mode: int = L.BE_OVL_POLAR, precision: int = L.BE_FP64):
     """spin_diag: (n_sys, N) float64 (numpy or torch)."""
     torch = _torch()
     m = max(g.m, 1)
@@ -101,7 +101,7 @@ def spin(ctx: L.Context, g: EigGrid, spin_diag, mode: int = L.BE_OVL_POLAR):
     cs = torch.empty(g.n_sys, dtype=torch.float64, device="cuda")
     st = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
     mdn = ctx.spin_resolved_wilson(g.U, g.N, g.m, g.ldu, g.U.stride(0), g.n_sys, g.n_par, g.n_perp, mode, sd, pso,
-                                   tdn, tup, cdn, cup, cs, st)
+                                   tdn, tup, cdn, cup, cs, st, precision)
     return {"mu": pso, "theta_dn": tdn, "theta_up": tup, "m_dn": mdn, "C_dn": cdn, "C_up": cup, "C_s": cs,
             "status": st}
 
@@ -129,6 +129,6 @@ def wspinsurf(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, mode=L.BE_
     """Spin-resolved WCCs over a plane (paper's WSpinSurf)."""
     plan = ctx.hk_plan(list(hoplists))
     g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision, chunk)
-    out = spin(ctx, g, spin_diag, mode)
+    out = spin(ctx, g, spin_diag, mode, precision)
     out["eig"] = g
     return out

@@ -265,7 +265,7 @@ class GpuExecutor:
         r: Request = st["req"]
         g = P.EigGrid(st["U"], st["ev"], st["st"], r.N, r.m, r.N, 1, r.kappa.shape[1], r.kappa.shape[0])
         if r.kind == KIND_SPIN:
-            out = P.spin(self.ctx, g, np.asarray(r.spin_diag)[None])
+            out = P.spin(self.ctx, g, np.asarray(r.spin_diag)[None], precision=r.precision)
         elif r.kind == KIND_NESTED:
             out = P.nested(self.ctx, g, r.window)
         else:

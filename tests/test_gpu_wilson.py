@@ -203,9 +203,10 @@ def test_mixed_precision_phases_within_gate(name):
     sd = syn.bhz_spin_diag(hl)
     plan = c.hk_plan([hl])
     g = P.eig_grid(c, plan, 0, 1, kg, 0, m, precision=1)
-    sp = P.spin(c, g, sd[None])
     sref = orc.spin_resolved_wilson(hl, sd, kg, 0, m)
-    md = sp["m_dn"][0]
-    assert md == sref["m_minus"]
-    assert phase_set_error(sp["theta_dn"][0, :, :md].cpu().numpy(), sref["theta_dn"]) < 1e-6
-    assert phase_set_error(sp["theta_up"][0, :, :m - md].cpu().numpy(), sref["theta_up"]) < 1e-6
+    for inner in (0, 1):  # eigensolver of the projected spin operator: FP64, mixed
+        sp = P.spin(c, g, sd[None], precision=inner)
+        md = sp["m_dn"][0]
+        assert md == sref["m_minus"]
+        assert phase_set_error(sp["theta_dn"][0, :, :md].cpu().numpy(), sref["theta_dn"]) < 1e-6
+        assert phase_set_error(sp["theta_up"][0, :, :m - md].cpu().numpy(), sref["theta_up"]) < 1e-6
