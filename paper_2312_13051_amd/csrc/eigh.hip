@@ -19,7 +19,7 @@
 //    supports; lanes that must share a block fall back to Gram-Schmidt. The
 //    vectors are then orthonormalized in FP64 by Newton-Schulz steps on the
 //    Gram matrix (symmetric orthonormalization, MFMA DGEMMs) until
-//    max |Z^T Z - I| < 1e-14.
+//    max |Z^T Z - I| < 1e-14 (1e-10 on the mixed path).
 // 3. Back-transformation U = Q Z by panels in reverse order with three MFMA
 //    GEMMs each: X = V^H U, Y = T X, U -= V Y.
 // 4. Mixed precision: the reduction and back-transformation run in FP32 on
@@ -145,19 +145,16 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
 
   for (int jj = 0; jj < nbp; ++jj) {
     const int j = p0 + jj;
-    // ---- (1) apply the panel's earlier reflectors to column j
-    for (int c = tid; c < jj; c += NT) {
-      sVr[c] = V[j + int64_t(c) * N];
-      sWr[c] = W[j + int64_t(c) * N];
-    }
-    __syncthreads();
+    // ---- (1) apply the panel's earlier reflectors to column j,
+    //   a -= V(r,c) conj(W(j,c)) + W(r,c) conj(V(j,c)),  c < jj.
+    // The terms c < jj-1 were applied during the previous column's pass over
+    // V and W (step 6); the term c = jj-1 uses that column's v and w, which
+    // are still in LDS.
     for (int r = j + tid; r < N; r += NT) {
       C a = Aq[r + int64_t(j) * lda];
       T ar = a.x, ai = a.y;
-      for (int c = 0; c < jj; ++c) {
-        C vr = V[r + int64_t(c) * N], wr = W[r + int64_t(c) * N];
-        C wj = sWr[c], vj = sVr[c];
-        // a -= V(r,c) conj(W(j,c)) + W(r,c) conj(V(j,c))
+      if (jj > 0) {
+        const C vr = sv[r], wr = sy[r], wj = sy[j], vj = sv[j];
         ar -= vr.x * wj.x + vr.y * wj.y + wr.x * vj.x + wr.y * vj.y;
         ai -= vr.y * wj.x - vr.x * wj.y + wr.y * vj.x - wr.x * vj.y;
       }
@@ -166,6 +163,13 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
         d[q * sDE + j] = double(ar);
       }
       Aq[r + int64_t(j) * lda] = mk<C>(ar, ai);
+    }
+    // row j+1 of V and W (columns < jj), for step 6's share of column j+1
+    for (int c = tid; c < jj; c += NT) {
+      if (j + 1 < N) {
+        sVr[c] = V[j + 1 + int64_t(c) * N];
+        sWr[c] = W[j + 1 + int64_t(c) * N];
+      }
     }
     __syncthreads();
     if (j == N - 1) {
@@ -385,17 +389,26 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
       }
     }
     __syncthreads();
-    // y -= V t1 + W t2
+    // y -= V t1 + W t2; with the same loads of V(r, c) and W(r, c), the
+    // terms c < jj of step 1 for column j+1 when it belongs to this panel
+    const bool fuse = jj > 0 && jj + 1 < nbp && j + 1 < N;
     for (int r = r0 + tid; r < N; r += NT) {
       C y = sy[r];
-      T yr = y.x, yi = y.y;
+      T yr = y.x, yi = y.y, pr = 0, pi = 0;
       for (int c = 0; c < jj; ++c) {
         C vv = V[r + int64_t(c) * N], w = W[r + int64_t(c) * N], a = st1[c], b = st2[c];
         yr -= vv.x * a.x - vv.y * a.y + w.x * b.x - w.y * b.y;
         yi -= vv.x * a.y + vv.y * a.x + w.x * b.y + w.y * b.x;
+        const C wj = sWr[c], vj = sVr[c];
+        pr += vv.x * wj.x + vv.y * wj.y + w.x * vj.x + w.y * vj.y;
+        pi += vv.y * wj.x - vv.x * wj.y + w.y * vj.x - w.x * vj.y;
       }
       // w = tau * y
       sy[r] = mk<C>(tau.x * yr - tau.y * yi, tau.x * yi + tau.y * yr);
+      if (fuse) {
+        const C a0 = Aq[r + int64_t(j + 1) * lda];
+        Aq[r + int64_t(j + 1) * lda] = mk<C>(a0.x - pr, a0.y - pi);
+      }
     }
     // compact-WY column: T(0:jj, jj) = -tau T(0:jj, 0:jj) t2, T(jj, jj) = tau
     if (tid < jj) {
@@ -428,6 +441,7 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
         w = mk<C>(y.x + alr * v.x - ali * v.y, y.y + alr * v.y + ali * v.x);
       }
       W[r + int64_t(jj) * N] = w;
+      sy[r] = w;  // kept for step 1 of the next column
     }
     __syncthreads();
   }
@@ -657,7 +671,9 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
     const double lm = (!found || shared) ? lam[c] + (jr - 0.5 * (c1 - c0 - 1)) * 2.0 * eps * tnorm : lam[c];
     for (int i = 0; i < N; ++i)
       if (i < bs || i >= bt) X[int64_t(i) * mp + c] = 0.0;
-    for (int it = 0; it < 3; ++it) {
+    // two solves: from a pseudo-random start the first already amplifies the
+    // wanted direction by ~1/(eps ||T||) against ~1/gap for the others
+    for (int it = 0; it < 2; ++it) {
       // forward elimination with partial pivoting on [T_block - lm I | rhs]
       double a = sd[bs] - lm, b = bt - bs > 1 ? se[bs] : 0.0;
       double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, bs) : X[int64_t(bs) * mp + c];
@@ -1152,8 +1168,10 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   const int64_t ust = mixed ? int64_t(N) * m : us;
   // ---- symmetric orthonormalization of Z (Newton-Schulz on the Gram matrix),
   // Z held as X = Z^T (m x N, leading dim mp); iterated until max |X X^T - I|
-  // is below 1e-14 (two steps from inverse-iteration vectors)
+  // is below 1e-14 (FP64 path), or 1e-10 on the mixed path, whose FP32
+  // back-transformation leaves errors of order 1e-7 anyway
   {
+    const double tol_orth = mixed ? 1e-10 : 1e-14;
     const int64_t sZ = int64_t(4) * N * mp;
     double *Xa = Zs + int64_t(3) * N * mp, *Xt = Zs;
     double *hmax = static_cast<double *>(ctx->pinned);
@@ -1182,7 +1200,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       BE_HIP_TRY(ctx, hipMemcpyAsync(hmax, gmax, sizeof(double), hipMemcpyDeviceToHost, stream));
       BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
       const double e = *hmax;
-      if (e <= 1e-14) break;
+      if (e <= tol_orth) break;
       DGemm h;  // X <- (3 I - G) X / 2
       h.M = m;
       h.N = N;
