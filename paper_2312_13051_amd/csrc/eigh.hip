@@ -589,11 +589,11 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
   }
 }
 
-// Tolerances relative to eps ||T||: split < block window < cluster gap, so a
-// cluster's window never reaches the next cluster.
+// Tolerances relative to ||T||: split < block window < cluster gap, so a
+// cluster's window never reaches the next cluster (clu_rel = 64 eps).
 __device__ __forceinline__ double tol_split(double tnorm) { return 16.0 * DBL_EPSILON * tnorm; }
-__device__ __forceinline__ double tol_window(double tnorm) { return 32.0 * DBL_EPSILON * tnorm; }
-__device__ __forceinline__ double tol_cluster(double tnorm) { return 64.0 * DBL_EPSILON * tnorm; }
+__device__ __forceinline__ double tol_window(double tnorm, double clu_rel) { return 0.5 * clu_rel * tnorm; }
+__device__ __forceinline__ double tol_cluster(double tnorm, double clu_rel) { return clu_rel * tnorm; }
 
 // (a4) eigenvectors by inverse iteration, one lane per eigenvector. T is
 // split where an off-diagonal is negligible; the k lanes of a k-fold
@@ -602,14 +602,15 @@ __device__ __forceinline__ double tol_cluster(double tnorm) { return 64.0 * DBL_
 // share a block are marked for Gram-Schmidt (tri_gs).
 __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e, int64_t sDE, int N, int m,
                                                 const double *lamg, double *Zs, int64_t sZ, int mp, int *marks,
-                                                uint32_t *status) {
+                                                double clu_rel, uint32_t *status) {
   extern __shared__ double tsm[];
   double *sd = tsm;        // N
   double *se = sd + N;     // N
   double *se2 = se + N;    // N
   double *lam = se2 + N;   // m
   int *sblk = reinterpret_cast<int *>(lam + m);  // block starts (N + 1)
-  int *smark = sblk + N + 1;                     // m
+  int *smark = sblk + N + 1;                     // m: group id per lane
+  int *sbad = smark + m;                         // m: cluster start -> a lane found no block
   __shared__ int s_bad, s_nblk;
   const int64_t q = blockIdx.x;
   const int tid = threadIdx.x;
@@ -618,6 +619,7 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
   for (int c = tid; c < m; c += PT) {
     lam[c] = lamg[q * (m + 1) + 1 + c];
     smark[c] = 0;
+    sbad[c] = 0;
   }
   const double tnorm = lamg[q * (m + 1)];
   const double eps = DBL_EPSILON;
@@ -640,7 +642,7 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
   double *Z2 = Z1 + int64_t(N) * mp;
   double *X = Z2 + int64_t(N) * mp;
   const double tiny = eps * fmax(tnorm, DBL_MIN);
-  const double dblk = tol_window(tnorm), dclu = tol_cluster(tnorm);
+  const double dblk = tol_window(tnorm, clu_rel), dclu = tol_cluster(tnorm, clu_rel);
   bool lane_bad = false;
   for (int c = tid; c < m; c += PT) {
     int c0 = c, c1 = c + 1;
@@ -662,7 +664,11 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
       }
       cnt += nb;
     }
-    if (!found || shared) smark[c0] = 1;
+    // group id of the lane for the orthonormalization: lanes sharing a block
+    // (block start + 2); a lane that found no block makes its whole cluster
+    // one group (id 1, set below)
+    if (shared) smark[c] = bs + 2;
+    if (!found) sbad[c0] = 1;
     // Lanes that share a block with other members of their cluster take
     // shifts a few eps ||T|| apart: far larger than the splitting of a
     // degenerate pair (so neither member dominates a lane's solve and each
@@ -727,51 +733,71 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
     }
   }
   __syncthreads();
-  for (int c = tid; c < m; c += PT) marks[q * m + c] = smark[c];
+  for (int c = tid; c < m; c += PT) {
+    int c0 = c;
+    while (c0 > 0 && lam[c0] - lam[c0 - 1] <= dclu) --c0;
+    marks[q * m + c] = sbad[c0] ? 1 : smark[c];
+  }
   if (lane_bad) atomicOr(&status[q], uint32_t(BE_ST_NONCONVERGED));
 }
 
-// Clusters whose members share a block of T are orthonormalized by two
-// passes of Cholesky QR (G = V^T V = R^T R, V <- V R^-1), done in lanes: the
-// marked clusters are packed into 64-lane bins (no cluster straddles a bin),
-// a bin is one wave, vector c sits on one lane, and the rows of X are swept
-// with coalesced loads (the eigenvector index is the fastest dimension of X).
-// A Gram sweep reads the other members of a lane's cluster by cross-lane
-// permutes; the first member of each cluster factors G in LDS; an apply sweep
-// solves y R = x row by row, the members finalizing y in order and passing it
-// on by permutes. Clusters larger than GK run the same passes with the whole
-// workgroup; a breakdown of the Cholesky factorization falls back to modified
-// Gram-Schmidt with one wave per cluster.
+// End of the orthonormalization group starting at c0: the following lanes of
+// the same cluster with the same group id (0: no group, a group of one).
+__device__ __forceinline__ int group_end(const double *lam, const int *mk, int m, int c0, double dclu) {
+  int c1 = c0 + 1;
+  if (mk[c0] == 0) return c1;
+  while (c1 < m && mk[c1] == mk[c0] && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+  return c1;
+}
+
+// Groups of vectors that share a block of T (inside a cluster of equal
+// eigenvalues; vectors in different blocks have disjoint supports and are
+// orthogonal already) are orthonormalized by two passes of Cholesky QR
+// (G = V^T V = R^T R, V <- V R^-1), done in lanes: the groups are packed into
+// 64-lane bins (no group straddles a bin), a bin is one wave, vector c sits
+// on one lane, and the rows of X are swept with coalesced loads (the
+// eigenvector index is the fastest dimension of X). A Gram sweep reads the
+// other members of a lane's group by cross-lane permutes; the first member of
+// each group factors G in LDS; an apply sweep solves y R = x row by row, the
+// members finalizing y in order and passing it on by permutes. Groups larger
+// than GK run the same passes with the whole workgroup; a breakdown of the
+// Cholesky factorization falls back to modified Gram-Schmidt with one wave
+// per group.
 constexpr int GK = 32;
 
 __host__ __device__ inline int gs_bins_max(int m) { return m / (64 - GK + 1) + 2; }
 
 size_t gs_smem(int m) {
-  return size_t(PT) * GK * sizeof(double) + (3 * size_t(gs_bins_max(m)) * 64 + size_t(std::max(m, 1))) * sizeof(int);
+  return size_t(PT) * GK * sizeof(double) + size_t(std::max(m, 1)) * sizeof(double) +
+         (3 * size_t(gs_bins_max(m)) * 64 + 2 * size_t(std::max(m, 1))) * sizeof(int);
 }
 
 __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, double *Zs, int64_t sZ, int mp,
-                                             const int *marks, double *Gm, const uint32_t *status) {
+                                             const int *marks, double *Gm, double clu_rel, const uint32_t *status) {
   extern __shared__ double gsm[];
   const int nbmax = gs_bins_max(m);
-  int *sv = reinterpret_cast<int *>(gsm + PT * GK);  // bin lane -> vector (-1: idle)
-  int *sb = sv + nbmax * 64;                         // bin lane -> lane of its cluster's first member
-  int *sk = sb + nbmax * 64;                         // bin lane -> cluster size
-  int *sfl = sk + nbmax * 64;                        // cluster start -> Cholesky breakdown
+  int *sv = reinterpret_cast<int *>(gsm + PT * GK + m);  // bin lane -> vector (-1: idle)
+  int *sb = sv + nbmax * 64;                         // bin lane -> lane of its group's first member
+  int *sk = sb + nbmax * 64;                         // bin lane -> group size
+  int *sfl = sk + nbmax * 64;                        // group start -> Cholesky breakdown
+  int *mk_q = sfl + m;                               // group id per vector
+  double *lam = gsm + PT * GK;                       // selected eigenvalues (m)
   __shared__ int s_nbins;
   const int64_t q = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = PT / 64;
   if (status[q] & BE_ST_NAN_INF) return;
-  const double *lam = lamg + q * (m + 1) + 1;
-  const double dclu = tol_cluster(lamg[q * (m + 1)]);
+  const double dclu = tol_cluster(lamg[q * (m + 1)], clu_rel);
   double *X = Zs + q * sZ + int64_t(3) * N * mp;
-  const int *mk_q = marks + q * m;
-  for (int c = tid; c < m; c += PT) sfl[c] = 0;
+  for (int c = tid; c < m; c += PT) {
+    sfl[c] = 0;
+    mk_q[c] = marks[q * m + c];
+    lam[c] = lamg[q * (m + 1) + 1 + c];
+  }
+  __syncthreads();
   if (tid == 0) {
     int nb = 0, fill = 0;
     for (int c0 = 0; c0 < m;) {
-      int c1 = c0 + 1;
-      while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+      const int c1 = group_end(lam, mk_q, m, c0, dclu);
       const int k = c1 - c0;
       if (mk_q[c0] && k > 1 && k <= GK) {
         if (fill + k > 64) {
@@ -820,7 +846,7 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
 #pragma unroll
       for (int t = 0; t < GK; ++t) G[lane * GK + t] = g[t];
       __syncthreads();
-      // Cholesky G = R^T R in place (upper triangle), by the cluster's first lane
+      // Cholesky G = R^T R in place (upper triangle), by the group's first lane
       if (act && rel == 0 && !sfl[c]) {
         for (int jj = 0; jj < k; ++jj) {
           double dg = G[(b + jj) * GK + jj];
@@ -864,21 +890,29 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
       __syncthreads();
     }
   }
-  // clusters larger than GK: the same two Cholesky-QR passes by the whole
-  // workgroup. The Gram matrix is accumulated from LDS tiles of rows, the
-  // factorization runs one column per step in the matrix's m x m scratch
-  // (Gq, row-major k x k), and each thread solves y R = x for whole rows of
-  // the cluster, in place.
+  // groups larger than GK: the same two Cholesky-QR passes by the whole
+  // workgroup. The Gram matrix and its factor are kept packed (upper
+  // triangle, row by row) in LDS next to a tile of the cluster's rows when
+  // they fit (k(k+1)/2 + k <= PT*GK), else in the matrix's m x m scratch Gq.
+  // The Gram matrix is accumulated tile by tile, the factorization runs one
+  // column per step, R is inverted in place, and X_c R^-1 is formed from
+  // rows staged in the LDS tile, one (row, column) dot product per thread.
   double *Gq = Gm + q * int64_t(m) * m;
-  double *tile = gsm;
   for (int c0 = 0; c0 < m;) {
-    int c1 = c0 + 1;
-    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+    const int c1 = group_end(lam, mk_q, m, c0, dclu);
     const int k = c1 - c0;
     if (mk_q[c0] && k > GK) {
-      const int RB = (PT * GK) / k;  // rows per LDS tile
+      const int npk = k * (k + 1) / 2;
+      const bool in_lds = npk + k <= PT * GK;
+      double *Rp = in_lds ? gsm : Gq;              // packed upper triangle
+      double *tile = in_lds ? gsm + npk : gsm;     // rows of the group
+      const int RB = in_lds ? (PT * GK - npk) / k : (PT * GK) / k;
+      // packed index of (s, t), s <= t
+      auto pk = [k](int s2, int t) { return s2 * k - (s2 * (s2 - 1)) / 2 + (t - s2); };
       for (int pass = 0; pass < 2 && !sfl[c0]; ++pass) {
-        for (int e = tid; e < k * k; e += PT) Gq[e] = 0.0;
+        __syncthreads();
+        for (int e = tid; e < npk; e += PT) Rp[e] = 0.0;
+        // Gram matrix, upper triangle, tile by tile (16 threads per row s2)
         for (int i0 = 0; i0 < N; i0 += RB) {
           const int nr = min(RB, N - i0);
           __syncthreads();
@@ -887,42 +921,60 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
             tile[e] = X[int64_t(i0 + r) * mp + c0 + col];
           }
           __syncthreads();
-          for (int e = tid; e < k * k; e += PT) {
-            const int s2 = e / k, t = e - s2 * k;
-            if (t < s2) continue;
-            double acc = 0.0;
-            for (int r = 0; r < nr; ++r) acc = fma(tile[r * k + s2], tile[r * k + t], acc);
-            Gq[e] += acc;
-          }
+          for (int s2 = tid >> 4; s2 < k; s2 += PT >> 4)
+            for (int t = s2 + (tid & 15); t < k; t += 16) {
+              double acc = 0.0;
+              for (int r = 0; r < nr; ++r) acc = fma(tile[r * k + s2], tile[r * k + t], acc);
+              Rp[pk(s2, t)] += acc;
+            }
         }
         __syncthreads();
-        // right-looking Cholesky on the upper triangle
+        // right-looking Cholesky, one column per step
         for (int j = 0; j < k; ++j) {
           if (tid == 0) {
-            const double dg = Gq[j * k + j];
+            const double dg = Rp[pk(j, j)];
             if (!(dg > 1e-12) || !isfinite(dg)) sfl[c0] = 1;  // columns enter with unit norm
-            Gq[j * k + j] = sqrt(fmax(dg, DBL_MIN));
+            Rp[pk(j, j)] = sqrt(fmax(dg, DBL_MIN));
           }
           __syncthreads();
           if (sfl[c0]) break;
-          const double rjj = Gq[j * k + j];
-          for (int t = j + 1 + tid; t < k; t += PT) Gq[j * k + t] /= rjj;
+          const double rjj = Rp[pk(j, j)];
+          for (int t = j + 1 + tid; t < k; t += PT) Rp[pk(j, t)] /= rjj;
           __syncthreads();
-          const int nt = k - j - 1;
-          for (int e = tid; e < nt * nt; e += PT) {
-            const int s2 = j + 1 + e / nt, t = j + 1 + e % nt;
-            if (t >= s2) Gq[s2 * k + t] -= Gq[j * k + s2] * Gq[j * k + t];
+          for (int s2 = j + 1 + (tid >> 4); s2 < k; s2 += PT >> 4) {
+            const double rs = Rp[pk(j, s2)];
+            for (int t = s2 + (tid & 15); t < k; t += 16) Rp[pk(s2, t)] -= rs * Rp[pk(j, t)];
           }
           __syncthreads();
         }
         if (sfl[c0]) break;
-        // X_c <- X_c R^-1, row by row
-        for (int i = tid; i < N; i += PT) {
-          double *xr = X + int64_t(i) * mp + c0;
-          for (int j = 0; j < k; ++j) {
-            double v = xr[j];
-            for (int p = 0; p < j; ++p) v = fma(-xr[p], Gq[p * k + j], v);
-            xr[j] = v / Gq[j * k + j];
+        // R^-1 in place, rows from the bottom: row i needs rows > i of R^-1
+        for (int i = k - 1; i >= 0; --i) {
+          const double rii = Rp[pk(i, i)];
+          for (int j = i + tid; j < k; j += PT) {
+            double v = j == i ? 1.0 : 0.0;
+            for (int p = i + 1; p <= j; ++p) v -= Rp[pk(i, p)] * Rp[pk(p, j)];
+            tile[j] = v / rii;
+          }
+          __syncthreads();
+          for (int j = i + tid; j < k; j += PT) Rp[pk(i, j)] = tile[j];
+          __syncthreads();
+        }
+        // X_c <- X_c R^-1: rows staged in LDS, independent (row, column) dot products
+        for (int i0 = 0; i0 < N; i0 += RB) {
+          const int nr = min(RB, N - i0);
+          __syncthreads();
+          for (int e = tid; e < nr * k; e += PT) {
+            const int r = e / k, col = e - r * k;
+            tile[e] = X[int64_t(i0 + r) * mp + c0 + col];
+          }
+          __syncthreads();
+          for (int e = tid; e < nr * k; e += PT) {
+            const int r = e / k, j = e - r * k;
+            const double *xr = tile + r * k;
+            double v = 0.0;
+            for (int p = 0, ix = j; p <= j; ix += k - p - 1, ++p) v = fma(xr[p], Rp[ix], v);
+            X[int64_t(i0 + r) * mp + c0 + j] = v;
           }
         }
         __syncthreads();
@@ -933,8 +985,7 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
   __syncthreads();
   // clusters left to the fallback: a Cholesky breakdown
   for (int c0 = 0, w = 0; c0 < m;) {
-    int c1 = c0 + 1;
-    while (c1 < m && lam[c1] - lam[c1 - 1] <= dclu) ++c1;
+    const int c1 = group_end(lam, mk_q, m, c0, dclu);
     const int k = c1 - c0;
     if (mk_q[c0] && k > 1 && sfl[c0]) {
       if (w++ % nw == wave) {
@@ -1131,6 +1182,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     }
   }
   // ---- tridiagonal eigenpairs: bisection, inverse iteration, Gram-Schmidt of shared-block clusters
+  const double clu_rel = 64.0 * DBL_EPSILON;
   {
     const size_t smb = (2 * size_t(N) + m + 4) * sizeof(double);
     if (smb > 65536)
@@ -1143,13 +1195,13 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   BE_RET_IF(check_launch(ctx, "tri_bisect"));
   if (m == 0) return BE_OK;
   {
-    const size_t smi = (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + m) * sizeof(int);
+    const size_t smi = (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + 2 * size_t(m)) * sizeof(int);
     if (smi > 65536)
       BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tri_invit),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(smi)));
     ProfScope prof(ctx, "tri_invit", stream);
     hipLaunchKernelGGL(tri_invit, dim3(nb_mat), dim3(PT), smi, stream, dd, ee, int64_t(N), N, m, lamg, Zs,
-                       int64_t(4) * N * mp, mp, marks, status);
+                       int64_t(4) * N * mp, mp, marks, clu_rel, status);
   }
   BE_RET_IF(check_launch(ctx, "tri_invit"));
   {
@@ -1159,7 +1211,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(smg)));
     ProfScope prof(ctx, "tri_gs", stream);
     hipLaunchKernelGGL(tri_gs, dim3(nb_mat), dim3(PT), smg, stream, N, m, lamg, Zs, int64_t(4) * N * mp, mp, marks, Gm,
-                       status);
+                       clu_rel, status);
   }
   BE_RET_IF(check_launch(ctx, "tri_gs"));
   // back-transformation target: the output itself (FP64) or an FP32 copy (mixed)
