@@ -224,10 +224,6 @@ int be_profile_names(be_ctx *ctx, char *buf, size_t len);
 /* Tuning knobs: algorithm variants with identical results up to rounding,
  * chosen per context (by measurement). Unknown knob names and out-of-range
  * values return BE_EINVAL. Knobs:
- *   "hetrd_hemv_lower"  0: the panel kernel's H v reads the full trailing
- *                       square; 1: it reads the lower block triangle and adds
- *                       the conjugate-transposed products (half the bytes,
- *                       cross-lane reductions instead). Default 0.
  *   "hetrd_panel_threads" threads per matrix of the panel kernel: 256, 512
  *                       or 1024 (default 512: two matrices per compute
  *                       unit overlap one's serial reflector steps with the

@@ -38,7 +38,6 @@ struct be_ctx {
   std::string err;
   int n_cu = 256;
   // tuning knobs (be_tune_set)
-  int tune_hemv_lower = 0;       // panel H v over the lower block triangle (1) or the full square (0)
   int tune_panel_threads = 512;   // threads per matrix of the Householder panel kernel
   std::string prof_scope;         // prefix of launch-timer names (nested calls)
 };
@@ -48,11 +47,15 @@ namespace be {
 // ---------------------------------------------------------------- errors
 int set_err(be_ctx *ctx, int code, const std::string &msg);
 
+// A failed HIP call is reported as BE_EHIP; HIP's last-error state is cleared
+// so that the caller's next unrelated HIP call does not see it again.
 #define BE_HIP_TRY(ctx, expr)                                                         \
   do {                                                                                \
     hipError_t _e = (expr);                                                           \
-    if (_e != hipSuccess)                                                             \
+    if (_e != hipSuccess) {                                                           \
+      (void)hipGetLastError();                                                        \
       return ::be::set_err((ctx), BE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    }                                                                                 \
   } while (0)
 
 #define BE_CHECK_ARG(ctx, cond, msg)                                    \

@@ -147,11 +147,6 @@ int be_profile_query(be_ctx *ctx, const char *name, double *total_ms, int64_t *l
 int be_tune_set(be_ctx *ctx, const char *knob, int32_t value) {
   if (!ctx || !knob) return BE_EINVAL;
   const std::string k(knob);
-  if (k == "hetrd_hemv_lower") {
-    BE_CHECK_ARG(ctx, value == 0 || value == 1, "hetrd_hemv_lower takes 0 or 1");
-    ctx->tune_hemv_lower = value;
-    return BE_OK;
-  }
   if (k == "hetrd_panel_threads") {
     BE_CHECK_ARG(ctx, value == 256 || value == 512 || value == 1024, "hetrd_panel_threads takes 256, 512 or 1024");
     ctx->tune_panel_threads = value;
@@ -163,10 +158,6 @@ int be_tune_set(be_ctx *ctx, const char *knob, int32_t value) {
 int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value) {
   if (!ctx || !knob || !value) return BE_EINVAL;
   const std::string k(knob);
-  if (k == "hetrd_hemv_lower") {
-    *value = ctx->tune_hemv_lower;
-    return BE_OK;
-  }
   if (k == "hetrd_panel_threads") {
     *value = ctx->tune_panel_threads;
     return BE_OK;

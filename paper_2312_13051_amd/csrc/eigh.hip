@@ -84,36 +84,11 @@ __device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
   __syncthreads();
 }
 
-// Column sums of a wave's register tile. Each lane holds K values x[0..K-1]
-// (K a power of two, at most 64); on return the lane holds the sum over all 64
-// lanes of x[k] with k = (lane >> (6 - log2 K)) & (K - 1). Each halving step
-// exchanges half of the remaining values with the partner lane at distance o
-// and keeps the half selected by that bit of the lane index, so K values cost
-// K - 1 exchanges instead of 6 K for separate reductions.
-template <typename T, int LOGK>
-__device__ __forceinline__ T transpose_reduce(T (&x)[1 << LOGK], int lane) {
-#pragma unroll
-  for (int s = 0; s < LOGK; ++s) {
-    const int o = 32 >> s, half = (1 << LOGK) >> (s + 1);
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const T keep = up ? x[i + half] : x[i];
-      const T send = up ? x[i] : x[i + half];
-      x[i] = keep + __shfl_xor(send, o, 64);
-    }
-  }
-  T v = x[0];
-#pragma unroll
-  for (int o = 32 >> LOGK; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // ---------------------------------------------------------------- panel kernel
 // A: matrices (full Hermitian storage), VW: [V | W | V] panel buffers (N x 3NB,
 // leading dimension N), Tm: per-matrix NB x NB compact-WY factor of each
 // panel, d/e: FP64 tridiagonal output.
-template <typename T, bool LOWER, int NT>
+template <typename T, int NT>
 __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
                                                   typename CT<T>::c *VW, int64_t sVW, typename CT<T>::c *Tm,
                                                   int64_t sTm, double *d, double *e, int64_t sDE, uint32_t *status) {
@@ -127,9 +102,7 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
   C *st2 = st1 + NB;                        // V^H v (NB)
   C *sT = st2 + NB;                         // NB x NB, column-major
   C *spart = sT + NB * NB;                  // per-lane partial sums of H v (NT)
-  C *szp = spart + NT;                      // lower-triangle H v: per-wave column sums (NT / 2)
-  T *red = reinterpret_cast<T *>(szp + NT / 2);  // 2 * waves
-  __shared__ int s_ry[NT / 64], s_rz[NT / 64];
+  T *red = reinterpret_cast<T *>(spart + NT);  // 2 * waves
   __shared__ C s_tau, s_scal;
   __shared__ T s_beta;
 
@@ -270,83 +243,7 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
         yi += a.x * v.y + a.y * v.x;
       }
     };
-    if (LOWER && nrb >= 4) {
-      // Lower-triangle variant: items are (64-row block rb, 32-column half of
-      // column block cb <= rb). An item adds A(rows, cols) v(cols) to y(rows)
-      // and, below the diagonal block, A(rows, cols)^H v(rows) to y(cols)
-      // (A is Hermitian), so only the lower block triangle is read. One item
-      // per wave and round; partial sums go to per-wave LDS slots and are
-      // combined in wave order, so the result does not depend on scheduling.
-      constexpr int UN = 64 / sizeof(C);  // 64 bytes of loads per lane and step
-      static_assert(UN == 4 || UN == 8, "one 64-byte load group per lane");
-      constexpr int LOGK = UN == 8 ? 3 : 2;  // log2 UN
-      const int n_items = nrb * (nrb + 1);  // two halves per block
-      for (int t0 = 0; t0 < n_items; t0 += nw) {
-        const int t = t0 + wave;
-        T yr = 0, yi = 0;
-        int ry = -1, rz = -1;
-        if (t < n_items) {
-          const int tile = t >> 1, hf = t & 1;
-          int rb = int((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
-          while (rb * (rb + 1) / 2 > tile) --rb;
-          while ((rb + 1) * (rb + 2) / 2 <= tile) ++rb;
-          const int cb = tile - rb * (rb + 1) / 2;
-          ry = r0 + rb * 64;
-          const int c0 = r0 + cb * 64 + hf * 32, c1 = min(N, c0 + 32);
-          const bool diag = rb == cb;
-          if (!diag) rz = c0;
-          const int R = ry + lane;
-          const bool rok = R < N;
-          const C vR = rok ? sv[R] : mk<C>(0, 0);
-          const C *row = Aq + (rok ? R : r0);
-          for (int c = c0; c < c1; c += UN) {
-            C a[UN];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) a[u] = (rok && c + u < c1) ? row[int64_t(c + u) * lda] : mk<C>(0, 0);
-#pragma unroll
-            for (int u = 0; u < UN; ++u) {
-              const C v = sv[min(c + u, N - 1)];
-              yr += a[u].x * v.x - a[u].y * v.y;
-              yi += a[u].x * v.y + a[u].y * v.x;
-            }
-            if (!diag) {
-              T x[2 * UN];
-#pragma unroll
-              for (int u = 0; u < UN; ++u) {
-                x[u] = a[u].x * vR.x + a[u].y * vR.y;       // Re conj(a) v(R)
-                x[u + UN] = a[u].x * vR.y - a[u].y * vR.x;  // Im conj(a) v(R)
-              }
-              const T z = transpose_reduce<T, LOGK + 1>(x, lane);
-              const int k = (lane >> (5 - LOGK)) & (2 * UN - 1);
-              if ((lane & ((1 << (5 - LOGK)) - 1)) == 0 && c + (k % UN) < c1)
-                reinterpret_cast<T *>(szp)[wave * 64 + 2 * (c - c0 + (k % UN)) + (k >= UN)] = z;
-            }
-          }
-        }
-        spart[tid] = mk<C>(yr, yi);
-        if (lane == 0) {
-          s_ry[wave] = ry;
-          s_rz[wave] = rz;
-        }
-        __syncthreads();
-        for (int r = r0 + tid; r < N; r += NT) {
-          C acc = t0 == 0 ? mk<C>(0, 0) : sy[r];
-          for (int w = 0; w < nw; ++w) {
-            const int dy = r - s_ry[w], dz = r - s_rz[w];
-            if (s_ry[w] >= 0 && dy >= 0 && dy < 64) {
-              acc.x += spart[w * 64 + dy].x;
-              acc.y += spart[w * 64 + dy].y;
-            }
-            if (s_rz[w] >= 0 && dz >= 0 && dz < 32) {
-              acc.x += szp[w * 32 + dz].x;
-              acc.y += szp[w * 32 + dz].y;
-            }
-          }
-          sy[r] = acc;
-        }
-        __syncthreads();
-      }
-    } else if (ncs == 1) {
+    if (ncs == 1) {
       for (int rb = wave; rb < nrb; rb += nw) {
         T yr, yi;
         slice_dot(rb, 0, yr, yi);
@@ -1077,7 +974,7 @@ __global__ void zero_u32(uint32_t *p, int64_t n) {
 }
 
 size_t panel_smem(int N, size_t csize, int nt) {
-  return (2 * size_t(N) + 4 * NB + NB * NB + nt + nt / 2) * csize + 2 * (nt / 64) * (csize / 2) + 64;
+  return (2 * size_t(N) + 4 * NB + NB * NB + nt) * csize + 2 * (nt / 64) * (csize / 2) + 64;
 }
 
 }  // namespace
@@ -1135,16 +1032,11 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   BE_RET_IF(check_launch(ctx, "zero_u32"));
   const int64_t sVW = int64_t(N) * 3 * NB;
   const int64_t sT = int64_t(P) * NB * NB;
-  // panel kernel variant: H v over the full square or the lower block triangle,
-  // 256, 512 or 1024 threads per matrix
+  // panel kernel: 256, 512 or 1024 threads per matrix
   const int pnt = ctx->tune_panel_threads;
   const size_t psm = panel_smem(N, sizeof(C), pnt);
-  void (*panel)(C *, int64_t, int, int, int, int, C *, int64_t, C *, int64_t, double *, double *, int64_t, uint32_t *);
-  if (ctx->tune_hemv_lower)
-    panel = pnt == 256 ? &hetrd_panel<T, true, 256> : pnt == 512 ? &hetrd_panel<T, true, 512> : &hetrd_panel<T, true, 1024>;
-  else
-    panel = pnt == 256 ? &hetrd_panel<T, false, 256>
-                       : pnt == 512 ? &hetrd_panel<T, false, 512> : &hetrd_panel<T, false, 1024>;
+  void (*panel)(C *, int64_t, int, int, int, int, C *, int64_t, C *, int64_t, double *, double *, int64_t, uint32_t *) =
+      pnt == 256 ? &hetrd_panel<T, 256> : pnt == 512 ? &hetrd_panel<T, 512> : &hetrd_panel<T, 1024>;
   if (psm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)));

@@ -71,7 +71,9 @@ def test_argument_errors():
         c.tune_set("no_such_knob", 1)
     with pytest.raises(BerryError):
         c.tune_set("hetrd_panel_threads", 300)
-    assert c.tune_get("hetrd_panel_threads") == 512 and c.tune_get("hetrd_hemv_lower") == 0
+    assert c.tune_get("hetrd_panel_threads") == 512
+    with pytest.raises(BerryError):
+        c.tune_get("no_such_knob")
 
 
 def test_pso_gap_flag_with_zero_spin_operator():

@@ -145,20 +145,17 @@ def test_eigh_mixed_precision_bounds(name):
         assert st[q] == 0
 
 
-@pytest.mark.parametrize("hemv_lower,threads", [(0, 1024), (1, 1024), (0, 512), (0, 256), (1, 256)])
+@pytest.mark.parametrize("threads", [1024, 512, 256])
 @pytest.mark.parametrize("N,lo,hi", [(257, 0, 128), (400, 7, 203), (463, 100, 300)])
-def test_eigh_panel_variants(N, lo, hi, hemv_lower, threads):
-    """The panel kernel's variants: H v over the full square or the lower
-    block triangle (taken for trailing matrices of more than three 64-row
-    blocks), 256 to 1024 threads per matrix."""
+def test_eigh_panel_variants(N, lo, hi, threads):
+    """The panel kernel with 256 to 1024 threads per matrix."""
     gu.need_gpu()
     rng = np.random.default_rng([N, 7])
     A = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
     Hs = A + np.conj(np.swapaxes(A, 1, 2))
     c = gu.ctx()
-    c.tune_set("hetrd_hemv_lower", hemv_lower)
     c.tune_set("hetrd_panel_threads", threads)
-    assert c.tune_get("hetrd_hemv_lower") == hemv_lower and c.tune_get("hetrd_panel_threads") == threads
+    assert c.tune_get("hetrd_panel_threads") == threads
     ev, U, st = run_eigh(c, Hs, lo, hi, ld_pad=1)
     check(Hs, lo, hi, ev, U, st)
     hl = syn.bhz_disordered(10, 2.0, [3, 2, 4])
