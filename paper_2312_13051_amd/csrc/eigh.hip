@@ -399,8 +399,8 @@ __device__ bool load_tridiag(const double *d, const double *e, int64_t q, int64_
 // the selected [lo, hi), their neighbours lo-1 and hi (for the gap test) and
 // the extremes 0 and N-1 (for the scale).
 __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *e, int64_t sDE, int N, int lo, int hi,
-                                                 double *evals, double *lamg, double2 *U, int ldu, int64_t sU,
-                                                 uint32_t *status) {
+                                                 double bis_rel, double *evals, double *lamg, double2 *U, int ldu,
+                                                 int64_t sU, uint32_t *status) {
   extern __shared__ double tsm[];
   double *sd = tsm;          // N
   double *se2 = sd + N;      // N
@@ -452,6 +452,7 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
   const double eps = DBL_EPSILON;
   gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm + 2.0 * pivmin;
+  const double tol_abs = bis_rel * tnorm;
   const int nidx = m + 4;
   for (int t = tid; t < nidx; t += PT) {
     int k;
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
       double a = gl, b = gu;
       for (int it = 0; it < 128; ++it) {
         const double mid = 0.5 * (a + b);
-        if (b - a <= 2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin || mid <= a || mid >= b) break;
+        if (b - a <= fmax(2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin, tol_abs) || mid <= a || mid >= b) break;
         if (sturm_count(sd, se2, N, mid, pivmin) > k) b = mid;
         else a = mid;
       }
@@ -1081,8 +1082,11 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tri_bisect),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(smb)));
     ProfScope prof(ctx, "tri_bisect", stream);
-    hipLaunchKernelGGL(tri_bisect, dim3(nb_mat), dim3(PT), smb, stream, dd, ee, int64_t(N), N, lo, hi, evals, lamg, U,
-                       ldu, us, status);
+    // eigenvalues to eps |lambda|: inverse iteration must separate the
+    // closely spaced ones (bis_rel > 0 would stop at bis_rel ||T||)
+    const double bis_rel = 0.0;
+    hipLaunchKernelGGL(tri_bisect, dim3(nb_mat), dim3(PT), smb, stream, dd, ee, int64_t(N), N, lo, hi, bis_rel, evals,
+                       lamg, U, ldu, us, status);
   }
   BE_RET_IF(check_launch(ctx, "tri_bisect"));
   if (m == 0) return BE_OK;
