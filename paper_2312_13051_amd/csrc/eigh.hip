@@ -19,7 +19,7 @@
 //    supports; lanes that must share a block fall back to Gram-Schmidt. The
 //    vectors are then orthonormalized in FP64 by Newton-Schulz steps on the
 //    Gram matrix (symmetric orthonormalization, MFMA DGEMMs) until
-//    max |Z^T Z - I| < 1e-14 (1e-10 on the mixed path).
+//    max |Z^T Z - I| < 1e-14 (1e-8 on the mixed path).
 // 3. Back-transformation U = Q Z by panels in reverse order with three MFMA
 //    GEMMs each: X = V^H U, Y = T X, U -= V Y.
 // 4. Mixed precision: the reduction and back-transformation run in FP32 on
@@ -1116,10 +1116,10 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   const int64_t ust = mixed ? int64_t(N) * m : us;
   // ---- symmetric orthonormalization of Z (Newton-Schulz on the Gram matrix),
   // Z held as X = Z^T (m x N, leading dim mp); iterated until max |X X^T - I|
-  // is below 1e-14 (FP64 path), or 1e-10 on the mixed path, whose FP32
+  // is below 1e-14 (FP64 path), or 1e-8 on the mixed path, whose FP32
   // back-transformation leaves errors of order 1e-7 anyway
   {
-    const double tol_orth = mixed ? 1e-10 : 1e-14;
+    const double tol_orth = mixed ? 1e-8 : 1e-14;
     const int64_t sZ = int64_t(4) * N * mp;
     double *Xa = Zs + int64_t(3) * N * mp, *Xt = Zs;
     double *hmax = static_cast<double *>(ctx->pinned);
@@ -1172,7 +1172,8 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
         break;
       }
     }
-    hipLaunchKernelGGL(flag_nonorth, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat, 1e-10, status);
+    hipLaunchKernelGGL(flag_nonorth, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat,
+                       std::max(tol_orth, 1e-10), status);
     hipLaunchKernelGGL(z_to_u<C>, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream, Xa, sZ, mp, N, m, Ut, ldt,
                        ust);
     BE_RET_IF(check_launch(ctx, "z_to_u"));
