@@ -187,7 +187,10 @@ struct ZGemm {
   double2 beta = {0.0, 0.0};
   int64_t batch = 0;
   const char *tag = "zgemm";  // profiling label of the call site
-  bool lower = false;         // only tiles on or below the diagonal of C are needed
+  // C (square) is Hermitian and the update keeps it so: only tiles on or
+  // below the diagonal are computed, and each strictly lower tile's conjugate
+  // transpose is written to the upper triangle (the old upper values are not read)
+  bool herm = false;
 };
 
 // C = alpha op(A) op(B) + beta C, FP64 MFMA. C must not alias A or B.
@@ -210,7 +213,7 @@ struct CGemm {
   float2 beta = {0.0f, 0.0f};
   int64_t batch = 0;
   const char *tag = "cgemm";
-  bool lower = false;
+  bool herm = false;  // as in ZGemm
 };
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
 

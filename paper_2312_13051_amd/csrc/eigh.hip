@@ -5,9 +5,11 @@
 //    One workgroup per matrix runs a panel of nb columns (hetrd_panel): for
 //    each column it applies the panel's earlier reflectors to that column,
 //    builds the reflector, forms the matrix-vector product with the trailing
-//    matrix (full square, one wave per 64-row block, v broadcast from LDS) and the
+//    matrix (full square, (64-row block x column slice) work items, v broadcast
+//    from LDS) and the
 //    symmetric rank-2 correction vector w. The trailing matrix is then updated
-//    once per panel by a rank-2nb MFMA GEMM, C -= [V W] [W V]^H. The panel's
+//    once per panel by a rank-2nb MFMA GEMM, C -= [V W] [W V]^H (lower tiles,
+//    mirrored into the upper triangle). The panel's
 //    compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the fly from
 //    the same dot products.
 // 2. FP64 tridiagonal eigensolver (tri_bisect, tri_invit, tri_gs): bisection with Sturm counts,
@@ -1071,6 +1073,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.beta = mk<C>(1.0, 0.0);
       g.batch = nb_mat;
       g.tag = "her2k";
+      g.herm = true;
       BE_RET_IF(GemmOf<T>::run(ctx, g, stream));
     }
   }

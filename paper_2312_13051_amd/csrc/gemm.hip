@@ -62,7 +62,7 @@ struct GP {
   cplx alpha, beta;
   int64_t batch;
   int tiles_m, tiles_n;
-  int lower;  // skip tiles strictly above the diagonal
+  int herm;  // Hermitian C: lower tiles only, strictly lower tiles mirrored into the upper triangle
 };
 
 // BM x BN block tile, WM x WN waves, each wave (BM/WM) x (BN/WN).
@@ -85,7 +85,8 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   const int t2 = static_cast<int>(w - q * tiles);
   const int tm = t2 % p.tiles_m, tn = t2 / p.tiles_m;
   const int i0 = tm * BM, j0 = tn * BN;
-  if (p.lower && i0 + BM <= j0) return;
+  static_assert(BM == BN, "square tiles (Hermitian mode pairs tile (tm, tn) with (tn, tm))");
+  if (p.herm && tm < tn) return;
   const cplx *A = p.A + be::zbatch_off(p.bA, q);
   const cplx *B = p.B + be::zbatch_off(p.bB, q);
   cplx *C = p.C + be::zbatch_off(p.bC, q);
@@ -222,6 +223,11 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
             out.y += p.beta.x * c.y + p.beta.y * c.x;
           }
           C[idx] = out;
+          if (p.herm && tm > tn) {
+            cplx o2 = out;
+            o2.y = -out.y;
+            C[gj + int64_t(gi) * p.ldc] = o2;
+          }
         }
       }
     }
@@ -417,7 +423,7 @@ int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
   p.alpha = g.alpha;
   p.beta = g.beta;
   p.batch = g.batch;
-  p.lower = g.lower ? 1 : 0;
+  p.herm = g.herm ? 1 : 0;
   return dispatch<double>(ctx, p, g.opA, g.opB, stream);
 }
 
@@ -439,7 +445,7 @@ int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
   p.alpha = g.alpha;
   p.beta = g.beta;
   p.batch = g.batch;
-  p.lower = g.lower ? 1 : 0;
+  p.herm = g.herm ? 1 : 0;
   return dispatch<float>(ctx, p, g.opA, g.opB, stream);
 }
 
