@@ -5,13 +5,12 @@
 //    One workgroup per matrix runs a panel of nb columns (hetrd_panel): for
 //    each column it applies the panel's earlier reflectors to that column,
 //    builds the reflector, forms the matrix-vector product with the trailing
-//    matrix (full square, (64-row block x column slice) work items, v broadcast
-//    from LDS) and the
-//    symmetric rank-2 correction vector w. The trailing matrix is then updated
-//    once per panel by a rank-2nb MFMA GEMM, C -= [V W] [W V]^H (lower tiles,
-//    mirrored into the upper triangle). The panel's
-//    compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the fly from
-//    the same dot products.
+//    matrix (full square, (64-row block x column slice) work items, v
+//    broadcast from LDS) and the symmetric rank-2 correction vector w. The
+//    trailing matrix is then updated once per panel by a rank-2nb MFMA GEMM,
+//    C -= [V W] [W V]^H (lower tiles, mirrored into the upper triangle). The
+//    panel's compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the
+//    fly from the same dot products.
 // 2. FP64 tridiagonal eigensolver (tri_bisect, tri_invit, tri_gs): bisection with Sturm counts,
 //    one lane per eigenvalue, for the selected indices and their neighbours;
 //    T is split where an off-diagonal is negligible (an eigenvalue of
@@ -22,8 +21,10 @@
 //    vectors are then orthonormalized in FP64 by Newton-Schulz steps on the
 //    Gram matrix (symmetric orthonormalization, MFMA DGEMMs) until
 //    max |Z^T Z - I| < 1e-14 (1e-8 on the mixed path).
-// 3. Back-transformation U = Q Z by panels in reverse order with three MFMA
-//    GEMMs each: X = V^H U, Y = T X, U -= V Y.
+// 3. Back-transformation U = Q Z by pairs of panels in reverse order, each
+//    pair one compact-WY block of 64 columns, V = [V1 V2],
+//    T = [[T1, -T1 (V1^H V2) T2], [0, T2]], applied with three MFMA GEMMs:
+//    X = V^H U, Y = T X, U -= V Y.
 // 4. Mixed precision: the reduction and back-transformation run in FP32 on
 //    FP32 MFMA; the tridiagonal solve and the orthonormalization stay FP64.
 #include <algorithm>
@@ -976,6 +977,31 @@ __global__ void zero_u32(uint32_t *p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+template <typename C>
+__global__ void zero_c(C *p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = mk<C>(0, 0);
+}
+
+// T of a pair of panels (ld 2 NB): the diagonal blocks T1 (nb1 x nb1) and T2
+// (nb2 x nb2) and the zero lower-left block; the upper-right block is written
+// by a GEMM.
+template <typename C>
+__global__ void assemble_tpair(const C *T1, const C *T2, int64_t sT, C *Tb, int nb1, int nb2) {
+  const int64_t q = blockIdx.x;
+  const int nbc = nb1 + nb2;
+  C *Tq = Tb + q * int64_t(4) * NB * NB;
+  for (int e = threadIdx.x; e < nbc * nbc; e += blockDim.x) {
+    const int i = e % nbc, j = e / nbc;
+    C v;
+    if (i < nb1 && j < nb1) v = T1[q * sT + i + j * NB];
+    else if (i >= nb1 && j >= nb1) v = T2[q * sT + (i - nb1) + (j - nb1) * NB];
+    else if (i >= nb1) v = mk<C>(0, 0);
+    else continue;  // upper-right block: -T1 S12 T2
+    Tq[i + j * (2 * NB)] = v;
+  }
+}
+
 size_t panel_smem(int N, size_t csize, int nt) {
   return (2 * size_t(N) + 4 * NB + NB * NB + nt) * csize + 2 * (nt / 64) * (csize / 2) + 64;
 }
@@ -1027,8 +1053,12 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   cv.add(&Gm, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
   cv.add(&oerr, size_t(nb_mat));
   cv.add(&gmax, 1);
-  cv.add(&Xb, size_t(nb_mat) * NB * std::max(m, 1));
-  cv.add(&Yb, size_t(nb_mat) * NB * std::max(m, 1));
+  cv.add(&Xb, size_t(nb_mat) * 2 * NB * std::max(m, 1));
+  cv.add(&Yb, size_t(nb_mat) * 2 * NB * std::max(m, 1));
+  C *Tb = nullptr, *Sw = nullptr, *Ww = nullptr;  // paired back-transformation: T of a pair, V1^H V2, T1 V1^H V2
+  cv.add(&Tb, size_t(nb_mat) * 4 * NB * NB);
+  cv.add(&Sw, size_t(nb_mat) * NB * NB);
+  cv.add(&Ww, size_t(nb_mat) * NB * NB);
   if (mixed) cv.add(&Uw, size_t(nb_mat) * N * std::max(m, 1));
   BE_RET_IF(cv.commit(ctx, stream, WS_EIGH));
   hipLaunchKernelGGL(zero_u32, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, status, nb_mat);
@@ -1181,63 +1211,75 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
                        ust);
     BE_RET_IF(check_launch(ctx, "z_to_u"));
   }
-  // ---- back-transformation, panels in reverse order
-  for (int p = P - 1; p >= 0; --p) {
-    const int p0 = p * NB, nbp = std::min(NB, N - p0);
+  // ---- back-transformation by pairs of panels (pa, pb = pa + 1), last pair
+  // first; with an odd panel count the first panel runs alone at the end.
+  // Columns p0 .. p0 + nbc of H hold V = [V1 V2] explicitly (zeros above the
+  // unit entries), so one compact-WY block of nbc <= 2 NB columns needs only
+  // T = [[T1, -T1 (V1^H V2) T2], [0, T2]].
+  constexpr int NB2 = 2 * NB;
+  auto gemm = [&](int M_, int N_, int K_, int opA, const C *A_, int lda_, int64_t sA_, const C *B_, int ldb_,
+                  int64_t sB_, C *C_, int ldc_, int64_t sC_, double alpha, double beta) {
+    G g;
+    g.M = M_;
+    g.N = N_;
+    g.K = K_;
+    g.opA = opA;
+    g.opB = 0;
+    g.A = A_;
+    g.lda = lda_;
+    g.bA = ZBatch::strided(sA_);
+    g.B = B_;
+    g.ldb = ldb_;
+    g.bB = ZBatch::strided(sB_);
+    g.C = C_;
+    g.ldc = ldc_;
+    g.bC = ZBatch::strided(sC_);
+    g.alpha = mk<C>(alpha, 0.0);
+    g.beta = mk<C>(beta, 0.0);
+    g.batch = nb_mat;
+    g.tag = "unmtr";
+    return GemmOf<T>::run(ctx, g, stream);
+  };
+  const int64_t sXY = int64_t(NB2) * std::max(m, 1);
+  for (int pb = P - 1; pb >= 0; pb -= 2) {
+    const int pa = pb - 1;
+    const bool pair = pa >= 0;
+    const int p0 = (pair ? pa : pb) * NB;
+    const int nb1 = pair ? NB : 0, nb2 = std::min(NB, N - pb * NB), nbc = nb1 + nb2;
     const int K = N - p0 - 1;
     if (K <= 0) continue;
-    G g1;  // X = V^H U(p0+1:, :)
-    g1.M = nbp;
-    g1.N = m;
-    g1.K = K;
-    g1.opA = 1;
-    g1.opB = 0;
-    g1.A = H + (p0 + 1) + int64_t(p0) * ld;
-    g1.lda = ld;
-    g1.bA = ZBatch::strided(ms);
-    g1.B = Ut + (p0 + 1);
-    g1.ldb = ldt;
-    g1.bB = ZBatch::strided(ust);
-    g1.C = Xb;
-    g1.ldc = NB;
-    g1.bC = ZBatch::strided(int64_t(NB) * m);
-    g1.batch = nb_mat;
-    g1.tag = "unmtr";
-    BE_RET_IF(GemmOf<T>::run(ctx, g1, stream));
-    G g2;  // Y = T X
-    g2.M = nbp;
-    g2.N = m;
-    g2.K = nbp;
-    g2.A = Tm + int64_t(p) * NB * NB;
-    g2.lda = NB;
-    g2.bA = ZBatch::strided(sT);
-    g2.B = Xb;
-    g2.ldb = NB;
-    g2.bB = ZBatch::strided(int64_t(NB) * m);
-    g2.C = Yb;
-    g2.ldc = NB;
-    g2.bC = ZBatch::strided(int64_t(NB) * m);
-    g2.batch = nb_mat;
-    g2.tag = "unmtr";
-    BE_RET_IF(GemmOf<T>::run(ctx, g2, stream));
-    G g3;  // U -= V Y
-    g3.M = K;
-    g3.N = m;
-    g3.K = nbp;
-    g3.A = H + (p0 + 1) + int64_t(p0) * ld;
-    g3.lda = ld;
-    g3.bA = ZBatch::strided(ms);
-    g3.B = Yb;
-    g3.ldb = NB;
-    g3.bB = ZBatch::strided(int64_t(NB) * m);
-    g3.C = Ut + (p0 + 1);
-    g3.ldc = ldt;
-    g3.bC = ZBatch::strided(ust);
-    g3.alpha = mk<C>(-1.0, 0.0);
-    g3.beta = mk<C>(1.0, 0.0);
-    g3.batch = nb_mat;
-    g3.tag = "unmtr";
-    BE_RET_IF(GemmOf<T>::run(ctx, g3, stream));
+    const C *Tblk = Tm + int64_t(pb) * NB * NB;
+    int ldT = NB;
+    int64_t sTb = sT;
+    if (pair) {
+      const int p0b = pb * NB, K12 = N - p0b - 1;
+      // S12 = V1^H V2 (V2 is zero above row p0b + 1)
+      if (K12 > 0) {
+        BE_RET_IF(gemm(nb1, nb2, K12, 1, H + (p0b + 1) + int64_t(p0) * ld, ld, ms, H + (p0b + 1) + int64_t(p0b) * ld,
+                       ld, ms, Sw, NB, int64_t(NB) * NB, 1.0, 0.0));
+      } else {
+        hipLaunchKernelGGL(zero_c<C>, dim3((nb_mat * NB * NB + 255) / 256), dim3(256), 0, stream, Sw,
+                           nb_mat * NB * NB);
+        BE_RET_IF(check_launch(ctx, "zero_c"));
+      }
+      // W = T1 S12; upper-right block of T = -W T2
+      BE_RET_IF(gemm(nb1, nb2, nb1, 0, Tm + int64_t(pa) * NB * NB, NB, sT, Sw, NB, int64_t(NB) * NB, Ww, NB,
+                     int64_t(NB) * NB, 1.0, 0.0));
+      BE_RET_IF(gemm(nb1, nb2, nb2, 0, Ww, NB, int64_t(NB) * NB, Tm + int64_t(pb) * NB * NB, NB, sT,
+                     Tb + int64_t(nb1) * NB2, NB2, int64_t(NB2) * NB2, -1.0, 0.0));
+      hipLaunchKernelGGL(assemble_tpair<C>, dim3(static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream,
+                         Tm + int64_t(pa) * NB * NB, Tm + int64_t(pb) * NB * NB, sT, Tb, nb1, nb2);
+      BE_RET_IF(check_launch(ctx, "assemble_tpair"));
+      Tblk = Tb;
+      ldT = NB2;
+      sTb = int64_t(NB2) * NB2;
+    }
+    // X = V^H U(p0+1:, :), Y = T X, U(p0+1:, :) -= V Y
+    BE_RET_IF(gemm(nbc, m, K, 1, H + (p0 + 1) + int64_t(p0) * ld, ld, ms, Ut + (p0 + 1), ldt, ust, Xb, NB2, sXY,
+                   1.0, 0.0));
+    BE_RET_IF(gemm(nbc, m, nbc, 0, Tblk, ldT, sTb, Xb, NB2, sXY, Yb, NB2, sXY, 1.0, 0.0));
+    BE_RET_IF(gemm(K, m, nbc, 0, H + (p0 + 1) + int64_t(p0) * ld, ld, ms, Yb, NB2, sXY, Ut + (p0 + 1), ldt, ust,
+                   -1.0, 1.0));
   }
   if (mixed) {
     hipLaunchKernelGGL(widen_u, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream,
@@ -1257,11 +1299,11 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
   const size_t cs = sizeof(typename CT<T>::c);
-  const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 2 * size_t(NB) * std::max(m, 1) +
-                           size_t(N) * std::max(m, 1)) +
+  const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 4 * size_t(NB) * std::max(m, 1) +
+                           6 * size_t(NB) * NB + size_t(N) * std::max(m, 1)) +
                      sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) +
                                        size_t(m) + 1) +
-                     sizeof(int) * size_t(std::max(m, 1)) + 13 * 256;
+                     sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
   const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
