@@ -66,7 +66,8 @@ extern "C" {
 
 /* ---- status bits (per matrix or per system) ---- */
 #define BE_ST_GAP_CLOSED 1u         /* selected bands touch their neighbours       */
-#define BE_ST_OVERLAP_SINGULAR 2u   /* an overlap has smallest singular value < 1e-8 */
+#define BE_ST_OVERLAP_SINGULAR 2u   /* an overlap has smallest singular value < 1e-8 (polar mode: the
+                                        Newton-Schulz iteration needs more steps than sigma = 1e-8 does) */
 #define BE_ST_WINDING_UNRESOLVED 4u /* transverse step of Phi > 0.8 pi or non-integer */
 #define BE_ST_PSO_GAP 8u            /* projected spin spectrum touches 0 or its sign
                                        count varies over the grid                  */

@@ -416,7 +416,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
     double *hmax = static_cast<double *>(ctx->pinned);
     int it = 0;
     bool converged = false;
-    for (; it < 80; ++it) {
+    for (; it < 51; ++it) {  // sigma_min = 1e-8 converges at the 51st check
       BE_HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), stream));
       ZGemm g;  // G = X^H X
       g.M = m;
@@ -458,14 +458,12 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       if (e < 1e-30) break;  // already unitary to working precision
       BE_RET_IF(zgemm(ctx, h, stream));
       std::swap(X, Xn);
-      if (e < 1e-9) {
-        // quadratic convergence: one more step after this brings the
-        // error below 1e-17 relative; stop after it
-        if (e < 1e-13) {
-          converged = true;
-          ++it;
-          break;
-        }
+      if (e < 1e-7) {
+        // quadratic convergence: the step just taken leaves a Gram error of
+        // about (3/4) e^2 < 1e-14
+        converged = true;
+        ++it;
+        break;
       }
     }
     if (X != F) {
@@ -474,9 +472,10 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       BE_RET_IF(check_launch(ctx, "copy_mats"));
     }
     (void)converged;
-    // matrices whose Gram error never fell below 1e-9 are (near) singular
+    // matrices whose Gram error before the last step stayed above 1e-7 did
+    // not converge: (near) singular overlaps
     hipLaunchKernelGGL(k_flag_err, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, err,
-                       n_lines, n_loop, 1e-9, BE_ST_OVERLAP_SINGULAR, line_status);
+                       n_lines, n_loop, 1e-7, BE_ST_OVERLAP_SINGULAR, line_status);
     BE_RET_IF(check_launch(ctx, "flag_err"));
   }
   if (Fkeep) *Fkeep = F;

@@ -118,3 +118,20 @@ def test_uneven_sizes_one_call_per_size():
             for r, h in enumerate(group):
                 ref = orc.wilson_surface(h, kg, 0, N // 2)
                 assert phase_set_error(out["theta"][r].cpu().numpy(), ref["theta"]) < 1e-10
+
+
+def test_singular_overlap_flag_matches_oracle():
+    """The occupied state switches orbital between two grid points (two
+    uncoupled orbitals with energies cos 2 pi k and -cos 2 pi k), so the
+    overlap across the switch vanishes: OVERLAP_SINGULAR on the GPU as in
+    the oracle, whose criterion is a smallest singular value below 1e-8."""
+    gu.need_gpu()
+    from synthetic.models import _from_blocks
+    P = pipe()
+    c = gu.ctx()
+    hl = _from_blocks(2, 1, {(0,): np.zeros((2, 2)), (1,): np.diag([0.5, -0.5])})
+    kg = syn.kplane(8, 2, k0=(1.0 / 16, 0.0, 0.0))
+    ref = orc.wilson_surface(hl, kg, 0, 1)
+    assert ref["status"] & 2
+    out = P.wsurf(c, [hl], kg, 0, 1)
+    assert int(out["status"][0]) & 2

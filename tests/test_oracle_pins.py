@@ -336,3 +336,17 @@ def test_choti_spin_chern_matches_paper():
     x = np.sort(np.mod(th.ravel() / (2 * np.pi), 1.0))
     gaps = np.diff(np.concatenate([x, [x[0] + 1]]))
     assert gaps.max() > 0.2
+
+
+def test_singular_overlap_flagged():
+    """Uncoupled orbitals with energies +-cos 2 pi k: the occupied state jumps
+    from one orbital to the other between grid points, the overlap there is
+    exactly zero and the loop is flagged instead of given a phase."""
+    from synthetic.models import _from_blocks
+    hl = _from_blocks(2, 1, {(0,): np.zeros((2, 2)), (1,): np.diag([0.5, -0.5])})
+    kg = syn.kplane(8, 2, k0=(1.0 / 16, 0.0, 0.0))
+    out = orc.wilson_surface(hl, kg, 0, 1)
+    assert out["status"] & orc.OVERLAP_SINGULAR
+    # a smooth path (no switch) is not flagged
+    out = orc.wilson_surface(syn.qwz(1.5), syn.kplane(16, 4), 0, 1)
+    assert not out["status"] & orc.OVERLAP_SINGULAR
