@@ -350,3 +350,64 @@ def test_singular_overlap_flagged():
     # a smooth path (no switch) is not flagged
     out = orc.wilson_surface(syn.qwz(1.5), syn.kplane(16, 4), 0, 1)
     assert not out["status"] & orc.OVERLAP_SINGULAR
+
+
+# ---------------------------------------------------------------- Berry flux per plaquette
+@pytest.mark.parametrize("m,C", [(-1.0, 1), (1.5, -1), (2.5, 0)])
+def test_plaquette_flux_chern_equals_wilson_winding(m, C):
+    """The plaquette sum is 2 pi times an integer to rounding, and it is the
+    Chern number of the Wilson-loop winding (eq. 6) for QWZ in each phase."""
+    kg = syn.kplane(24, 20, e_par=(0, 1, 0), e_perp=(1, 0, 0))
+    f = orc.plaquette_flux(syn.qwz(m), kg, 0, 1)
+    assert f["status"] == 0
+    assert abs(f["total"] - round(f["total"])) < 1e-12
+    assert f["chern"] == C
+    assert orc.wilson_surface(syn.qwz(m), kg, 0, 1)["winding"] == C
+
+
+def test_plaquette_flux_converges_to_two_band_curvature():
+    """Closed form for a two-band model H = d(k).sigma: the Berry curvature of
+    the lower band is (1/2) d.(d_x d x d_y d)/|d|^3 up to the orientation,
+    so the flux per plaquette approaches it times the plaquette area."""
+    n = 48
+    M = -1.0
+    kg = syn.kplane(n, n, e_par=(0, 1, 0), e_perp=(1, 0, 0))
+    F = orc.plaquette_flux(syn.qwz(M), kg, 0, 1)["flux"]      # [i (kx), j (ky)]
+    kx = 2 * np.pi * (np.arange(n) + 0.5) / n
+    KX, KY = np.meshgrid(kx, kx, indexing="ij")
+    d = np.stack([np.sin(KX), np.sin(KY), M + np.cos(KX) + np.cos(KY)])
+    dx = np.stack([np.cos(KX), 0 * KX, -np.sin(KX)])
+    dy = np.stack([0 * KY, np.cos(KY), -np.sin(KY)])
+    omega = 0.5 * np.einsum("i...,i...->...", d, np.cross(dx, dy, axis=0)) / np.linalg.norm(d, axis=0) ** 3
+    ref = omega * (2 * np.pi / n) ** 2
+    sign = np.sign(np.sum(F * ref))
+    assert sign != 0
+    assert np.max(np.abs(F - sign * ref)) < 0.02 * np.max(np.abs(F))
+    assert abs(sign * ref.sum() / (2 * np.pi) - round(F.sum() / (2 * np.pi))) < 0.02
+
+
+def test_plaquette_flux_trivial_and_gauge_invariant():
+    """An atomic insulator carries no flux; random unitary rotations of the
+    occupied basis at every k leave every plaquette's flux unchanged."""
+    kg = syn.kplane(6, 5)
+    f = orc.plaquette_flux(syn.atomic([-1.0, -0.5, 2.0]), kg, 0, 2)
+    assert np.max(np.abs(f["flux"])) < 1e-14 and f["chern"] == 0
+    hl = syn.bhz_disordered(2, 1.0, [7, 7, 7])
+    ev, U, st = orc.eigh_grid(hl, kg, 0, hl.N // 2)
+    rng = np.random.default_rng(3)
+    R = np.linalg.qr(rng.standard_normal(U.shape[:2] + (U.shape[-1],) * 2)
+                     + 1j * rng.standard_normal(U.shape[:2] + (U.shape[-1],) * 2))[0]
+    a = orc.plaquette_flux_from_grid(U)["flux"]
+    b = orc.plaquette_flux_from_grid(U @ R)["flux"]
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_spin_resolved_flux_bhz():
+    """Spin sectors of BHZ (Sec. IV): C_dn = -1, C_up = +1, C_s = +1, the
+    values the spin-resolved Wilson loop gives."""
+    kg = syn.kplane(16, 16)
+    out = orc.spin_resolved_flux(syn.bhz(), np.array([1.0, -1, -1, 1]), kg, 0, 2)
+    assert out["status"] == 0
+    assert (out["C_dn"], out["C_up"], out["C_s"]) == (-1, 1, 1.0)
+    w = orc.spin_resolved_wilson(syn.bhz(), np.array([1.0, -1, -1, 1]), kg, 0, 2)
+    assert (w["C_dn"], w["C_up"]) == (out["C_dn"], out["C_up"])
