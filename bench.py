@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 import synthetic as syn  # noqa: E402
 
 METRIC = "Wilson-loop k-point solves/s at ≤1e-6 phase err vs FP64; p50/p99 latency"
+METRIC_FLUX = "Berry-flux (plaquette) k-point solves/s at ≤1e-6 flux err vs FP64; p50/p99 latency"
 L_SC, N_PAR, N_PERP = 10, 24, 24
 W_VALUES = (0.0, 1.0, 2.0, 3.0)
 REALIZATIONS = 16
@@ -76,16 +77,29 @@ def _oracle_line(args):
     return (w_idx, r, i, out[0], out[1])
 
 
-def cpu_baseline(sample, workers):
+def _oracle_strip(args):
+    """Spin-resolved Berry flux of one row of plaquettes (k-point rows i and
+    i + 1, all j) with the FP64 oracle: row 0 of the 2-row grid's maps."""
+    w_idx, r, i = args
+    from oracle import berry as orc
+    hl = syn.bhz_disordered(L_SC, W_VALUES[w_idx], [3, w_idx, r])
+    kg = syn.kplane(N_PAR, N_PERP)
+    out = orc.spin_resolved_flux(hl, syn.bhz_spin_diag(hl), kg[[i, (i + 1) % N_PERP]], 0, hl.N // 2)
+    if out["status"] & orc.PSO_GAP:
+        return (w_idx, r, i, None, None)
+    return (w_idx, r, i, out["flux_dn"][0], out["flux_up"][0])
+
+
+def cpu_baseline(sample, workers, fn=_oracle_line):
     ctx = mp.get_context("spawn")
     old = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     try:
         with ctx.Pool(workers) as pool:
-            pool.map(_oracle_line, sample[:workers])  # warm the workers (imports)
+            pool.map(fn, sample[:workers])  # warm the workers (imports)
             t0 = time.perf_counter()
-            res = pool.map(_oracle_line, sample)
+            res = pool.map(fn, sample)
             dt = time.perf_counter() - t0
     finally:
         if old is None:
@@ -135,7 +149,19 @@ def gemm_phase_flops(N, m, n_par, n_k_sys, m_dn):
         "spin_sector": 8.0 * N * m * m * nk,               # U [Q- Q+]
         "overlap": float(np.sum(8.0 * N * (md ** 2 + mu ** 2))) * n_k_sys,
         "chain": float(np.sum(8.0 * (md ** 3 + mu ** 3))) * (n_par - 1) / n_par * n_k_sys,
+        "flux_links": 2.0 * float(np.sum(8.0 * N * (md ** 2 + mu ** 2))) * n_k_sys,   # both directions
     }
+
+
+def det_phase_flops(m_dn, m, n_k_sys):
+    """Algorithmic flops of the link determinants (LU, 8 flops per complex
+    multiply-add, sum over k of (ms - k - 1)^2 updates): both sectors, both
+    directions."""
+    tot = 0.0
+    for md in m_dn:
+        for ms in (md, m - md):
+            tot += 8.0 * sum((ms - k - 1) ** 2 for k in range(ms))
+    return 2.0 * n_k_sys * tot
 
 
 PANEL_SRC_BEGIN = "// ---------------------------------------------------------------- reductions"
@@ -172,6 +198,9 @@ def traffic_from_profile(path, source, precision):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["spin_wilson", "spin_flux"], default="spin_wilson",
+                    help="spin_wilson: spin-resolved Wilson loops (the headline metric); spin_flux: spin-resolved "
+                         "Berry flux per plaquette (coupling-matrix method) on the same systems and grid")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk-systems", type=int, default=8)
@@ -206,14 +235,27 @@ def main():
         for r in rng.choice(REALIZATIONS, size=2, replace=False):
             for i in rng.choice(N_PERP, size=max(1, args.cpu_lines // 8), replace=False):
                 sample.append((w_idx, int(r), int(i)))
+    flux_wl = args.workload == "spin_flux"
+    if flux_wl:
+        sample = sample[:max(1, len(sample) // 2)]
     cpu = None
     oracle_res = []
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1, len(sample)))
-        oracle_res, cdt = cpu_baseline(sample, workers)
-        cpu = {"value": len(sample) * N_PAR / cdt, "unit": "k-point solves/s", "cores": workers, "kind": "oracle",
-               "sample": f"{len(sample)} transverse lines ({len(sample) * N_PAR} k-points) of the same workload, "
-                         f"NumPy/LAPACK FP64, one worker process per core, OMP_NUM_THREADS=1, wall {cdt:.2f} s"}
+        if flux_wl:
+            oracle_res, cdt = cpu_baseline(sample, workers, _oracle_strip)
+            cpu = {"value": len(sample) * N_PAR / cdt, "unit": "k-point solves/s", "cores": workers,
+                   "kind": "oracle",
+                   "sample": f"{len(sample)} rows of plaquettes ({len(sample) * N_PAR} plaquettes, "
+                             f"{2 * len(sample) * N_PAR} eigensolves) of the same workload, NumPy/LAPACK FP64, "
+                             f"one worker process per core, OMP_NUM_THREADS=1, wall {cdt:.2f} s"}
+        else:
+            oracle_res, cdt = cpu_baseline(sample, workers)
+            cpu = {"value": len(sample) * N_PAR / cdt, "unit": "k-point solves/s", "cores": workers,
+                   "kind": "oracle",
+                   "sample": f"{len(sample)} transverse lines ({len(sample) * N_PAR} k-points) of the same "
+                             f"workload, NumPy/LAPACK FP64, one worker process per core, OMP_NUM_THREADS=1, "
+                             f"wall {cdt:.2f} s"}
 
     import torch
     from paper_2312_13051_amd import _lib as L
@@ -254,6 +296,12 @@ def main():
     csp = torch.empty(n_sys, dtype=torch.float64, device=dev)
     sst = torch.empty(n_sys, dtype=torch.int32, device=dev)
     eig_bad = torch.zeros(n_sys, dtype=torch.int32, device=dev)
+    if flux_wl:
+        V = torch.empty((nmat, m, N), dtype=torch.complex128, device=dev)
+        fdn = torch.empty((n_sys, N_PERP, N_PAR), dtype=torch.float64, device=dev)
+        fup = torch.empty((n_sys, N_PERP, N_PAR), dtype=torch.float64, device=dev)
+        ftot = torch.empty((2, n_sys), dtype=torch.float64, device=dev)
+        fst = torch.empty((3, n_sys), dtype=torch.int32, device=dev)
     mdn_all = [0] * n_sys
     chunk_lat = []
 
@@ -264,8 +312,24 @@ def main():
             ctx.build_hk(plan, s0, ns, kap, H, N * N, N, hcode)
             ctx.eigh_batched(H, hcode, N, N, N * N, ns * n_k, 0, m, prec, ev, U, N, U.stride(0), est)
             eig_bad[s0:s0 + ns] = est[:ns * n_k].view(ns, n_k).ne(0).any(dim=1).to(torch.int32)
-            md = ctx.spin_resolved_wilson(U, N, m, N, U.stride(0), ns, N_PAR, N_PERP, L.BE_OVL_POLAR, spin[s0:],
-                                          pso[s0:], tdn[s0:], tup[s0:], cdn[s0:], cup[s0:], csp[s0:], sst[s0:], prec)
+            if flux_wl:
+                md = ctx.spin_sectors(U, N, m, N, U.stride(0), ns, n_k, spin[s0:], pso[s0:], V, N, V.stride(0),
+                                      fst[0, s0:], prec)
+                a = 0
+                while a < ns:  # runs of systems with equal sector sizes
+                    b = a + 1
+                    while b < ns and md[b] == md[a]:
+                        b += 1
+                    ctx.plaquette_flux(V[a * n_k:], N, md[a], N, V.stride(0), b - a, N_PAR, N_PERP,
+                                       fdn[s0 + a:], cdn[s0 + a:], ftot[0, s0 + a:], fst[1, s0 + a:])
+                    ctx.plaquette_flux(V[a * n_k:, md[a] if md[a] < m else 0:], N, m - md[a], N, V.stride(0),
+                                       b - a, N_PAR, N_PERP, fup[s0 + a:], cup[s0 + a:], ftot[1, s0 + a:],
+                                       fst[2, s0 + a:])
+                    a = b
+            else:
+                md = ctx.spin_resolved_wilson(U, N, m, N, U.stride(0), ns, N_PAR, N_PERP, L.BE_OVL_POLAR,
+                                              spin[s0:], pso[s0:], tdn[s0:], tup[s0:], cdn[s0:], cup[s0:], csp[s0:],
+                                              sst[s0:], prec)
             mdn_all[s0:s0 + ns] = md
             if record:
                 torch.cuda.synchronize()
@@ -303,7 +367,7 @@ def main():
     roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
             "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
     flops = gemm_phase_flops(N, m, N_PAR, n_k, mdn_all)
-    fp32_tags = ("her2k", "unmtr") if mixed else ()
+    fp32_tags = ("her2k", "unmtr", "pso_her2k", "pso_unmtr") if mixed else ()
     if name == "hetrd_panel":
         elem = 8 if mixed else 16
         byts = hetrd_panel_bytes(N, total_k, elem) * steps
@@ -313,6 +377,11 @@ def main():
         roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": round(byts / launches, 1)})
+    elif name == "det_phase":
+        fl = det_phase_flops(mdn_all, m, n_k) * steps
+        ach = fl / (ms_tot * 1e-3) / 1e12
+        roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / FP64_PEAK_TFLOPS, 4)})
     elif name in flops:
         pk = FP32_PEAK_TFLOPS if name in fp32_tags else FP64_PEAK_TFLOPS
         ach = flops[name] * steps / (ms_tot * 1e-3) / 1e12
@@ -337,7 +406,17 @@ def main():
 
     # ---- phase error of the sampled lines against the FP64 oracle
     max_err = None
-    if oracle_res:
+    if oracle_res and flux_wl:
+        fdn_h, fup_h = fdn.cpu().numpy(), fup.cpu().numpy()
+        errs = []
+        for (w_idx, r, i, a, b) in oracle_res:
+            if a is None:
+                continue
+            s = w_idx * REALIZATIONS + r
+            for g, ref in ((fdn_h[s, i], a), (fup_h[s, i], b)):
+                errs.append(float(np.max(np.abs(np.mod(g - ref + np.pi, 2 * np.pi) - np.pi))))
+        max_err = float(max(errs)) if errs else None
+    elif oracle_res:
         from tests.phase_metrics import phase_set_error
         tdn_h, tup_h = tdn.cpu().numpy(), tup.cpu().numpy()
         errs = []
@@ -350,10 +429,13 @@ def main():
                 errs.append(phase_set_error(tup_h[s, i, :m - md], b))
         max_err = float(max(errs)) if errs else None
 
+    if flux_wl:
+        csp.copy_(0.5 * (cup - cdn).to(torch.float64))
+        sst.copy_(fst[0] | fst[1] | fst[2])
     st = sst.cpu().numpy() | eig_bad.cpu().numpy()
     lat = np.array(chunk_lat) * 1e3
     out = {
-        "metric": METRIC,
+        "metric": METRIC if not flux_wl else METRIC_FLUX,
         "value": round(value, 1),
         "unit": "k-point solves/s",
         "n_gpus": 1,
@@ -366,8 +448,10 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "BHZ 10x10 supercell (N=400) with Anderson disorder W in {0,1,2,3} x 16 seeded "
-                               "realizations, 24x24 supercell k-grid, half filling, spin-resolved Wilson loop "
-                               "(eig of P S_z P), " + ("mixed path: FP32 Householder reduction and "
+                               "realizations, 24x24 supercell k-grid, half filling, " +
+                               ("spin-resolved Berry flux per plaquette (coupling-matrix method, eig of P S_z P, "
+                                "link determinants in both directions), " if flux_wl else
+                                "spin-resolved Wilson loop (eig of P S_z P), ") + ("mixed path: FP32 Householder reduction and "
                                "back-transformation on MFMA, FP64 elsewhere" if mixed else "FP64 path"),
                    "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs, "tuning": tuning},
         "roofline": roof,
@@ -375,7 +459,7 @@ def main():
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
                        "unit": f"per chunk of {cs} systems ({cs * n_k} k-points)"},
-        "phase_err_vs_fp64_oracle_rad": max_err,
+        ("flux_err_vs_fp64_oracle_rad" if flux_wl else "phase_err_vs_fp64_oracle_rad"): max_err,
         "phase_gate_1e-6_ok": (max_err is not None and max_err <= 1e-6),
         "valid_systems": int((st == 0).sum()),
         "spin_chern_W0": [float(x) for x in csp.cpu().numpy()[:REALIZATIONS]][:4],

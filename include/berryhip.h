@@ -211,6 +211,47 @@ int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, in
                             double *pso_evals, double *theta_dn, double *theta_up, int32_t *C_dn, int32_t *C_up,
                             double *C_s, int32_t *m_dn_h, uint32_t *status, hipStream_t stream);
 
+/* Berry flux per plaquette (the coupling-matrix method of the disordered
+ * quadrupolar-insulator example, Sec. IV: the zone is cut into plaquettes and
+ * the flux through each is integrated along its closed boundary; applied
+ * there to the occupied space and to its spin sectors). On a U-grid (the
+ * layout above, U c128), with link phases
+ *   phi_par(i, j)  = arg det(U(i, j+1)^H U(i, j)),
+ *   phi_perp(i, j) = arg det(U(i+1, j)^H U(i, j))   (both periodic),
+ * the flux through the plaquette with corners (i, j), (i, j+1), (i+1, j+1),
+ * (i+1, j) is
+ *   F(i, j) = wrap(phi_par(i+1, j) - phi_par(i, j) + phi_perp(i, j) - phi_perp(i, j+1))
+ * in (-pi, pi], oriented so that its sum over the zone is 2 pi times the
+ * winding of eq. 6 (be_wilson_loop's on the same grid). Outputs (device):
+ *   flux [n_sys][n_perp][n_par], total [n_sys] = sum F / 2 pi (an integer
+ *   to rounding: every link enters two plaquettes with opposite signs),
+ *   chern [n_sys] = the nearest integer, status [n_sys]:
+ *   OVERLAP_SINGULAR if some link has |det| < 1e-8 (its phase is then
+ *   undetermined; |det| never exceeds the link's smallest singular value),
+ *   WINDING_UNRESOLVED if some |F| > 0.8 pi or |total - chern| > 1e-6
+ *   (the grid is too coarse for the flux), NAN_INF (non-finite flux; chern 0).
+ * m = 0 gives zero flux; m > 2544 is rejected (BE_EINVAL). The links of one direction for as many systems as
+ * fit in about 1 GiB are held in the context's workspace (at least one
+ * system, n_par*n_perp*m*m*16 bytes). */
+int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                      int32_t n_sys, int32_t n_par, int32_t n_perp, double *flux, int32_t *chern, double *total,
+                      uint32_t *status, hipStream_t stream);
+
+/* Spin-sector bases of the occupied space (Sec. IV): the projected spin
+ * operator and its eigendecomposition exactly as in be_spin_resolved_wilson,
+ * on n_k_sys k-points per system (U matrix (s, k) at (s*n_k_sys + k)*u_stride),
+ * and V = U Q with the columns in ascending mu: the first m_dn_h[s] columns
+ * span the spin-down sector (mu < 0), the rest the spin-up sector.
+ *   pso_evals [n_sys][n_k_sys][m], V + (s*n_k_sys + k)*v_stride: N x m
+ *   (c128, leading dimension ldv >= N; V must not overlap U), m_dn_h [n_sys]
+ *   (host), status [n_sys] (PSO_GAP, NAN_INF, NONCONVERGED).
+ * Sector flux maps: be_plaquette_flux on V (m_dn_h[s] columns) and on
+ * V + m_dn_h[s]*ldv (m - m_dn_h[s] columns), with ldu = ldv, u_stride = v_stride.
+ * Synchronizes the stream once (the sector sizes are read back). */
+int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride, int32_t n_sys,
+                    int32_t n_k_sys, int32_t precision, const double *spin_diag, double *pso_evals, void *V,
+                    int32_t ldv, int64_t v_stride, int32_t *m_dn_h, uint32_t *status, hipStream_t stream);
+
 /* Launch timing (tracing aid). While enabled, every library launch is
  * bracketed by a pair of hipEvents recorded on its own stream, keyed by the
  * kernel or GEMM call-site name ("hk_scatter", "hetrd_panel", "her2k",

@@ -352,19 +352,21 @@ def link_phases(U_grid: np.ndarray):
     """Phases of the link variables det(U(k')^H U(k)) between neighbouring
     grid points, along the loop direction (k' = k(i, j+1)) and across it
     (k' = k(i+1, j)), both closing periodically. Returns (phi_par, phi_perp,
-    smallest singular value of any link)."""
+    smallest |det| of any link). A link variable det/|det| is undetermined
+    when |det| vanishes; |det| is the product of the link's singular values,
+    none above 1, so it never exceeds the smallest one."""
     n_perp, n_par = U_grid.shape[:2]
     phi_par = np.empty((n_perp, n_par))
     phi_perp = np.empty((n_perp, n_par))
-    smin = np.inf
+    dmin = np.inf
     for i in range(n_perp):
         for j in range(n_par):
             for phi, Un in ((phi_par, U_grid[i, (j + 1) % n_par]), (phi_perp, U_grid[(i + 1) % n_perp, j])):
                 L = Un.conj().T @ U_grid[i, j]
-                phi[i, j] = np.angle(np.linalg.det(L))
-                if L.size:
-                    smin = min(smin, float(np.linalg.svd(L, compute_uv=False).min()))
-    return phi_par, phi_perp, smin
+                d = np.linalg.det(L)
+                phi[i, j] = np.angle(d)
+                dmin = min(dmin, float(abs(d)))
+    return phi_par, phi_perp, dmin
 
 
 def plaquette_flux_from_grid(U_grid: np.ndarray):
@@ -382,13 +384,13 @@ def plaquette_flux_from_grid(U_grid: np.ndarray):
     over the zone is an exact multiple of 2 pi (the Chern number).
     Returns flux (n_perp, n_par), chern (int), total (sum / 2 pi), status.
     """
-    phi_par, phi_perp, smin = link_phases(U_grid)
+    phi_par, phi_perp, dmin = link_phases(U_grid)
     F = np.roll(phi_par, -1, axis=0) - phi_par + phi_perp - np.roll(phi_perp, -1, axis=1)
     F = F - TWO_PI * np.round(F / TWO_PI)
     F = np.where(F <= -np.pi, np.pi, F)
     total = F.sum() / TWO_PI
     status = 0
-    if smin < 1e-8:
+    if dmin < 1e-8:
         status |= OVERLAP_SINGULAR
     if np.max(np.abs(F)) > 0.8 * np.pi or abs(total - np.round(total)) > 1e-6:
         status |= WINDING_UNRESOLVED

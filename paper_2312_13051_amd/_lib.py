@@ -27,7 +27,7 @@ EXPORTS = [
     "be_create", "be_destroy", "be_last_error", "be_workspace_bytes",
     "be_hk_plan_create", "be_hk_plan_destroy", "be_hk_plan_N",
     "be_build_hk", "be_eigh_batched", "be_wilson_loop", "be_nested_wilson",
-    "be_spin_resolved_wilson", "be_zgemm_strided",
+    "be_spin_resolved_wilson", "be_plaquette_flux", "be_spin_sectors", "be_zgemm_strided",
     "be_profile_enable", "be_profile_query", "be_profile_names", "be_tune_set", "be_tune_get",
 ]
 
@@ -70,6 +70,9 @@ def load():
                                      vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.be_spin_resolved_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp]
+    lib.be_plaquette_flux.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.be_spin_sectors.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, vp, vp, vp, i32, i64,
+                                    C.POINTER(i32), vp, vp]
     lib.be_zgemm_strided.argtypes = [vp, C.c_char, C.c_char, i32, i32, i32, f64p, vp, i32, i64, vp, i32, i64,
                                      f64p, vp, i32, i64, i32, vp]
     lib.be_profile_enable.argtypes = [vp, C.c_int]
@@ -185,6 +188,18 @@ class Context:
                                                      mode, precision, _ptr(spin_diag), _ptr(pso_evals), _ptr(theta_dn),
                                                      _ptr(theta_up), _ptr(C_dn), _ptr(C_up), _ptr(C_s), m_dn,
                                                      _ptr(status), _stream()))
+        return [int(x) for x in m_dn]
+
+    def plaquette_flux(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status):
+        self._check(self.lib.be_plaquette_flux(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
+                                               _ptr(flux), _ptr(chern), _ptr(total), _ptr(status), _stream()))
+
+    def spin_sectors(self, U, N, m, ldu, u_stride, n_sys, n_k_sys, spin_diag, pso_evals, V, ldv, v_stride, status,
+                     precision=BE_FP64):
+        m_dn = (C.c_int32 * n_sys)()
+        self._check(self.lib.be_spin_sectors(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_k_sys, precision,
+                                             _ptr(spin_diag), _ptr(pso_evals), _ptr(V), ldv, v_stride, m_dn,
+                                             _ptr(status), _stream()))
         return [int(x) for x in m_dn]
 
     def tune_set(self, knob: str, value: int):

@@ -856,45 +856,20 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 
 }  // namespace
 
-extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
-                                       int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, int32_t precision,
-                                       const double *spin_diag, double *pso_evals, double *theta_dn, double *theta_up,
-                                       int32_t *C_dn, int32_t *C_up, double *C_s, int32_t *m_dn_h, uint32_t *status,
-                                       hipStream_t stream) {
+namespace {
+
+// The projected spin operator A = U^H S U of every k-point and its
+// eigendecomposition (mu ascending, eigenvectors Q, m x m per k-point), the
+// per-k PSO_GAP test and the per-system spin-down sector size m_dn_h (read
+// back, so the stream is synchronized once).
+int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride, int32_t n_sys,
+                      int64_t kps, int32_t precision, const double *spin_diag, double *pso_evals, double2 *SU,
+                      double2 *A, double2 *Q, double *ev, uint32_t *kst, int32_t *cnt, int32_t *mdn, int32_t *m_dn_h,
+                      uint32_t *status, hipStream_t stream) {
   using namespace be;
-  BE_RET_IF(check_grid_args(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode));
-  BE_CHECK_ARG(ctx, spin_diag && pso_evals && theta_dn && theta_up && C_dn && C_up && C_s && m_dn_h && status,
-               "be_spin_resolved_wilson: null argument");
-  BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_resolved_wilson: at most 1024 systems per call");
-  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32, "be_spin_resolved_wilson: bad precision");
-  if (n_sys == 0) return BE_OK;
-  const int64_t kps = int64_t(n_par) * n_perp;
   const int64_t n_k = int64_t(n_sys) * kps;
-  const int64_t n_lines = int64_t(n_sys) * n_perp;
   const int64_t mm = int64_t(m) * std::max(m, 1);
   const int64_t Nm = int64_t(N) * std::max(m, 1);
-  double2 *SU = nullptr, *A = nullptr, *Q = nullptr, *V = nullptr;
-  double *ev = nullptr;
-  uint32_t *kst = nullptr, *lst = nullptr;
-  int32_t *cnt = nullptr, *mdn = nullptr;
-  Carve cv;
-  cv.add(&SU, size_t(n_k * Nm));
-  cv.add(&A, size_t(n_k * mm));
-  cv.add(&Q, size_t(n_k * mm));
-  cv.add(&V, size_t(n_k * Nm));
-  cv.add(&ev, size_t(n_k * (m + 2)));
-  cv.add(&kst, size_t(n_k));
-  cv.add(&lst, size_t(2 * n_lines));
-  cv.add(&cnt, size_t(n_k));
-  cv.add(&mdn, size_t(n_sys));
-  BE_RET_IF(cv.commit(ctx, stream, WS_OUTER));
-  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
-                     int64_t(n_sys));
-  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((2 * n_lines + 255) / 256)), dim3(256), 0, stream, lst,
-                     2 * n_lines);
-  BE_RET_IF(check_launch(ctx, "zero"));
-  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
-  if (m == 0) return BE_OK;
   // ---- A = U^H S U
   hipLaunchKernelGGL(k_spin_scale, dim3(64, static_cast<uint32_t>(std::min<int64_t>(n_k, 65535))), dim3(256), 0, stream,
                      static_cast<const double2 *>(U), ldu, u_stride, spin_diag, N, m, kps, n_k, SU);
@@ -941,6 +916,52 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   BE_HIP_TRY(ctx, hipMemcpyAsync(hm, mdn, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost, stream));
   BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
   for (int s = 0; s < n_sys; ++s) m_dn_h[s] = hm[s];
+  return BE_OK;
+}
+
+}  // namespace
+
+extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                                       int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, int32_t precision,
+                                       const double *spin_diag, double *pso_evals, double *theta_dn, double *theta_up,
+                                       int32_t *C_dn, int32_t *C_up, double *C_s, int32_t *m_dn_h, uint32_t *status,
+                                       hipStream_t stream) {
+  using namespace be;
+  BE_RET_IF(check_grid_args(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode));
+  BE_CHECK_ARG(ctx, spin_diag && pso_evals && theta_dn && theta_up && C_dn && C_up && C_s && m_dn_h && status,
+               "be_spin_resolved_wilson: null argument");
+  BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_resolved_wilson: at most 1024 systems per call");
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32, "be_spin_resolved_wilson: bad precision");
+  if (n_sys == 0) return BE_OK;
+  const int64_t kps = int64_t(n_par) * n_perp;
+  const int64_t n_k = int64_t(n_sys) * kps;
+  const int64_t n_lines = int64_t(n_sys) * n_perp;
+  const int64_t mm = int64_t(m) * std::max(m, 1);
+  const int64_t Nm = int64_t(N) * std::max(m, 1);
+  double2 *SU = nullptr, *A = nullptr, *Q = nullptr, *V = nullptr;
+  double *ev = nullptr;
+  uint32_t *kst = nullptr, *lst = nullptr;
+  int32_t *cnt = nullptr, *mdn = nullptr;
+  Carve cv;
+  cv.add(&SU, size_t(n_k * Nm));
+  cv.add(&A, size_t(n_k * mm));
+  cv.add(&Q, size_t(n_k * mm));
+  cv.add(&V, size_t(n_k * Nm));
+  cv.add(&ev, size_t(n_k * (m + 2)));
+  cv.add(&kst, size_t(n_k));
+  cv.add(&lst, size_t(2 * n_lines));
+  cv.add(&cnt, size_t(n_k));
+  cv.add(&mdn, size_t(n_sys));
+  BE_RET_IF(cv.commit(ctx, stream, WS_OUTER));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
+                     int64_t(n_sys));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((2 * n_lines + 255) / 256)), dim3(256), 0, stream, lst,
+                     2 * n_lines);
+  BE_RET_IF(check_launch(ctx, "zero"));
+  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
+  if (m == 0) return BE_OK;
+  BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, SU, A, Q, ev,
+                              kst, cnt, mdn, m_dn_h, status, stream));
   hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<uint32_t>((n_lines * m + 255) / 256)), dim3(256), 0, stream, theta_dn,
                      n_lines * m);
   hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<uint32_t>((n_lines * m + 255) / 256)), dim3(256), 0, stream, theta_up,
@@ -989,4 +1010,57 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   }
   hipLaunchKernelGGL(k_spin_chern, dim3((n_sys + 255) / 256), dim3(256), 0, stream, C_dn, C_up, n_sys, C_s);
   return check_launch(ctx, "spin_chern");
+}
+
+extern "C" int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                               int32_t n_sys, int32_t n_k_sys, int32_t precision, const double *spin_diag,
+                               double *pso_evals, void *V, int32_t ldv, int64_t v_stride, int32_t *m_dn_h,
+                               uint32_t *status, hipStream_t stream) {
+  using namespace be;
+  BE_RET_IF(check_grid_args(ctx, U, N, m, ldu, u_stride, n_sys, n_k_sys, 1, BE_OVL_POLAR));
+  BE_CHECK_ARG(ctx, spin_diag && pso_evals && V && m_dn_h && status, "be_spin_sectors: null argument");
+  BE_CHECK_ARG(ctx, ldv >= N && v_stride >= int64_t(ldv) * std::max(m, 1), "be_spin_sectors: ldv < N or v_stride < ldv*m");
+  BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_sectors: at most 1024 systems per call");
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32, "be_spin_sectors: bad precision");
+  if (n_sys == 0) return BE_OK;
+  const int64_t kps = n_k_sys;
+  const int64_t n_k = int64_t(n_sys) * kps;
+  const int64_t mm = int64_t(m) * std::max(m, 1);
+  const int64_t Nm = int64_t(N) * std::max(m, 1);
+  double2 *SU = nullptr, *A = nullptr, *Q = nullptr;
+  double *ev = nullptr;
+  uint32_t *kst = nullptr;
+  int32_t *cnt = nullptr, *mdn = nullptr;
+  Carve cv;
+  cv.add(&SU, size_t(n_k * Nm));
+  cv.add(&A, size_t(n_k * mm));
+  cv.add(&Q, size_t(n_k * mm));
+  cv.add(&ev, size_t(n_k * (m + 2)));
+  cv.add(&kst, size_t(n_k));
+  cv.add(&cnt, size_t(n_k));
+  cv.add(&mdn, size_t(n_sys));
+  BE_RET_IF(cv.commit(ctx, stream, WS_OUTER));
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
+                     int64_t(n_sys));
+  BE_RET_IF(check_launch(ctx, "zero"));
+  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
+  if (m == 0) return BE_OK;
+  BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, SU, A, Q, ev,
+                              kst, cnt, mdn, m_dn_h, status, stream));
+  ZGemm g;  // V = U Q: spin-down columns first (mu ascending)
+  g.M = N;
+  g.N = m;
+  g.K = m;
+  g.A = static_cast<const double2 *>(U);
+  g.lda = ldu;
+  g.bA = ZBatch::strided(u_stride);
+  g.B = Q;
+  g.ldb = m;
+  g.bB = ZBatch::strided(mm);
+  g.C = static_cast<double2 *>(V);
+  g.ldc = ldv;
+  g.bC = ZBatch::strided(v_stride);
+  g.batch = n_k;
+  g.tag = "spin_sector";
+  return zgemm(ctx, g, stream);
 }

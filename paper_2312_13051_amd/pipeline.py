@@ -2,7 +2,9 @@
 
 These chain the library calls the way the paper's functions are used:
 ``wsurf`` (hybrid Wannier centres over a plane, Sec. II), ``wnwl`` (nested
-Wilson loop, Sec. III) and ``wspinsurf`` (spin-resolved Wilson loop, Sec. IV).
+Wilson loop, Sec. III), ``wspinsurf`` (spin-resolved Wilson loop, Sec. IV)
+and ``wflux`` / ``wspinflux`` (Berry flux per plaquette of the occupied
+space or of its spin sectors, the coupling-matrix method of Sec. IV).
 Every step runs in the HIP library; torch only allocates device memory.
 """
 from __future__ import annotations
@@ -106,6 +108,50 @@ def spin(ctx: L.Context, g: EigGrid, spin_diag, mode: int = L.BE_OVL_POLAR, prec
             "status": st}
 
 
+def flux(ctx: L.Context, g: EigGrid):
+    """Berry flux through every plaquette of the grid: flux (n_sys, n_perp, n_par)."""
+    torch = _torch()
+    f = torch.empty((g.n_sys, g.n_perp, g.n_par), dtype=torch.float64, device="cuda")
+    ch = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    tot = torch.empty(g.n_sys, dtype=torch.float64, device="cuda")
+    st = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    ctx.plaquette_flux(g.U, g.N, g.m, g.ldu, g.U.stride(0), g.n_sys, g.n_par, g.n_perp, f, ch, tot, st)
+    return {"flux": f, "chern": ch, "total": tot, "status": st}
+
+
+def spin_flux(ctx: L.Context, g: EigGrid, spin_diag, precision: int = L.BE_FP64):
+    """Berry flux maps of the spin-down and spin-up sectors of the occupied
+    space; C_s = (C_up - C_dn)/2. spin_diag: (n_sys, N) float64."""
+    torch = _torch()
+    m = max(g.m, 1)
+    n_k = g.n_perp * g.n_par
+    sd = torch.as_tensor(np.asarray(spin_diag, dtype=np.float64).reshape(g.n_sys, g.N)).cuda()
+    pso = torch.empty((g.n_sys, g.n_perp, g.n_par, m), dtype=torch.float64, device="cuda")
+    V = torch.empty((g.n_sys * n_k, m, g.N), dtype=torch.complex128, device="cuda")
+    st = torch.empty(g.n_sys, dtype=torch.int32, device="cuda")
+    mdn = ctx.spin_sectors(g.U, g.N, g.m, g.ldu, g.U.stride(0), g.n_sys, n_k, sd, pso, V, g.N, V.stride(0), st,
+                           precision)
+    out = {"mu": pso, "m_dn": mdn, "status_pso": st}
+    f = {k: torch.zeros((g.n_sys, g.n_perp, g.n_par), dtype=torch.float64, device="cuda") for k in ("dn", "up")}
+    ch = {k: torch.zeros(g.n_sys, dtype=torch.int32, device="cuda") for k in ("dn", "up")}
+    tot = {k: torch.zeros(g.n_sys, dtype=torch.float64, device="cuda") for k in ("dn", "up")}
+    sst = {k: torch.zeros(g.n_sys, dtype=torch.int32, device="cuda") for k in ("dn", "up")}
+    s0 = 0
+    while s0 < g.n_sys:  # runs of systems with equal sector sizes
+        s1 = s0 + 1
+        while s1 < g.n_sys and mdn[s1] == mdn[s0]:
+            s1 += 1
+        for key, c0, ms in (("dn", 0, mdn[s0]), ("up", mdn[s0], g.m - mdn[s0])):
+            ctx.plaquette_flux(V[s0 * n_k:, c0 if ms > 0 else 0:, :], g.N, ms, g.N, V.stride(0), s1 - s0, g.n_par, g.n_perp,
+                               f[key][s0:], ch[key][s0:], tot[key][s0:], sst[key][s0:])
+        s0 = s1
+    out.update({"flux_dn": f["dn"], "flux_up": f["up"], "C_dn": ch["dn"], "C_up": ch["up"],
+                "total_dn": tot["dn"], "total_up": tot["up"],
+                "C_s": 0.5 * (ch["up"] - ch["dn"]).to(torch.float64),
+                "status": st | sst["dn"] | sst["up"]})
+    return out
+
+
 def wsurf(ctx, hoplists: Sequence, kappa_grid, lo, hi, mode=L.BE_OVL_POLAR, precision=L.BE_FP64):
     """Hybrid WCCs over a plane for systems of equal N (paper's WSurf)."""
     plan = ctx.hk_plan(list(hoplists))
@@ -130,5 +176,24 @@ def wspinsurf(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, mode=L.BE_
     plan = ctx.hk_plan(list(hoplists))
     g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision, chunk)
     out = spin(ctx, g, spin_diag, mode, precision)
+    out["eig"] = g
+    return out
+
+
+def wflux(ctx, hoplists: Sequence, kappa_grid, lo, hi, precision=L.BE_FP64):
+    """Berry flux per plaquette of the bands [lo, hi) over a plane."""
+    plan = ctx.hk_plan(list(hoplists))
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision)
+    out = flux(ctx, g)
+    out["eig"] = g
+    return out
+
+
+def wspinflux(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, precision=L.BE_FP64, chunk: int = 4096):
+    """Spin-resolved Berry flux per plaquette (the spin-resolved coupling-matrix
+    method of Sec. IV): flux maps and Chern numbers of both spin sectors."""
+    plan = ctx.hk_plan(list(hoplists))
+    g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision, chunk)
+    out = spin_flux(ctx, g, spin_diag, precision)
     out["eig"] = g
     return out

@@ -411,3 +411,39 @@ def test_spin_resolved_flux_bhz():
     assert (out["C_dn"], out["C_up"], out["C_s"]) == (-1, 1, 1.0)
     w = orc.spin_resolved_wilson(syn.bhz(), np.array([1.0, -1, -1, 1]), kg, 0, 2)
     assert (w["C_dn"], w["C_up"]) == (out["C_dn"], out["C_up"])
+
+
+def test_plaquette_flux_singular_link_flagged():
+    """The occupied state of two uncoupled orbitals with energies +-cos 2 pi k
+    jumps from one orbital to the other: the link across the switch has
+    det = 0 and its plaquettes are flagged; a smooth grid is not. Every
+    singular value of an overlap of orthonormal bases is at most 1, so
+    |det| <= sigma_min on random overlaps (the flag covers the Wilson-loop
+    criterion sigma_min < 1e-8)."""
+    from synthetic.models import _from_blocks
+    hl = _from_blocks(2, 1, {(0,): np.zeros((2, 2)), (1,): np.diag([0.5, -0.5])})
+    kg = syn.kplane(8, 3, k0=(1.0 / 16, 0.0, 0.0))
+    f = orc.plaquette_flux(hl, kg, 0, 1)
+    assert f["status"] & orc.OVERLAP_SINGULAR
+    f = orc.plaquette_flux(syn.qwz(1.5), syn.kplane(12, 10), 0, 1)
+    assert not f["status"] & orc.OVERLAP_SINGULAR
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        a = np.linalg.qr(rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4)))[0]
+        b = np.linalg.qr(rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4)))[0]
+        L = b.conj().T @ a
+        s = np.linalg.svd(L, compute_uv=False)
+        assert s.max() <= 1 + 1e-12 and abs(np.linalg.det(L)) <= s.min() + 1e-12
+
+
+def test_plaquette_flux_is_local():
+    """A plaquette's flux depends on its four corners only: the map of the
+    2 x 2 grid of those corners holds it at (0, 0) (how full-size maps are
+    sampled in the parity tests)."""
+    hl = syn.bhz_disordered(2, 1.0, [7, 1])
+    kg = syn.kplane(5, 4)
+    m = hl.N // 2
+    full = orc.plaquette_flux(hl, kg, 0, m)["flux"]
+    for i, j in ((0, 0), (3, 4), (2, 1)):
+        sub = kg[[i, (i + 1) % 4]][:, [j, (j + 1) % 5]]
+        assert abs(orc.plaquette_flux(hl, sub, 0, m)["flux"][0, 0] - full[i, j]) < 1e-12
