@@ -198,17 +198,23 @@ def traffic_from_profile(path, source, precision):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["spin_wilson", "spin_flux"], default="spin_wilson",
+    ap.add_argument("--workload", choices=["spin_wilson", "spin_flux", "bbh_disorder", "choti_nested"],
+                    default="spin_wilson",
                     help="spin_wilson: spin-resolved Wilson loops (the headline metric); spin_flux: spin-resolved "
-                         "Berry flux per plaquette (coupling-matrix method) on the same systems and grid")
+                         "Berry flux per plaquette (coupling-matrix method) on the same systems and grid; "
+                         "bbh_disorder: the disordered quadrupolar-insulator study (spinful BBH, 21x21 supercell, "
+                         "20x20 plaquettes, W = 1 and 9); choti_nested: nested Wilson loop of the chiral HOTI on "
+                         "21 kz planes of 100x100")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk-systems", type=int, default=8)
     ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample size (transverse lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere; "
-                         "its phases are checked against the FP64 oracle at 1e-6 rad)")
+                         "its phases are checked against the FP64 oracle at 1e-6 rad). Default: mixed, except "
+                         "fp64 for bbh_disorder (N = 1764, m = 882: the c64 Hamiltonian alone puts the summed "
+                         "phases of 882 bands near 1e-6 rad)")
     ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
     ap.add_argument("--tune", action="append", default=[], metavar="KNOB=VALUE",
                     help="set a library tuning knob (be_tune_set) before timing")
@@ -218,6 +224,10 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.precision is None:
+        args.precision = "fp64" if args.workload == "bbh_disorder" else "mixed"
+    if args.workload in ("bbh_disorder", "choti_nested"):
+        return main_study(args)
 
     hls, tags = systems()
     if args.systems:
@@ -466,6 +476,178 @@ def main():
         "kernels": kernels,
     }
     print(json.dumps(out))
+
+
+# ---------------------------------------------------------------- paper studies (secondary workloads)
+BBH_L, BBH_GRID, BBH_W = 21, 20, (1.0, 9.0)
+CHOTI_PLANES, CHOTI_GRID = 21, 100
+
+
+def _oracle_bbh_corner(args):
+    """Spin-resolved flux of one plaquette of the 21 x 21 spinful-BBH study
+    with the FP64 oracle (its 2 x 2 corner grid: four eigensolves)."""
+    w_idx, i, j = args
+    from oracle import berry as orc
+    hl = syn.spinful_bbh_disordered(BBH_L, BBH_W[w_idx], [7, w_idx])
+    kg = syn.kplane(BBH_GRID, BBH_GRID)
+    sub = kg[[i, (i + 1) % BBH_GRID]][:, [j, (j + 1) % BBH_GRID]]
+    out = orc.spin_resolved_flux(hl, syn.spinful_bbh_spin_diag(hl), sub, 0, hl.N // 2)
+    if out["status"] & orc.PSO_GAP:
+        return (w_idx, i, j, None, None)
+    return (w_idx, i, j, float(out["flux_dn"][0, 0]), float(out["flux_up"][0, 0]))
+
+
+def _oracle_choti_plane(q):
+    """Nested Wilson loop of one kz plane of the chiral-HOTI study with the FP64 oracle."""
+    from oracle import berry as orc
+    kz = np.linspace(0.0, 1.0, CHOTI_PLANES)[q]
+    out = orc.nested_wilson(syn.choti(1.0), syn.kplane(CHOTI_GRID, CHOTI_GRID, k0=(0.0, 0.0, kz)), 0, 2)
+    return (q, out["p"])
+
+
+def main_study(args):
+    """The disordered quadrupolar-insulator study (Sec. IV) or the chiral-HOTI
+    nested loop against kz (Sec. III), timed like the headline workload."""
+    bbh = args.workload == "bbh_disorder"
+    workers = max(1, min(16, os.cpu_count() or 1))
+    cpu, oracle_res = None, []
+    if bbh:
+        sample = [(w, int(i), int(j)) for w in range(2) for (i, j) in
+                  np.random.default_rng([9, 10 + w]).integers(0, BBH_GRID, size=(max(1, workers // 2), 2))]
+        fn, per = _oracle_bbh_corner, 4
+        what = "plaquettes (each its 2x2 corner grid: 4 eigensolves of N=1764 and their PSO eigensolves)"
+    else:
+        sample = list(range(0, CHOTI_PLANES, max(1, CHOTI_PLANES // max(1, min(workers, 4)))))[:max(1, min(workers, 4))]
+        fn, per = _oracle_choti_plane, CHOTI_GRID * CHOTI_GRID
+        what = f"kz planes of {CHOTI_GRID}x{CHOTI_GRID} k-points (nested Wilson loop of each)"
+    if not args.no_cpu_baseline:
+        oracle_res, cdt = cpu_baseline(sample, min(workers, len(sample)), fn)
+        cpu = {"value": len(sample) * per / cdt, "unit": "k-point solves/s", "cores": min(workers, len(sample)),
+               "kind": "oracle", "sample": f"{len(sample)} {what}, NumPy/LAPACK FP64, one worker process per core, "
+                                           f"OMP_NUM_THREADS=1, wall {cdt:.2f} s"}
+
+    import torch
+    from paper_2312_13051_amd import _lib as L
+    from paper_2312_13051_amd import pipeline as PL
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    ctx = L.Context(0)
+    mixed = args.precision == "mixed"
+    prec = L.BE_MIXED_FP32 if mixed else L.BE_FP64
+    if bbh:
+        hls = [syn.spinful_bbh_disordered(BBH_L, W, [7, w]) for w, W in enumerate(BBH_W)]
+        plan = ctx.hk_plan(hls)
+        kg = syn.kplane(BBH_GRID, BBH_GRID)
+        n_k = BBH_GRID * BBH_GRID
+        N = hls[0].N
+        m = N // 2
+        sd = np.stack([syn.spinful_bbh_spin_diag(h) for h in hls])
+        res = {}
+
+        def step():
+            for s in range(len(hls)):  # one supercell per eigensolver call
+                g = PL.eig_grid(ctx, plan, s, 1, kg, 0, m, prec, chunk=n_k)
+                res[s] = (g, PL.spin_flux(ctx, g, sd[s:s + 1], prec))
+        total_k = len(hls) * n_k
+    else:
+        hl = syn.choti(1.0)
+        kzs = np.linspace(0.0, 1.0, CHOTI_PLANES)
+        kp = np.stack([syn.kplane(CHOTI_GRID, CHOTI_GRID, k0=(0.0, 0.0, kz)) for kz in kzs])
+        N, m = hl.N, 2
+        res = {}
+
+        def step():
+            g = PL.eig_planes(ctx, hl, kp, 0, m, prec, chunk=kp.shape[0] * CHOTI_GRID * CHOTI_GRID)
+            res[0] = (g, PL.nested(ctx, g))
+        total_k = CHOTI_PLANES * CHOTI_GRID * CHOTI_GRID
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        note(f"warmup step {w + 1}/{args.warmup} done")
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        note(f"timed step {k + 1}/{args.steps} issued")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile()
+    ctx.profile_enable(False)
+    lat = []
+    for _ in range(2):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    sec = (t1 - t0) / args.steps
+    steps = args.steps
+    name, (ms_tot, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    roof = {"kernel": name, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+    n_mat = total_k * steps
+    if name == "hetrd_panel":
+        byts = hetrd_panel_bytes(N, n_mat, 8 if mixed else 16)
+        ach = byts / (ms_tot * 1e-3) / 1e9
+        roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": round(byts / launches, 1)})
+    elif name in ("her2k", "unmtr"):
+        fl = eigh_gemm_flops(name, N, m, n_mat)
+        pk = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+        ach = fl / (ms_tot * 1e-3) / 1e12
+        roof.update({"bound": "mfma", "achieved": round(ach, 2), "peak": pk, "unit": "TFLOP/s",
+                     "frac": round(ach / pk, 4)})
+    kernels = {k: {"ms_per_step": round(v[0] / steps, 2), "launches_per_step": v[1] // steps} for k, v in
+               sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    err = None
+    extra = {}
+    if bbh:
+        errs = []
+        for (w, i, j, a, b) in oracle_res:
+            if a is None:
+                continue
+            f = res[w][1]
+            errs.append(float(circ_dist(float(f["flux_dn"][0, i, j]), a)))
+            errs.append(float(circ_dist(float(f["flux_up"][0, i, j]), b)))
+        err = max(errs) if errs else None
+        extra = {"spin_chern": {f"W={W}": float(res[w][1]["C_s"][0]) for w, W in enumerate(BBH_W)},
+                 "status": {f"W={W}": int(res[w][1]["status"][0]) for w, W in enumerate(BBH_W)}}
+        metric, cfg = METRIC_FLUX, {"workload": "spinful BBH (eq. 10) 21x21 supercell (N=1764, m=882) with chiral "
+                                                "disorder w s0(x)t3, W in {1, 9}, one realization each, 20x20 "
+                                                "plaquettes, spin-resolved Berry flux (s = s0(x)t3)",
+                                    "systems": len(BBH_W), "k_points": total_k, "N": N, "m": m}
+    else:
+        p = res[0][1]["p"].cpu().numpy()
+        errs = [float(np.max(circ_dist(2 * np.pi * p[q], 2 * np.pi * ref))) for (q, ref) in oracle_res]
+        err = max(errs) if errs else None
+        pm = res[0][1]["p_mean"].cpu().numpy()
+        d = np.diff(np.r_[pm, pm[0]])
+        d -= np.round(d)
+        extra = {"nested_p_winding_vs_kz": round(float(d[:-1].sum()), 6)}
+        metric, cfg = ("nested Wilson-loop k-point solves/s at ≤1e-6 phase err vs FP64",
+                       {"workload": "chiral HOTI (eq. 9, Delta0 = 1), 21 kz planes in [0, 1] of 100x100 k-points, "
+                                    "Wilson loop along kx, nested loop along ky", "planes": CHOTI_PLANES,
+                        "k_points": total_k, "N": N, "m": m})
+    out = {
+        "metric": metric, "value": round(total_k / sec, 1), "unit": "k-point solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
+        "config": cfg, "roofline": roof, "cpu_baseline": cpu,
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                       "unit": "per step"},
+        "err_vs_fp64_oracle_rad": err, "gate_1e-6_ok": (err is not None and err <= 1e-6), **extra,
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+def circ_dist(a, b):
+    return np.abs(np.mod(np.asarray(a) - np.asarray(b) + np.pi, 2 * np.pi) - np.pi)
 
 
 if __name__ == "__main__":

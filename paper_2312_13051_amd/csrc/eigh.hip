@@ -1295,7 +1295,9 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                     hipStream_t stream) {
   const int m = band_hi - band_lo;
   if (n_mat == 0) return BE_OK;
-  // sub-batches bounded to ~4 GiB of workspace
+  // sub-batches bounded to ~4 GiB of workspace; where that holds fewer than
+  // 512 matrices (one workgroup per matrix in the panel kernel: two per CU),
+  // up to 512 matrices within 32 GiB
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
   const size_t cs = sizeof(typename CT<T>::c);
@@ -1304,7 +1306,8 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                      sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) +
                                        size_t(m) + 1) +
                      sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
-  const int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
+  int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
+  if (cap < 512) cap = std::max<int64_t>(cap, std::min<int64_t>(512, int64_t((size_t(32) << 30) / per)));
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
     BE_RET_IF(eigh_chunk<T>(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo, band_hi, evals + b0 * (m + 2),

@@ -3,8 +3,10 @@
 These chain the library calls the way the paper's functions are used:
 ``wsurf`` (hybrid Wannier centres over a plane, Sec. II), ``wnwl`` (nested
 Wilson loop, Sec. III), ``wspinsurf`` (spin-resolved Wilson loop, Sec. IV)
-and ``wflux`` / ``wspinflux`` (Berry flux per plaquette of the occupied
-space or of its spin sectors, the coupling-matrix method of Sec. IV).
+``wflux`` / ``wspinflux`` (Berry flux per plaquette of the occupied space
+or of its spin sectors, the coupling-matrix method of Sec. IV), and
+``eig_planes`` / ``wnwl_planes`` (a family of parallel planes of a 3D model,
+e.g. the nested loop against kz of Sec. III, in one batch).
 Every step runs in the HIP library; torch only allocates device memory.
 """
 from __future__ import annotations
@@ -195,5 +197,29 @@ def wspinflux(ctx, hoplists: Sequence, spin_diag, kappa_grid, lo, hi, precision=
     plan = ctx.hk_plan(list(hoplists))
     g = eig_grid(ctx, plan, 0, len(hoplists), kappa_grid, lo, hi, precision, chunk)
     out = spin_flux(ctx, g, spin_diag, precision)
+    out["eig"] = g
+    return out
+
+
+def eig_planes(ctx: L.Context, hoplist, kappa_planes: np.ndarray, lo: int, hi: int, precision: int = L.BE_FP64,
+               chunk: int = 4096) -> EigGrid:
+    """Selected eigenvectors on n_planes k-planes of one model
+    (kappa_planes: (n_planes, n_perp, n_par, 3)) in one batch. The planes are
+    diagonalized as one grid of n_planes * n_perp lines; since a U-grid stores
+    matrix (s, i, j) at ((s n_perp + i) n_par + j), the result is returned as a
+    grid of n_planes systems, one per plane, for any of the loop calls."""
+    kp = np.asarray(kappa_planes, dtype=np.float64)
+    n_planes, n_perp, n_par = kp.shape[:3]
+    plan = ctx.hk_plan([hoplist])
+    g = eig_grid(ctx, plan, 0, 1, kp.reshape(n_planes * n_perp, n_par, 3), lo, hi, precision, chunk)
+    return EigGrid(g.U, g.evals, g.status, g.N, g.m, g.ldu, n_planes, n_par, n_perp)
+
+
+def wnwl_planes(ctx, hoplist, kappa_planes, lo, hi, window=(0.0, 0.5), mode=L.BE_OVL_POLAR,
+                precision=L.BE_FP64):
+    """Nested Wilson loop on every plane of a family (paper's WNWL in a loop
+    over kz): nested phases, p and p_mean per plane."""
+    g = eig_planes(ctx, hoplist, kappa_planes, lo, hi, precision)
+    out = nested(ctx, g, window, mode)
     out["eig"] = g
     return out

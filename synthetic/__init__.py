@@ -19,6 +19,9 @@ from .models import (  # noqa: F401
     bhz_vacancies,
     wannier_like,
     bhz_spin_diag,
+    spinful_bbh,
+    spinful_bbh_disordered,
+    spinful_bbh_spin_diag,
     kplane,
     concat_hops,
 )

@@ -200,14 +200,16 @@ def atomic(energies: Sequence[float], dim: int = 2) -> HopList:
 
 
 def supercell(cell: HopList, L: int, removed_sites: Optional[np.ndarray] = None,
-              site_onsite: Optional[np.ndarray] = None) -> HopList:
+              site_onsite: Optional[np.ndarray] = None,
+              onsite_weights: Optional[np.ndarray] = None) -> HopList:
     """Fold a 2D unit-cell hopping list into an L x L supercell.
 
     Site (x, y) has index s = x*L + y. Orbital a of site s becomes supercell
     orbital ``n_orb*c(s) + a`` where c() compacts the surviving sites.
     Supercell lattice vectors are in units of the supercell (k -> 2pi/L).
     ``removed_sites`` drops every orbital of those sites (vacancies);
-    ``site_onsite`` adds a per-site scalar on every orbital of the site.
+    ``site_onsite`` adds a per-site scalar on every orbital of the site,
+    times ``onsite_weights[a]`` on orbital a (default 1: the identity).
     """
     assert cell.dim == 2
     n_orb = cell.N
@@ -234,12 +236,14 @@ def supercell(cell: HopList, L: int, removed_sites: Optional[np.ndarray] = None,
     if site_onsite is not None:
         eps = np.asarray(site_onsite, dtype=np.float64)
         assert eps.shape == (ns,)
+        wts = np.ones(n_orb) if onsite_weights is None else np.asarray(onsite_weights, dtype=np.float64)
+        assert wts.shape == (n_orb,)
         src = np.arange(ns)[keep]
         for a in range(n_orb):
             ii.append(n_orb * compact[src] + a)
             jj.append(n_orb * compact[src] + a)
             RR.append(np.zeros((src.size, 2), dtype=np.int64))
-            tt.append(eps[src].astype(np.complex128))
+            tt.append((wts[a] * eps[src]).astype(np.complex128))
     N = n_orb * int(keep.sum())
     meta = dict(cell.meta)
     meta.update({"L": L, "n_removed": int(ns - keep.sum()), "n_orb_cell": n_orb})
@@ -289,6 +293,44 @@ def bhz_spin_diag(hl: HopList) -> np.ndarray:
     """Diagonal of the spin operator s3 (x) t3 = diag(1,-1,-1,1) per site, for a BHZ (super)cell."""
     n_sites = hl.N // 4
     return np.tile(np.array([1.0, -1.0, -1.0, 1.0]), n_sites)
+
+
+def spinful_bbh(mass: float = 1.0, delta: float = 0.5) -> HopList:
+    """Spinful quadrupolar insulator of eq. 10 (orbital index 2*sigma + tau):
+    sin kx s1(x)t3 + sin ky s2(x)t3 + (cos kx + cos ky + mass) s3(x)t3
+    + delta (cos kx - cos ky) s0(x)t1.
+
+    The last matrix is printed as s0(x)t0, which commutes with the chiral
+    operator S = s0(x)t2 that the model is said to have and closes the gap at
+    half filling; s0(x)t1 is the matrix that anticommutes with S and with the
+    other three terms (the quadrupolar mass), and is used here.
+    """
+    m3 = np.kron(_S3, _S3)
+    d = np.kron(_S0, _S1)
+    blocks = {
+        (0, 0): mass * m3,
+        (1, 0): 0.5 * m3 + np.kron(_S1, _S3) / 2j + 0.5 * delta * d,
+        (0, 1): 0.5 * m3 + np.kron(_S2, _S3) / 2j - 0.5 * delta * d,
+    }
+    return _from_blocks(4, 2, blocks, {"model": "spinful_bbh", "mass": mass, "delta": delta})
+
+
+SPINFUL_BBH_SPIN = np.array([1.0, -1.0, 1.0, -1.0])   # diagonal of s0(x)t3 per site
+
+
+def spinful_bbh_disordered(L: int, W: float, seed: Sequence[int]) -> HopList:
+    """Spinful BBH on an L x L supercell with chiral-symmetric disorder
+    w_s s0(x)t3 on every site, w_s ~ U[-W/2, W/2] (Sec. IV example)."""
+    rng = np.random.default_rng(list(seed))
+    eps = rng.uniform(-W / 2.0, W / 2.0, L * L)
+    hl = supercell(spinful_bbh(), L, site_onsite=eps, onsite_weights=SPINFUL_BBH_SPIN)
+    hl.meta.update({"W": W, "seed": list(seed)})
+    return hl
+
+
+def spinful_bbh_spin_diag(hl: HopList) -> np.ndarray:
+    """Diagonal of the spin operator s0(x)t3 for a spinful-BBH (super)cell."""
+    return np.tile(SPINFUL_BBH_SPIN, hl.N // 4)
 
 
 def wannier_like(n_orb: int, seed: Sequence[int], r_max: float = 3.0,

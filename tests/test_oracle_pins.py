@@ -447,3 +447,71 @@ def test_plaquette_flux_is_local():
     for i, j in ((0, 0), (3, 4), (2, 1)):
         sub = kg[[i, (i + 1) % 4]][:, [j, (j + 1) % 5]]
         assert abs(orc.plaquette_flux(hl, sub, 0, m)["flux"][0, 0] - full[i, j]) < 1e-12
+
+
+# ---------------------------------------------------------------- spinful BBH with chiral disorder
+def test_spinful_bbh_reading_chiral_and_gapped():
+    """Eq. 10 with the quadrupolar mass read as s0 (x) t1: H anticommutes with
+    S = s0 (x) t2 (also with the disorder w s0 (x) t3) and is gapped at half
+    filling; the printed s0 (x) t0 commutes with S and closes the gap at
+    half filling: at k = (pi, 0) and (0, pi) (sin kx = sin ky = 0, mass term
+    +-1) it shifts the spectrum by -1 and +1, so the second band reaches 0 at
+    one point and the third band comes down to 0 at the other."""
+    S = np.kron(np.eye(2), np.array([[0, -1j], [1j, 0]]))
+    rng = np.random.default_rng(8)
+    hls = [syn.spinful_bbh(), syn.spinful_bbh_disordered(3, 2.0, [4, 4])]
+    for hl in hls:
+        Sb = np.kron(np.eye(hl.N // 4), S)
+        for _ in range(4):
+            H = orc.bloch_hamiltonian(hl, np.r_[rng.random(2), 0.0])
+            assert np.abs(Sb @ H @ Sb.conj().T + H).max() < 1e-13
+    w = np.linalg.eigvalsh(orc.bloch_hamiltonian(hls[0], np.array([0.5, 0.0, 0.0])))
+    assert w[2] - w[1] > 1.0
+    s3t3 = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+    # (pi, 0): mass cos pi + cos 0 + 1 = 1, printed term 0.5 (cos pi - cos 0) = -1; (0, pi): +1
+    wa = np.linalg.eigvalsh(1.0 * s3t3 - 1.0 * np.eye(4))
+    wb = np.linalg.eigvalsh(1.0 * s3t3 + 1.0 * np.eye(4))
+    assert wb[1] >= wa[2] - 1e-15
+
+
+def test_spinful_bbh_spin_chern_against_paper():
+    """Fig. 5c-d: C_s = 1 at W = 1 and 0 at W = 9. Clean and weakly disordered
+    supercells give C_s = +1 by the plaquette flux and by the spin-resolved
+    Wilson loop (with a PSO spectrum away from +-1: spin is not conserved);
+    at W = 9 no realization keeps |C_s| = 1 (each is 0, or its PSO gap has
+    closed)."""
+    g = golden()
+    hl = syn.spinful_bbh()
+    sd = syn.spinful_bbh_spin_diag(hl)
+    kg = syn.kplane(12, 12)
+    f = orc.spin_resolved_flux(hl, sd, kg, 0, 2)
+    w = orc.spin_resolved_wilson(hl, sd, kg, 0, 2)
+    assert f["status"] == 0 and w["status"] == 0
+    assert f["C_s"] == w["C_s"] == g["spinful_bbh_W1_spin_chern"]["value"]
+    assert np.abs(np.abs(w["mu"]) - 1).max() > 0.2
+    for r in range(3):
+        h = syn.spinful_bbh_disordered(5, 1.0, [2, r])
+        o = orc.spin_resolved_flux(h, syn.spinful_bbh_spin_diag(h), syn.kplane(6, 6), 0, h.N // 2)
+        assert o["status"] == 0 and o["C_s"] == g["spinful_bbh_W1_spin_chern"]["value"]
+    for r in range(3):
+        h = syn.spinful_bbh_disordered(5, 9.0, [2, r])
+        o = orc.spin_resolved_flux(h, syn.spinful_bbh_spin_diag(h), syn.kplane(6, 6), 0, h.N // 2)
+        assert (o["status"] & orc.PSO_GAP) or o["C_s"] == g["spinful_bbh_W9_spin_chern"]["value"]
+
+
+def test_choti_nested_spectrum_gapless_against_kz():
+    """Sec. III, Fig. 4b: the nested spectrum of the chiral HOTI (eq. 9,
+    Delta0 = 1; loop along kx, nested along ky) is gapless against kz: the
+    nested polarization p(kz) winds once around the circle as kz runs over
+    the zone (a Chern-insulator-like flow), while each plane is resolved."""
+    assert golden()["choti_nested_gapless_vs_kz"]["value"] is True
+    hl = syn.choti(1.0)
+    ps = []
+    for kz in np.arange(20) / 20:
+        out = orc.nested_wilson(hl, syn.kplane(16, 16, k0=(0.0, 0.0, kz)), 0, 2)
+        assert out["status"] == 0 and out["s"] == 1
+        ps.append(out["p_mean"])
+    d = np.diff(np.r_[ps, ps[0]])
+    d -= np.round(d)
+    assert abs(abs(d.sum()) - 1.0) < 1e-9
+    assert np.abs(d).max() < 0.3   # resolved: no step near half a turn
