@@ -424,6 +424,16 @@ def spin_resolved_flux(hl, spin_diag: np.ndarray, kappa_grid: np.ndarray, lo: in
             "status": st | dn["status"] | up["status"]}
 
 
+def pso_spectrum(hl, kappa, lo: int, hi: int, S: np.ndarray):
+    """Spectrum of the projected spin operator P S P in the bands [lo, hi) at
+    one k-point, for any Hermitian spin operator S (N x N), e.g. n.sigma on
+    every spinor pair (the spin_spectrum scan of Sec. V, used to choose the
+    spin axis along which this spectrum is gapped)."""
+    H = bloch_hamiltonian(hl, np.asarray(kappa, dtype=np.float64))
+    w, U = eigh_bands(H, lo, hi)[:2]
+    return np.linalg.eigvalsh(U.conj().T @ S @ U)
+
+
 # ----------------------------------------------------------------------------
 # Independent Hermitian eigensolver (cross-check of LAPACK on small N)
 # ----------------------------------------------------------------------------

@@ -1308,6 +1308,10 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                      sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
   int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
   if (cap < 512) cap = std::max<int64_t>(cap, std::min<int64_t>(512, int64_t((size_t(32) << 30) / per)));
+  // equal sub-batches: a short remainder batch would cost nearly a full
+  // launch per panel (one workgroup per matrix, latency-bound when few)
+  const int64_t n_sub = (n_mat + cap - 1) / cap;
+  cap = (n_mat + n_sub - 1) / n_sub;
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
     BE_RET_IF(eigh_chunk<T>(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo, band_hi, evals + b0 * (m + 2),

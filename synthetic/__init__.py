@@ -22,6 +22,9 @@ from .models import (  # noqa: F401
     spinful_bbh,
     spinful_bbh_disordered,
     spinful_bbh_spin_diag,
+    rotated_bhz,
+    write_tb,
+    write_centres,
     kplane,
     concat_hops,
 )

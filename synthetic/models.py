@@ -379,6 +379,103 @@ def concat_hops(hls: Sequence[HopList]) -> HopList:
     return hl
 
 
+def rotated_bhz(axis=(1.0, 0.0, 0.0), L: int = 1, W: float = 0.0, seed: Sequence[int] = (0,)) -> HopList:
+    """BHZ (or its disordered L x L supercell) with the spin quantization axis
+    turned from z to ``axis``: every hopping block conjugated by the spinor
+    rotation exp(-i a/2 m.sigma) that takes z to the axis, in an interleaved
+    spinor basis: BHZ orbital (site, s, t) becomes 2*(2*site + s) + b with
+    b = 0 for the +1 eigenstate of the conserved BHZ spin s3 (x) t3 (b = s xor
+    t). The conserved spin of the result is axis.sigma on every pair, not
+    sigma_z."""
+    base = supercell(bhz(), L, site_onsite=np.random.default_rng(list(seed)).uniform(-W / 2.0, W / 2.0, L * L)) \
+        if L > 1 else bhz()
+    n = np.asarray(axis, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    z = np.array([0.0, 0.0, 1.0])
+    m = np.cross(z, n)
+    a = np.arccos(np.clip(n @ z, -1.0, 1.0))
+    if np.linalg.norm(m) < 1e-12:
+        m = np.array([1.0, 0.0, 0.0])
+    m = m / np.linalg.norm(m)
+    msig = m[0] * _S1 + m[1] * _S2 + m[2] * _S3
+    rot = np.cos(a / 2) * _S0 - 1j * np.sin(a / 2) * msig
+    ns = base.N // 4
+    perm = np.empty(base.N, dtype=np.int64)
+    for s_ in range(ns):
+        for sg in range(2):
+            for tau in range(2):
+                perm[4 * s_ + 2 * sg + tau] = 2 * (2 * s_ + sg) + (sg ^ tau)
+    Rmat = np.kron(np.eye(base.N // 2), rot)
+    keys = {}
+    for e in range(base.nnz):
+        keys.setdefault(tuple(int(x) for x in base.R[e]), []).append(e)
+    ii, jj, RR, tt = [], [], [], []
+    for R, es in keys.items():
+        T = np.zeros((base.N, base.N), dtype=np.complex128)
+        for e in es:
+            T[perm[base.i[e]], perm[base.j[e]]] += base.t[e]
+        T = Rmat @ T @ Rmat.conj().T
+        a_, b_ = np.nonzero(np.abs(T) > 1e-15)
+        ii.append(a_)
+        jj.append(b_)
+        RR.append(np.tile(np.array(R, dtype=np.int32), (a_.size, 1)))
+        tt.append(T[a_, b_])
+    hl = HopList(N=base.N, dim=2, i=np.concatenate(ii).astype(np.int32), j=np.concatenate(jj).astype(np.int32),
+                 R=np.concatenate(RR).astype(np.int32).reshape(-1, 2), t=np.concatenate(tt),
+                 meta={"model": "rotated_bhz", "axis": list(n), "L": L, "W": W})
+    hl.validate()
+    return hl
+
+
+def write_tb(hl: HopList, path, lattice=None, degeneracy=None, header: str = "synthetic tight-binding model") -> None:
+    """Write a hopping list in the Wannier90 ``_tb.dat`` layout: header,
+    lattice (3 rows), num_wann, nrpts, degeneracies (15 per line), then per R
+    a blank line, R (3 integers) and num_wann^2 lines 'm n Re Im' (1-based,
+    m fastest) holding ndegen(R) * t(R)_{mn}, then the position section (the
+    same R list, zeros). ``degeneracy(R)`` gives ndegen (default 1)."""
+    lat = np.eye(3) if lattice is None else np.asarray(lattice, dtype=np.float64)
+    N = hl.N
+    blocks = {}
+    for e in range(hl.nnz):
+        R = tuple(int(x) for x in hl.R[e]) + (0,) * (3 - hl.dim)
+        blocks.setdefault(R, np.zeros((N, N), dtype=np.complex128))[hl.i[e], hl.j[e]] += hl.t[e]
+    for R in list(blocks):
+        mR = tuple(-x for x in R)
+        blocks.setdefault(mR, np.zeros((N, N), dtype=np.complex128))
+    Rs = sorted(blocks)
+    deg = [1 if degeneracy is None else int(degeneracy(R)) for R in Rs]
+    with open(path, "w") as f:
+        f.write(header + "\n")
+        for row in lat:
+            f.write(" ".join(f"{x:22.15e}" for x in row) + "\n")
+        f.write(f"{N:12d}\n{len(Rs):12d}\n")
+        for k in range(0, len(deg), 15):
+            f.write("".join(f"{d:5d}" for d in deg[k:k + 15]) + "\n")
+        for R, d in zip(Rs, deg):
+            f.write("\n" + "".join(f"{x:5d}" for x in R) + "\n")
+            T = blocks[R] * d
+            for n_ in range(N):
+                for m_ in range(N):
+                    v = T[m_, n_]
+                    f.write(f"{m_ + 1:5d}{n_ + 1:5d}   {v.real:23.16e} {v.imag:23.16e}\n")
+        for R in Rs:
+            f.write("\n" + "".join(f"{x:5d}" for x in R) + "\n")
+            for n_ in range(N):
+                for m_ in range(N):
+                    f.write(f"{m_ + 1:5d}{n_ + 1:5d}   " + " ".join(["0.0"] * 6) + "\n")
+
+
+def write_centres(centres: np.ndarray, path, atoms=()) -> None:
+    """Wannier centres in the ``_centres.xyz`` layout (symbol X), then atoms."""
+    c = np.asarray(centres, dtype=np.float64)
+    with open(path, "w") as f:
+        f.write(f"{len(c) + len(atoms)}\nWannier centres\n")
+        for x in c:
+            f.write(f"X {x[0]:17.8f}{x[1]:17.8f}{x[2]:17.8f}\n")
+        for sym, x in atoms:
+            f.write(f"{sym} {x[0]:17.8f}{x[1]:17.8f}{x[2]:17.8f}\n")
+
+
 def kplane(n_par: int, n_perp: int, e_par=(1.0, 0.0, 0.0), e_perp=(0.0, 1.0, 0.0),
            k0=(0.0, 0.0, 0.0)) -> np.ndarray:
     """Fractional k-points of a plane: kappa[i, j] = k0 + (j/n_par) e_par + (i/n_perp) e_perp.
