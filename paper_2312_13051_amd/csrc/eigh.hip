@@ -227,8 +227,10 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
       if (r >= N) return;
       const C *col = Aq + r;
       int c = cb;
-      // UN independent column loads in flight per lane (128 B per lane)
-      constexpr int UN = 128 / sizeof(C);
+      // UN independent column loads in flight per lane (64 B in c64, 128 B in
+      // c128: measured faster than 16 c64 loads, which cost registers and
+      // occupancy)
+      constexpr int UN = 8;
       for (; c + UN <= ce; c += UN) {
         C a[UN];
 #pragma unroll
@@ -352,13 +354,27 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
 }
 
 // ---------------------------------------------------------------- tridiagonal solver
+// a / b by the hardware reciprocal and one Newton-Raphson step on it, then one
+// correction of the quotient (q + r (a - b q)); a few ulps at most, for
+// normal b (the Sturm recurrence keeps |b| >= pivmin >= DBL_MIN).
+__device__ __forceinline__ double div_nr(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
+// Number of eigenvalues of T below x (Sturm sequence of the LDL^T
+// factorization of T - x I). The quotient uses div_nr: the count is that of a
+// matrix within a few ulps of T, the same kind of backward error the
+// correctly rounded division gives.
 __device__ __forceinline__ int sturm_count(const double *sd, const double *se2, int N, double x, double pivmin) {
   int cnt = 0;
   double qv = sd[0] - x;
   if (fabs(qv) < pivmin) qv = -pivmin;
   cnt += qv < 0.0;
   for (int i = 1; i < N; ++i) {
-    qv = (sd[i] - x) - se2[i - 1] / qv;
+    qv = (sd[i] - x) - div_nr(se2[i - 1], qv);
     if (fabs(qv) < pivmin) qv = -pivmin;
     cnt += qv < 0.0;
   }
