@@ -20,7 +20,7 @@
 //    supports; lanes that must share a block fall back to Gram-Schmidt. The
 //    vectors are then orthonormalized in FP64 by Newton-Schulz steps on the
 //    Gram matrix (symmetric orthonormalization, MFMA DGEMMs) until
-//    max |Z^T Z - I| < 1e-14 (1e-8 on the mixed path).
+//    max |Z^T Z - I| < 1e-14 (5e-8 on the mixed path).
 // 3. Back-transformation U = Q Z by pairs of panels in reverse order, each
 //    pair one compact-WY block of 64 columns, V = [V1 V2],
 //    T = [[T1, -T1 (V1^H V2) T2], [0, T2]], applied with three MFMA GEMMs:
@@ -1165,10 +1165,11 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   const int64_t ust = mixed ? int64_t(N) * m : us;
   // ---- symmetric orthonormalization of Z (Newton-Schulz on the Gram matrix),
   // Z held as X = Z^T (m x N, leading dim mp); iterated until max |X X^T - I|
-  // is below 1e-14 (FP64 path), or 1e-8 on the mixed path, whose FP32
-  // back-transformation leaves errors of order 1e-7 anyway
+  // is below 1e-14 (FP64 path), or 5e-8 on the mixed path, whose FP32
+  // back-transformation leaves errors of order 1e-7 anyway (inverse iteration
+  // alone typically gives 1e-8 there: no Newton-Schulz step is then taken)
   {
-    const double tol_orth = mixed ? 1e-8 : 1e-14;
+    const double tol_orth = mixed ? 5e-8 : 1e-14;
     const int64_t sZ = int64_t(4) * N * mp;
     double *Xa = Zs + int64_t(3) * N * mp, *Xt = Zs;
     double *hmax = static_cast<double *>(ctx->pinned);
