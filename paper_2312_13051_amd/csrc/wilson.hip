@@ -69,28 +69,39 @@ __global__ void k_zero_u32(uint32_t *p, int64_t n) {
 // G <- 1.5 I - 0.5 G for every m x m matrix; per-matrix err = max |G - I|
 // (before the update) into err[q] and atomically into *gmax (bit pattern of a
 // non-negative double orders like an integer).
-__global__ void k_ns_prep(double2 *G, int m, int64_t n_mat, double *err, unsigned long long *gmax) {
-  const int64_t q = blockIdx.x;
-  if (q >= n_mat) return;
-  double2 *Gq = G + q * int64_t(m) * m;
+// tpm threads per matrix (64 for m*m <= 64: four matrices per block of 256;
+// else 256), one atomicMax per block.
+__global__ void k_ns_prep(double2 *G, int m, int64_t n_mat, int tpm, double *err, unsigned long long *gmax) {
+  const int per_blk = blockDim.x / tpm;
+  const int sub = threadIdx.x / tpm, t = threadIdx.x % tpm;
+  const int64_t q = int64_t(blockIdx.x) * per_blk + sub;
   double e = 0.0;
-  for (int k = threadIdx.x; k < m * m; k += blockDim.x) {
-    int r = k % m, c = k / m;
-    double2 g = Gq[k];
-    double dr = g.x - (r == c ? 1.0 : 0.0);
-    e = fmax(e, fmax(fabs(dr), fabs(g.y)));
-    Gq[k] = make_double2((r == c ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+  if (q < n_mat) {
+    double2 *Gq = G + q * int64_t(m) * m;
+    for (int k = t; k < m * m; k += tpm) {
+      int r = k % m, c = k / m;
+      double2 g = Gq[k];
+      double dr = g.x - (r == c ? 1.0 : 0.0);
+      e = fmax(e, fmax(fabs(dr), fabs(g.y)));
+      Gq[k] = make_double2((r == c ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+    }
   }
   for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
   __syncthreads();
+  if (tpm == 64) {  // one wave per matrix
+    if ((threadIdx.x & 63) == 0 && q < n_mat) err[q] = e == e ? e : INFINITY;
+  } else if (threadIdx.x == 0 && q < n_mat) {
+    double v = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+    err[q] = v == v ? v : INFINITY;
+  }
   if (threadIdx.x == 0) {
-    double t = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
-    if (!(t == t)) t = INFINITY;
-    err[q] = t;
-    atomicMax(gmax, (unsigned long long)__double_as_longlong(t));
+    double v = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+    if (!(v == v)) v = INFINITY;
+    atomicMax(gmax, (unsigned long long)__double_as_longlong(v));
   }
 }
 
@@ -435,7 +446,9 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       g.batch = nm;
       g.tag = "polar";
       BE_RET_IF(zgemm(ctx, g, stream));
-      hipLaunchKernelGGL(k_ns_prep, dim3(static_cast<uint32_t>(nm)), dim3(256), 0, stream, B1, m, nm, err, gmax);
+      const int tpm = m * m <= 64 ? 64 : 256;
+      hipLaunchKernelGGL(k_ns_prep, dim3(static_cast<uint32_t>((nm + 256 / tpm - 1) / (256 / tpm))), dim3(256), 0,
+                         stream, B1, m, nm, tpm, err, gmax);
       BE_RET_IF(check_launch(ctx, "ns_prep"));
       BE_HIP_TRY(ctx, hipMemcpyAsync(hmax, gmax, sizeof(double), hipMemcpyDeviceToHost, stream));
       BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
