@@ -143,7 +143,7 @@ def gemm_phase_flops(N, m, n_par, n_k_sys, m_dn):
     return {
         "her2k": eigh_gemm_flops("her2k", N, m, nk),
         "unmtr": eigh_gemm_flops("unmtr", N, m, nk),
-        "pso": 8.0 * m * m * N * nk,                       # U^H (S U)
+        "pso": 4.0 * m * (m + 1) * N * nk,                 # U^H (S U), one triangle (Hermitian)
         "pso_her2k": eigh_gemm_flops("her2k", m, m, nk),   # eigensolver of P S P (order m, all bands)
         "pso_unmtr": eigh_gemm_flops("unmtr", m, m, nk),
         "spin_sector": 8.0 * N * m * m * nk,               # U [Q- Q+]
@@ -411,7 +411,7 @@ def main():
         w_sum += fl / (pk * 1e12)
         t_sum += t
     gemm_phases = {"per_tag": gemm, "frac_of_mfma_peak": round(w_sum / t_sum, 4) if t_sum else None,
-                   "note": "algorithmic flops (one triangle for her2k, 8 per complex multiply-add); "
+                   "note": "algorithmic flops (one triangle for her2k and pso, 8 per complex multiply-add); "
                            "FP64 extras (polar, reorth) are timed but not counted"}
 
     # ---- phase error of the sampled lines against the FP64 oracle

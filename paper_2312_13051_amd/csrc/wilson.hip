@@ -445,6 +445,7 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       g.bC = ZBatch::strided(mm);
       g.batch = nm;
       g.tag = "polar";
+      g.herm = true;  // X^H X: lower tiles, mirrored
       BE_RET_IF(zgemm(ctx, g, stream));
       const int tpm = m * m <= 64 ? 64 : 256;
       hipLaunchKernelGGL(k_ns_prep, dim3(static_cast<uint32_t>((nm + 256 / tpm - 1) / (256 / tpm))), dim3(256), 0,
@@ -904,6 +905,7 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
     g.bC = ZBatch::strided(mm);
     g.batch = n_k;
     g.tag = "pso";
+    g.herm = true;  // U^H S U is Hermitian: lower tiles computed, mirrored (bitwise Hermitian for the eigensolver)
     BE_RET_IF(zgemm(ctx, g, stream));
   }
   // ---- eigh of the m x m projected spin operator (all bands)
