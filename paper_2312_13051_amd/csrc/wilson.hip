@@ -138,16 +138,21 @@ __global__ void k_carry_last(const double2 *src, int n_src, double2 *dst, int n_
 // Schur vectors (m x m). Outputs: theta_sorted[q*ldt + 0..m-1] ascending in
 // (-pi, pi]; theta_raw[q*m + n] (optional) = phase of the eigenvalue belonging
 // to column n of Z.
+// INLDS: the whole m x m matrix is held in LDS (orders up to 100, no
+// eigenvectors): every access of the reduction and of the QR sweeps is an LDS
+// access instead of a dependent global round trip.
+template <bool INLDS>
 __global__ __launch_bounds__(64) void k_unitary_eig(const double2 *W, int m, int64_t n_mat, double2 *Hs,
                                                     double2 *Zs, double *theta_sorted, int ldt, double *theta_raw,
                                                     uint32_t *flags, int flag_div) {
-  extern __shared__ double2 sv[];  // Householder vector (m) then eigenvalues (m)
+  extern __shared__ double2 sv[];  // Householder vector (m), eigenvalues (m), [INLDS: the matrix (m x m)]
   double2 *slam = sv + m;
   const int64_t q = blockIdx.x;
   if (q >= n_mat) return;
   const int lane = threadIdx.x;
   const double2 *Wq = W + q * int64_t(m) * m;
-  double2 *H = Hs + q * int64_t(m) * m;
+  double2 *H = INLDS ? slam + m : Hs + q * int64_t(m) * m;
+  if (INLDS) Zs = nullptr;
   double2 *Z = Zs ? Zs + q * int64_t(m) * m : nullptr;
   for (int k = lane; k < m * m; k += 64) {
     H[k] = Wq[k];
@@ -528,13 +533,16 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
   }
   // cur now holds W per line (n_loop == 1 means W = F_0)
   // ---- eigenphases
-  const size_t esm = 2 * size_t(m) * sizeof(double2);
+  const size_t esm_lds = (size_t(m) * m + 2 * size_t(m)) * sizeof(double2);
+  const bool inlds = Zout == nullptr && esm_lds <= 160 * 1024;
+  const size_t esm = inlds ? esm_lds : 2 * size_t(m) * sizeof(double2);
+  auto kern = inlds ? &k_unitary_eig<true> : &k_unitary_eig<false>;
   if (esm > 65536)
-    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(esm)));
   ProfScope prof(ctx, "unitary_eig", stream);
-  hipLaunchKernelGGL(k_unitary_eig, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs,
-                     Zout, theta_sorted, ldt, theta_raw, line_status, 1);
+  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs, Zout,
+                     theta_sorted, ldt, theta_raw, line_status, 1);
   return check_launch(ctx, "unitary_eig");
 }
 
