@@ -595,30 +595,39 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
     for (int i = 0; i < N; ++i)
       if (i < bs || i >= bt) X[int64_t(i) * mp + c] = 0.0;
     // two solves: from a pseudo-random start the first already amplifies the
-    // wanted direction by ~1/(eps ||T||) against ~1/gap for the others
+    // wanted direction by ~1/(eps ||T||) against ~1/gap for the others. The
+    // second solve recomputes the same factorization (same operations, same
+    // factors) instead of storing it again, and takes the first solution's
+    // normalization as it reads it.
+    double scale = 1.0;
     for (int it = 0; it < 2; ++it) {
       // forward elimination with partial pivoting on [T_block - lm I | rhs]
       double a = sd[bs] - lm, b = bt - bs > 1 ? se[bs] : 0.0;
-      double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, bs) : X[int64_t(bs) * mp + c];
+      double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, bs) : X[int64_t(bs) * mp + c] * scale;
       for (int i = bs; i + 1 < bt; ++i) {
         const double ei = se[i], Dn = sd[i + 1] - lm, en = (i + 2 < bt) ? se[i + 1] : 0.0;
-        const double rn = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, i + 1) : X[int64_t(i + 1) * mp + c];
+        const double rn =
+            it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, i + 1) : X[int64_t(i + 1) * mp + c] * scale;
         const int64_t o = int64_t(i) * mp + c;
         if (fabs(a) >= fabs(ei)) {
           if (a == 0.0) a = tiny;
           const double l = ei / a;
-          Z0[o] = a;
-          Z1[o] = b;
-          Z2[o] = 0.0;
+          if (it == 0) {
+            Z0[o] = a;
+            Z1[o] = b;
+            Z2[o] = 0.0;
+          }
           X[o] = r;
           a = Dn - l * b;
           b = en;
           r = rn - l * r;
         } else {
           const double l = a / ei;
-          Z0[o] = ei;
-          Z1[o] = Dn;
-          Z2[o] = en;
+          if (it == 0) {
+            Z0[o] = ei;
+            Z1[o] = Dn;
+            Z2[o] = en;
+          }
           X[o] = rn;
           const double an = b - l * Dn, bn = -l * en, rr = r - l * rn;
           a = an;
@@ -629,9 +638,11 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
       if (a == 0.0) a = tiny;
       {
         const int64_t o = int64_t(bt - 1) * mp + c;
-        Z0[o] = a;
-        Z1[o] = 0.0;
-        Z2[o] = 0.0;
+        if (it == 0) {
+          Z0[o] = a;
+          Z1[o] = 0.0;
+          Z2[o] = 0.0;
+        }
         X[o] = r;
       }
       // back substitution
@@ -646,7 +657,10 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
       }
       const double inv = 1.0 / sqrt(nrm);
       if (!isfinite(inv) || inv == 0.0) lane_bad = true;
-      for (int i = bs; i < bt; ++i) X[int64_t(i) * mp + c] *= inv;
+      if (it == 0)
+        scale = inv;
+      else
+        for (int i = bs; i < bt; ++i) X[int64_t(i) * mp + c] *= inv;
     }
   }
   __syncthreads();
