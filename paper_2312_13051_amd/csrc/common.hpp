@@ -234,6 +234,7 @@ struct DGemm {
   double beta = 0.0;
   int64_t batch = 0;
   const char *tag = "dgemm";
+  bool sym = false;  // C (square) is symmetric: as ZGemm::herm, without conjugation
 };
 int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream);
 

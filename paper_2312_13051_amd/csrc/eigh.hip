@@ -1206,6 +1206,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.bC = ZBatch::strided(int64_t(m) * m);
       g.batch = nb_mat;
       g.tag = "reorth";
+      g.sym = true;
       BE_RET_IF(dgemm(ctx, g, stream));
       hipLaunchKernelGGL(ns_prep_real, dim3(nb_mat), dim3(PT), 0, stream, Gm, m, oerr, gmax);
       BE_RET_IF(check_launch(ctx, "ns_prep_real"));

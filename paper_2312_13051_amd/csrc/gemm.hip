@@ -285,6 +285,7 @@ struct DP {
   double alpha, beta;
   int64_t batch;
   int tiles_m, tiles_n;
+  int sym;  // symmetric C: lower tiles only, strictly lower tiles mirrored into the upper triangle
 };
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB>
@@ -304,6 +305,8 @@ __global__ __launch_bounds__(64 * WM * WN) void dgemm_kernel(DP p) {
   const int t2 = static_cast<int>(w - q * tiles);
   const int tm = t2 % p.tiles_m, tn = t2 / p.tiles_m;
   const int i0 = tm * BM, j0 = tn * BN;
+  static_assert(BM == BN, "square tiles (symmetric mode pairs tile (tm, tn) with (tn, tm))");
+  if (p.sym && tm < tn) return;
   const double *A = p.A + be::zbatch_off(p.bA, q);
   const double *B = p.B + be::zbatch_off(p.bB, q);
   double *C = p.C + be::zbatch_off(p.bC, q);
@@ -372,6 +375,7 @@ __global__ __launch_bounds__(64 * WM * WN) void dgemm_kernel(DP p) {
           double out = p.alpha * acc[a][b][r];
           if (p.beta != 0.0) out += p.beta * C[idx];
           C[idx] = out;
+          if (p.sym && tm > tn) C[gj + int64_t(gi) * p.ldc] = out;
         }
       }
     }
@@ -412,6 +416,7 @@ int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream) {
   p.alpha = g.alpha;
   p.beta = g.beta;
   p.batch = g.batch;
+  p.sym = g.sym ? 1 : 0;
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
   if (use_big_tiles(p.M, p.N)) return dlaunch<64, 64, 2, 2>(ctx, p, g.opA, g.opB, stream);
   if (p.M >= 24 && p.N >= 24) return dlaunch<32, 32, 2, 2>(ctx, p, g.opA, g.opB, stream);

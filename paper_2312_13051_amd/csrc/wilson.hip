@@ -992,34 +992,38 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   hipLaunchKernelGGL(k_fill_i32, dim3((n_sys + 255) / 256), dim3(256), 0, stream, C_dn, int64_t(n_sys), 0);
   hipLaunchKernelGGL(k_fill_i32, dim3((n_sys + 255) / 256), dim3(256), 0, stream, C_up, int64_t(n_sys), 0);
   BE_RET_IF(check_launch(ctx, "fill"));
-  // ---- per run of systems with equal sector sizes: V = U Q_sector, Wilson loop
+  // ---- V = U Q for all systems at once (columns in ascending mu: the first
+  // m_dn_h[s] span the spin-down sector), then per run of systems with equal
+  // sector sizes, the Wilson loop of each sector on its column slice of V
+  {
+    ZGemm g;
+    g.M = N;
+    g.N = m;
+    g.K = m;
+    g.A = static_cast<const double2 *>(U);
+    g.lda = ldu;
+    g.bA = ZBatch::strided(u_stride);
+    g.B = Q;
+    g.ldb = m;
+    g.bB = ZBatch::strided(mm);
+    g.C = V;
+    g.ldc = N;
+    g.bC = ZBatch::strided(Nm);
+    g.batch = n_k;
+    g.tag = "spin_sector";
+    BE_RET_IF(zgemm(ctx, g, stream));
+  }
   for (int s0 = 0; s0 < n_sys;) {
     const int md = m_dn_h[s0];
     int s1 = s0 + 1;
     while (s1 < n_sys && m_dn_h[s1] == md) ++s1;
-    const int64_t k0 = int64_t(s0) * kps, nk = int64_t(s1 - s0) * kps;
+    const int64_t k0 = int64_t(s0) * kps;
     const int64_t l0 = int64_t(s0) * n_perp, nl = int64_t(s1 - s0) * n_perp;
     for (int sector = 0; sector < 2; ++sector) {
       const int ms = sector == 0 ? md : m - md;
       const int c0 = sector == 0 ? 0 : md;
       if (ms == 0) continue;
-      ZGemm g;
-      g.M = N;
-      g.N = ms;
-      g.K = m;
-      g.A = static_cast<const double2 *>(U) + k0 * u_stride;
-      g.lda = ldu;
-      g.bA = ZBatch::strided(u_stride);
-      g.B = Q + k0 * mm + int64_t(c0) * m;
-      g.ldb = m;
-      g.bB = ZBatch::strided(mm);
-      g.C = V;
-      g.ldc = N;
-      g.bC = ZBatch::strided(int64_t(N) * ms);
-      g.batch = nk;
-      g.tag = "spin_sector";
-      BE_RET_IF(zgemm(ctx, g, stream));
-      Grid gv{V, N, int64_t(N) * ms};
+      Grid gv{V + k0 * Nm + int64_t(c0) * N, N, Nm};
       double *th = (sector == 0 ? theta_dn : theta_up) + l0 * m;
       uint32_t *ls = lst + sector * n_lines + l0;
       BE_RET_IF(wilson_core(ctx, gv, N, ms, nl, n_par, mode, th, m, nullptr, nullptr, ls, nullptr, stream));
