@@ -588,7 +588,7 @@ def main_study(args):
     sec = (t1 - t0) / args.steps
     steps = args.steps
     name, (ms_tot, launches) = max(prof.items(), key=lambda kv: kv[1][0])
-    roof = {"kernel": name, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+    roof = {"kernel": name, "bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
             "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
     n_mat = total_k * steps
     if name == "hetrd_panel":
