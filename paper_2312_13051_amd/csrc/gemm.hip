@@ -263,7 +263,9 @@ template <typename T>
 int dispatch(be_ctx *ctx, GP<T> p, int opA, int opB, hipStream_t s) {
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
   // Tile choice by output size; small outputs use one-wave tiles.
-  if (use_big_tiles(p.M, p.N)) return launch_cfg<T, 64, 64, 2, 2>(ctx, p, opA, opB, s);
+  // 64 x 64 tiles with 8 waves (each 16 x 32): fewer registers per wave than
+  // with 4 waves, twice the resident waves per SIMD (measured faster)
+  if (use_big_tiles(p.M, p.N)) return launch_cfg<T, 64, 64, 4, 2>(ctx, p, opA, opB, s);
   if (p.M >= 24 && p.N >= 24) return launch_cfg<T, 32, 32, 2, 2>(ctx, p, opA, opB, s);
   return launch_cfg<T, 16, 16, 1, 1>(ctx, p, opA, opB, s);
 }
@@ -418,7 +420,7 @@ int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream) {
   p.batch = g.batch;
   p.sym = g.sym ? 1 : 0;
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
-  if (use_big_tiles(p.M, p.N)) return dlaunch<64, 64, 2, 2>(ctx, p, g.opA, g.opB, stream);
+  if (use_big_tiles(p.M, p.N)) return dlaunch<64, 64, 4, 2>(ctx, p, g.opA, g.opB, stream);
   if (p.M >= 24 && p.N >= 24) return dlaunch<32, 32, 2, 2>(ctx, p, g.opA, g.opB, stream);
   return dlaunch<16, 16, 1, 1>(ctx, p, g.opA, g.opB, stream);
 }
