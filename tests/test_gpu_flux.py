@@ -224,3 +224,37 @@ def test_flux_random_bases_panel_widths(N, m):
     ref = orc.plaquette_flux_from_grid(Ug)
     assert circ(f.cpu().numpy(), ref["flux"]).max() < 1e-9
     assert (int(st[0]) & orc.OVERLAP_SINGULAR) == (ref["status"] & orc.OVERLAP_SINGULAR)
+
+
+def test_flux_multi_pass_matches_single_systems():
+    """Three BHZ 10x10 supercells (m = 200 occupied bands, 24 x 24 grid): their
+    links take 369 MB per system and direction, so one call runs them in two
+    passes; every system's flux map equals the one computed alone."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    hls = [syn.bhz_disordered(10, 1.0 + r, [8, r]) for r in range(3)]
+    kg = syn.kplane(24, 24)
+    m = hls[0].N // 2
+    g = P.eig_grid(c, c.hk_plan(hls), 0, 3, kg, 0, m, precision=1)
+    both = P.flux(c, g)
+    for s in range(3):
+        one = P.flux(c, P.EigGrid(g.U[s * 576:(s + 1) * 576], g.evals, g.status, g.N, g.m, g.ldu, 1, 24, 24))
+        assert float((both["flux"][s] - one["flux"][0]).abs().max()) == 0.0
+        assert int(both["chern"][s]) == int(one["chern"][0]) and int(both["status"][s]) == int(one["status"][0])
+
+
+def test_spin_sectors_bad_arguments():
+    gu.need_gpu()
+    from paper_2312_13051_amd import _lib as L
+    c = gu.ctx()
+    U = torch.zeros((4, 2, 4), dtype=torch.complex128, device="cuda")
+    V = torch.zeros((4, 2, 4), dtype=torch.complex128, device="cuda")
+    sd = torch.ones((1, 4), dtype=torch.float64, device="cuda")
+    mu = torch.empty((4, 2), dtype=torch.float64, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(L.BerryError):
+        c.spin_sectors(U, 4, 2, 4, 8, 1, 4, sd, mu, V, 3, 8, st)          # ldv < N
+    with pytest.raises(L.BerryError):
+        c.spin_sectors(U, 4, 2, 4, 8, 1, 4, sd, mu, V, 4, 8, st, precision=7)
+    assert c.spin_sectors(U, 4, 2, 4, 8, 0, 4, sd, mu, V, 4, 8, st) == []
