@@ -1,7 +1,8 @@
 """Continuous-batching request loop for Wilson-loop requests.
 
 A request is one model (hopping list) with a k-plane, a band window and a
-kind (plain, spin-resolved or nested Wilson loop). Requests arrive at any
+kind (plain, spin-resolved or nested Wilson loop, or the Berry flux per
+plaquette of the occupied space or of its spin sectors). Requests arrive at any
 time. The engine
 
 * admits a waiting request as soon as its device footprint (resident
@@ -34,6 +35,7 @@ import numpy as np
 from . import _lib as L
 
 KIND_WILSON, KIND_SPIN, KIND_NESTED = "wilson", "spin", "nested"
+KIND_FLUX, KIND_SPIN_FLUX = "flux", "spin_flux"
 
 
 @dataclass
@@ -268,6 +270,10 @@ class GpuExecutor:
             out = P.spin(self.ctx, g, np.asarray(r.spin_diag)[None], precision=r.precision)
         elif r.kind == KIND_NESTED:
             out = P.nested(self.ctx, g, r.window)
+        elif r.kind == KIND_FLUX:
+            out = P.flux(self.ctx, g)
+        elif r.kind == KIND_SPIN_FLUX:
+            out = P.spin_flux(self.ctx, g, np.asarray(r.spin_diag)[None], precision=r.precision)
         else:
             out = P.wilson(self.ctx, g)
         out = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}

@@ -23,7 +23,15 @@ def make_requests(S):
     reqs.append(S.Request(hoplist=syn.bbh(0.5, 1.0), kappa=syn.kplane(12, 12), lo=0, hi=2, kind=S.KIND_NESTED))
     hl = syn.bhz_disordered(3, 2.0, [5, 1, 9])
     reqs.append(S.Request(hoplist=hl, kappa=kg, lo=0, hi=hl.N // 2, kind=S.KIND_WILSON))
+    reqs.append(S.Request(hoplist=syn.qwz(1.5), kappa=syn.kplane(10, 8), lo=0, hi=1, kind=S.KIND_FLUX))
+    hl = syn.bhz_disordered(3, 1.0, [5, 1, 7])
+    reqs.append(S.Request(hoplist=hl, kappa=kg, lo=0, hi=hl.N // 2, kind=S.KIND_SPIN_FLUX,
+                          spin_diag=syn.bhz_spin_diag(hl)))
     return reqs
+
+
+def circ(a, b):
+    return float(np.max(np.abs(np.mod(np.asarray(a) - np.asarray(b) + np.pi, 2 * np.pi) - np.pi)))
 
 
 def test_served_mix_equals_alone():
@@ -56,6 +64,16 @@ def test_served_mix_equals_alone():
         elif r.kind == S.KIND_NESTED:
             assert abs(float(a["p_mean"][0]) - float(b["p_mean"][0])) < 1e-10
             assert abs(float(b["p_mean"][0]) - 0.5) < 1e-10
+        elif r.kind == S.KIND_FLUX:
+            ref = orc.plaquette_flux(r.hoplist, r.kappa, r.lo, r.hi)
+            assert circ(a["flux"][0], b["flux"][0]) < 1e-10 and circ(b["flux"][0], ref["flux"]) < 1e-10
+            assert int(b["chern"][0]) == ref["chern"] == 1
+        elif r.kind == S.KIND_SPIN_FLUX:
+            ref = orc.spin_resolved_flux(r.hoplist, r.spin_diag, r.kappa, r.lo, r.hi)
+            assert a["m_dn"] == b["m_dn"] == [ref["m_dn"]]
+            for key in ("flux_dn", "flux_up"):
+                assert circ(a[key][0], b[key][0]) < 1e-10 and circ(b[key][0], ref[key]) < 1e-10
+            assert float(b["C_s"][0]) == ref["C_s"]
         else:
             assert phase_set_error(a["theta"][0], b["theta"][0]) < 1e-10
             ref = orc.wilson_surface(r.hoplist, r.kappa, r.lo, r.hi)
