@@ -1339,7 +1339,7 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   if (n_mat == 0) return BE_OK;
   // sub-batches bounded to ~4 GiB of workspace; where that holds fewer than
   // 512 matrices (one workgroup per matrix in the panel kernel: two per CU),
-  // up to 512 matrices within 32 GiB
+  // up to 512 matrices within 32 GiB (or half the free device memory)
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
   const size_t cs = sizeof(typename CT<T>::c);
@@ -1349,7 +1349,15 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                                        size_t(m) + 1) +
                      sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
   int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
-  if (cap < 512) cap = std::max<int64_t>(cap, std::min<int64_t>(512, int64_t((size_t(32) << 30) / per)));
+  if (cap < 512) {
+    size_t free_b = 0, total_b = 0;
+    size_t budget = size_t(32) << 30;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+      budget = std::min(budget, free_b / 2 + ctx->ws_bytes[WS_EIGH]);  // the slot's current size is reusable
+    else
+      (void)hipGetLastError();
+    cap = std::max<int64_t>(cap, std::min<int64_t>(512, int64_t(budget / per)));
+  }
   // equal sub-batches: a short remainder batch would cost nearly a full
   // launch per panel (one workgroup per matrix, latency-bound when few)
   const int64_t n_sub = (n_mat + cap - 1) / cap;

@@ -287,16 +287,17 @@ extern "C" int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t 
   const int nbw = det_panel_width(m);
   BE_CHECK_ARG(ctx, nbw > 0, "be_plaquette_flux: m > 2544 not supported");
   if (n_sys == 0) return BE_OK;
-  static bool lds_set = false;
-  if (!lds_set) {  // dynamic LDS up to the panel size of each width
+  // dynamic LDS up to the panel size of the width in use (set on every call:
+  // a cheap host call, valid for whichever device is current)
+  if (nbw == 4)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_det_phase<4>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, 2544 * 4 * 16));
+  else if (nbw == 8)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_det_phase<8>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, 512 * 8 * 16));
+  else
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_det_phase<16>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, 256 * 16 * 16));
-    lds_set = true;
-  }
   const int64_t kps = int64_t(n_par) * n_perp;
   const int64_t mm = int64_t(std::max(m, 1)) * std::max(m, 1);
   hipLaunchKernelGGL(k_zero_st, dim3((n_sys + 255) / 256), dim3(256), 0, stream, status, int64_t(n_sys));
