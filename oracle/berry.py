@@ -40,7 +40,10 @@ Method (paper references are to sections and equations):
   insulator: the coupling-matrix method on a grid of plaquettes, per spin
   sector): the phase of the product of the link
   variables det(U(k')^H U(k)) around each plaquette; the sum over the zone
-  is 2 pi times the Chern number.
+  is 2 pi times the Chern number. A link with |det| < 1e-8 is flagged.
+* Spectrum of the projected spin operator for any spin operator S (Sec. V,
+  the scan over a grid of k-points for a spin axis with a gapped spectrum):
+  the eigenvalues of U^H S U in the selected bands.
 
 Where the paper is silent or garbled, the readings used here are listed in
 the design notes of the repository (overlap index order, polar factor as the
