@@ -1331,6 +1331,27 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   return BE_OK;
 }
 
+// Matrices the panel kernel holds resident on the whole device at once (one
+// workgroup per matrix): CUs times resident workgroups per CU.
+template <typename T>
+static int64_t panel_slots(be_ctx *ctx, int N) {
+  typedef typename CT<T>::c C;
+  const int pnt = ctx->tune_panel_threads;
+  const size_t psm = panel_smem(N, sizeof(C), pnt);
+  void (*panel)(C *, int64_t, int, int, int, int, C *, int64_t, C *, int64_t, double *, double *, int64_t, uint32_t *) =
+      pnt == 256 ? &hetrd_panel<T, 256> : pnt == 512 ? &hetrd_panel<T, 512> : &hetrd_panel<T, 1024>;
+  int per_cu = 0;
+  if (psm > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)) != hipSuccess)
+    (void)hipGetLastError();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(panel), pnt, psm) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = 0;
+  }
+  return int64_t(std::max(per_cu, 1)) * ctx->n_cu;
+}
+
 template <typename T>
 static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo,
                     int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
@@ -1358,8 +1379,13 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
       (void)hipGetLastError();
     cap = std::max<int64_t>(cap, std::min<int64_t>(512, int64_t(budget / per)));
   }
-  // equal sub-batches: a short remainder batch would cost nearly a full
-  // launch per panel (one workgroup per matrix, latency-bound when few)
+  // The panel kernel streams at full bandwidth only while the device is full:
+  // a sub-batch is a whole number of device-wide rounds of resident
+  // workgroups where the cap allows one, and the sub-batches are made equal,
+  // so that no short remainder costs a full round per panel (4,608 matrices
+  // of order 400 with 768 resident: six sub-batches of 768; 9,216: twelve).
+  const int64_t slots = panel_slots<T>(ctx, N);
+  if (cap >= slots) cap = cap / slots * slots;
   const int64_t n_sub = (n_mat + cap - 1) / cap;
   cap = (n_mat + n_sub - 1) / n_sub;
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
