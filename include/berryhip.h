@@ -156,9 +156,9 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
  * Inside a cluster of (nearly) degenerate eigenvalues the columns are some
  * orthonormal basis of the cluster's invariant subspace; the projector U U^H
  * is the gauge-invariant output. Workspace: the context's, grown on demand;
- * batches are processed in sub-batches of at most 4 GiB of it, or, for
- * large N where 4 GiB holds fewer than 512 matrices, of up to 512 matrices
- * within 32 GiB. */
+ * batches are processed in equal sub-batches of at most 4 GiB of it, or, for
+ * large N where 4 GiB holds fewer matrices than the device runs at once, of
+ * up to that many within 48 GiB (at most half the free device memory). */
 int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, int64_t mat_stride,
                     int32_t n_mat, int32_t band_lo, int32_t band_hi, int32_t precision, double *evals,
                     void *U, int32_t ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);

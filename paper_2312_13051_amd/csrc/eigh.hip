@@ -1359,8 +1359,8 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   const int m = band_hi - band_lo;
   if (n_mat == 0) return BE_OK;
   // sub-batches bounded to ~4 GiB of workspace; where that holds fewer than
-  // 512 matrices (one workgroup per matrix in the panel kernel: two per CU),
-  // up to 512 matrices within 32 GiB (or half the free device memory)
+  // one device-wide round of resident panel workgroups (large N), up to one
+  // round within 48 GiB (or half the free device memory)
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
   const size_t cs = sizeof(typename CT<T>::c);
@@ -1369,22 +1369,22 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                      sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) +
                                        size_t(m) + 1) +
                      sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
+  const int64_t slots = panel_slots<T>(ctx, N);
   int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
-  if (cap < 512) {
+  if (cap < slots) {
     size_t free_b = 0, total_b = 0;
-    size_t budget = size_t(32) << 30;
+    size_t budget = size_t(48) << 30;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
       budget = std::min(budget, free_b / 2 + ctx->ws_bytes[WS_EIGH]);  // the slot's current size is reusable
     else
       (void)hipGetLastError();
-    cap = std::max<int64_t>(cap, std::min<int64_t>(512, int64_t(budget / per)));
+    cap = std::max<int64_t>(cap, std::min<int64_t>(slots, int64_t(budget / per)));
   }
   // The panel kernel streams at full bandwidth only while the device is full:
   // a sub-batch is a whole number of device-wide rounds of resident
   // workgroups where the cap allows one, and the sub-batches are made equal,
   // so that no short remainder costs a full round per panel (4,608 matrices
   // of order 400 with 768 resident: six sub-batches of 768; 9,216: twelve).
-  const int64_t slots = panel_slots<T>(ctx, N);
   if (cap >= slots) cap = cap / slots * slots;
   const int64_t n_sub = (n_mat + cap - 1) / cap;
   cap = (n_mat + n_sub - 1) / n_sub;
