@@ -176,19 +176,20 @@ def test_spin_flux_disordered_supercell():
 
 @pytest.mark.parametrize("precision,tol", [(0, TOL), (1, TOL_MIXED)])
 def test_spin_flux_full_size_supercells(precision, tol):
-    """The coupling-matrix workload at full size: eight disordered spinful BHZ
-    10x10 supercells (N = 400, m = 200) on a 20 x 20 plaquette grid in one
-    call. Sampled plaquettes of both sectors against the oracle (2 x 2 corner
-    grids); every system's spin Chern number equals the spin-resolved
-    Wilson-loop winding on the same grid whenever both are resolved."""
+    """The coupling-matrix workload at full size and in the benchmark's launch
+    configuration: eight disordered spinful BHZ 10x10 supercells (N = 400,
+    m = 200) on a 24 x 24 plaquette grid in one eigensolver call. Sampled
+    plaquettes of both sectors against the oracle (2 x 2 corner grids); every
+    system's spin Chern number equals the spin-resolved Wilson-loop winding on
+    the same grid whenever both are resolved."""
     gu.need_gpu()
     P = pipe()
     c = gu.ctx()
     hls = [syn.bhz_disordered(10, 1.0, [6, r]) for r in range(8)]
-    kg = syn.kplane(20, 20)
+    kg = syn.kplane(24, 24)
     m = hls[0].N // 2
     sd = np.stack([syn.bhz_spin_diag(h) for h in hls])
-    out = P.wspinflux(c, hls, sd, kg, 0, m, precision=precision, chunk=8 * 400)
+    out = P.wspinflux(c, hls, sd, kg, 0, m, precision=precision, chunk=8 * 576)
     st = out["status"].cpu().numpy()
     w = P.spin(c, out["eig"], sd, precision=precision)
     wst = w["status"].cpu().numpy()
@@ -197,7 +198,7 @@ def test_spin_flux_full_size_supercells(precision, tol):
             assert int(out["C_dn"][s]) == int(w["C_dn"][s])
             assert int(out["C_up"][s]) == int(w["C_up"][s])
     assert (st == 0).sum() >= 6
-    for s, (i, j) in ((0, (0, 0)), (3, (7, 19)), (6, (19, 11))):
+    for s, (i, j) in ((0, (0, 0)), (3, (7, 19)), (6, (23, 11))):
         ref = orc.spin_resolved_flux(hls[s], sd[s], corners(kg, i, j), 0, m)
         assert not ref["status"] & orc.PSO_GAP
         assert out["m_dn"][s] == ref["m_dn"]
