@@ -207,6 +207,142 @@ __global__ __launch_bounds__(DT) void k_det_phase(double2 *A, int m, int64_t sA,
   }
 }
 
+// The same factorization by one wave per link (orders up to 256), with the
+// row interchanges kept as a permutation in LDS instead of moving rows in
+// memory: the panel's rows are read through the permutation, the block row
+// of U is solved in registers by the lane that owns its column and applied
+// to the trailing rows at once, and no barrier waits for another wave. The
+// pivots, their arguments and moduli are those of the workgroup kernel.
+template <int NB>
+__global__ __launch_bounds__(64) void k_det_phase_w(double2 *A, int m, int64_t sA, double *phase, double *logdet) {
+  extern __shared__ double2 sP[];            // panel, column-major: sP[c * rows + r]
+  int *perm = reinterpret_cast<int *>(sP + int64_t(m) * NB);  // logical row -> physical row
+  double2 *M = A + int64_t(blockIdx.x) * sA;  // M[r][c] = M[r * m + c]
+  const int lane = threadIdx.x;
+  double ph = 0.0, la = 0.0;
+  for (int r = lane; r < m; r += 64) perm[r] = r;
+  __syncthreads();
+  auto wave_best = [&](double best, int bi, double &ob, int &oi) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v = __shfl_xor(best, o, 64);
+      const int i = __shfl_xor(bi, o, 64);
+      if (v > best || (v == best && i < bi)) {
+        best = v;
+        bi = i;
+      }
+    }
+    ob = best;
+    oi = bi;
+  };
+  for (int k0 = 0; k0 < m; k0 += NB) {
+    const int nbp = min(NB, m - k0), rows = m - k0;
+    double best = -1.0;
+    int bi = 0;
+    // panel load through the permutation, pivot search of its first column
+    for (int e = lane; e < rows * nbp; e += 64) {
+      const int r = e / nbp, c = e - r * nbp;
+      const double2 v = M[int64_t(perm[k0 + r]) * m + k0 + c];
+      sP[c * rows + r] = v;
+      if (c == 0) {
+        const double a2 = v.x * v.x + v.y * v.y;
+        if (a2 > best || (a2 == best && r < bi)) {
+          best = a2;
+          bi = r;
+        }
+      }
+    }
+    double bv;
+    int p;
+    wave_best(best, bi, bv, p);
+    __syncthreads();
+    for (int c = 0; c < nbp; ++c) {
+      if (bv < 0.0) p = c;
+      if (p != c) {
+        for (int cc = lane; cc < nbp; cc += 64) {
+          const double2 t = sP[cc * rows + c];
+          sP[cc * rows + c] = sP[cc * rows + p];
+          sP[cc * rows + p] = t;
+        }
+        if (lane == 0) {
+          const int t = perm[k0 + c];
+          perm[k0 + c] = perm[k0 + p];
+          perm[k0 + p] = t;
+        }
+      }
+      __syncthreads();
+      const double2 piv = sP[c * rows + c];
+      const double den = piv.x * piv.x + piv.y * piv.y;
+      ph += atan2(piv.y, piv.x) + (p != c ? kPi : 0.0);
+      la += 0.5 * log(den);
+      const double2 ipv = den > 0.0 ? make_double2(piv.x / den, -piv.y / den) : make_double2(0.0, 0.0);
+      best = -1.0;
+      bi = c + 1;
+      for (int r = c + 1 + lane; r < rows; r += 64) {
+        const double2 a = sP[c * rows + r];
+        const double2 l = make_double2(a.x * ipv.x - a.y * ipv.y, a.x * ipv.y + a.y * ipv.x);
+        sP[c * rows + r] = l;
+        for (int cc = c + 1; cc < nbp; ++cc) {
+          const double2 u = sP[cc * rows + c];
+          double2 x = sP[cc * rows + r];
+          x.x -= l.x * u.x - l.y * u.y;
+          x.y -= l.x * u.y + l.y * u.x;
+          sP[cc * rows + r] = x;
+          if (cc == c + 1) {
+            const double a2 = x.x * x.x + x.y * x.y;
+            if (a2 > best) {
+              best = a2;
+              bi = r;
+            }
+          }
+        }
+      }
+      wave_best(best, bi, bv, p);
+      __syncthreads();
+    }
+    if (k0 + nbp >= m) break;
+    // block row of U (in registers) and trailing update, one lane per column
+    const int j0 = k0 + nbp, C = m - j0;
+    for (int jb = 0; jb < C; jb += 64) {
+      const int j = j0 + jb + lane;
+      if (jb + lane < C) {
+        double2 u[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c < nbp) {
+            double2 x = M[int64_t(perm[k0 + c]) * m + j];
+#pragma unroll
+            for (int cc = 0; cc < c; ++cc) {
+              const double2 l = sP[cc * rows + c];
+              x.x -= l.x * u[cc].x - l.y * u[cc].y;
+              x.y -= l.x * u[cc].y + l.y * u[cc].x;
+            }
+            u[c] = x;
+          } else {
+            u[c] = make_double2(0.0, 0.0);
+          }
+        }
+#pragma unroll 1
+        for (int r = nbp; r < rows; ++r) {
+          double2 *pr = M + int64_t(perm[k0 + r]) * m + j;
+          double2 x = *pr;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            const double2 l = sP[c * rows + r];
+            x.x -= l.x * u[c].x - l.y * u[c].y;
+            x.y -= l.x * u[c].y + l.y * u[c].x;
+          }
+          *pr = x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (lane == 0) {
+    phase[blockIdx.x] = m > 0 ? wrap_pi(ph) : 0.0;
+    logdet[blockIdx.x] = la;
+  }
+}
+
 // Panel width for order m: the widest whose panel (m x NB c128) fits in
 // 160 KiB of LDS, preferring at most 64 KiB (several workgroups per CU).
 int det_panel_width(int m) {
@@ -354,7 +490,13 @@ extern "C" int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t 
         const size_t lds = size_t(std::max(m, 1)) * nbw * sizeof(double2);
         double *ph = dir == 0 ? ph_par : ph_perp, *ld = dir == 0 ? ld_par : ld_perp;
         const dim3 grid(static_cast<uint32_t>(nk));
-        if (nbw == 16)
+        if (m <= 128)
+          hipLaunchKernelGGL(k_det_phase_w<16>, grid, dim3(64), size_t(m) * 16 * sizeof(double2) + size_t(m) * 4,
+                             stream, L, m, mm, ph, ld);
+        else if (m <= 256)
+          hipLaunchKernelGGL(k_det_phase_w<8>, grid, dim3(64), size_t(m) * 8 * sizeof(double2) + size_t(m) * 4,
+                             stream, L, m, mm, ph, ld);
+        else if (nbw == 16)
           hipLaunchKernelGGL(k_det_phase<16>, grid, dim3(DT), lds, stream, L, m, mm, ph, ld);
         else if (nbw == 8)
           hipLaunchKernelGGL(k_det_phase<8>, grid, dim3(DT), lds, stream, L, m, mm, ph, ld);
