@@ -207,7 +207,7 @@ __global__ __launch_bounds__(DT) void k_det_phase(double2 *A, int m, int64_t sA,
   }
 }
 
-// The same factorization by one wave per link (orders up to 256), with the
+// The same factorization by one wave per link (orders up to 128), with the
 // row interchanges kept as a permutation in LDS instead of moving rows in
 // memory: the panel's rows are read through the permutation, the block row
 // of U is solved in registers by the lane that owns its column and applied
@@ -492,9 +492,6 @@ extern "C" int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t 
         const dim3 grid(static_cast<uint32_t>(nk));
         if (m <= 128)
           hipLaunchKernelGGL(k_det_phase_w<16>, grid, dim3(64), size_t(m) * 16 * sizeof(double2) + size_t(m) * 4,
-                             stream, L, m, mm, ph, ld);
-        else if (m <= 256)
-          hipLaunchKernelGGL(k_det_phase_w<8>, grid, dim3(64), size_t(m) * 8 * sizeof(double2) + size_t(m) * 4,
                              stream, L, m, mm, ph, ld);
         else if (nbw == 16)
           hipLaunchKernelGGL(k_det_phase<16>, grid, dim3(DT), lds, stream, L, m, mm, ph, ld);
