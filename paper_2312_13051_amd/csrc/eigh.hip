@@ -391,8 +391,9 @@ __device__ __forceinline__ double hash_unit(uint64_t a, uint64_t b) {
 }
 
 // Per-matrix scratch of the tridiagonal solver: lam [m + 1] = (||T||, selected
-// eigenvalues), Zs: 4 arrays [N][mp] (U0, U1, U2, x) with the eigenvector
-// index fastest, marks [m] (1 at the first index of a cluster whose vectors
+// eigenvalues), Zs: 4 arrays [N][mp] (the diagonals met by the elimination of
+// inverse iteration, two arrays of orthonormalization scratch, x) with the
+// eigenvector index fastest, marks [m] (1 at the first index of a cluster whose vectors
 // share a block of T).
 
 // Loads d, e of matrix q into LDS; returns false (and flags the matrix, with
@@ -565,9 +566,7 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
   __syncthreads();
   const int nblk = s_nblk;
   double *Z0 = Zs + q * sZ;
-  double *Z1 = Z0 + int64_t(N) * mp;
-  double *Z2 = Z1 + int64_t(N) * mp;
-  double *X = Z2 + int64_t(N) * mp;
+  double *X = Z0 + int64_t(3) * N * mp;  // the fourth array (arrays 1 and 2 unused here)
   const double tiny = eps * fmax(tnorm, DBL_MIN);
   const double dblk = tol_window(tnorm, clu_rel), dclu = tol_cluster(tnorm, clu_rel);
   bool lane_bad = false;
@@ -608,69 +607,108 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
     // wanted direction by ~1/(eps ||T||) against ~1/gap for the others. The
     // second solve recomputes the same factorization (same operations, same
     // factors) instead of storing it again, and takes the first solution's
-    // normalization as it reads it.
+    // normalization as it reads it. Of the factorization only the diagonal
+    // a_i met at each elimination step is stored: the pivot choice of row i
+    // (|a_i| < |e_i|) and every factor entry follow from a_i, a_{i-1} and T,
+    // recomputed by the same operations in the back substitution.
+    // The loads of each sweep are issued PF rows ahead of the recurrence that
+    // consumes them, so the serial chain waits on memory once per PF rows.
+    constexpr int PF = 4;
     double scale = 1.0;
     for (int it = 0; it < 2; ++it) {
       // forward elimination with partial pivoting on [T_block - lm I | rhs]
       double a = sd[bs] - lm, b = bt - bs > 1 ? se[bs] : 0.0;
       double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, bs) : X[int64_t(bs) * mp + c] * scale;
-      for (int i = bs; i + 1 < bt; ++i) {
+      // one elimination step at row i (i + 1 < bt) with right-hand side entry rn of row i + 1
+      auto step = [&](int i, double rn) {
         const double ei = se[i], Dn = sd[i + 1] - lm, en = (i + 2 < bt) ? se[i + 1] : 0.0;
-        const double rn =
-            it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, i + 1) : X[int64_t(i + 1) * mp + c] * scale;
         const int64_t o = int64_t(i) * mp + c;
-        if (fabs(a) >= fabs(ei)) {
-          if (a == 0.0) a = tiny;
-          const double l = ei / a;
-          if (it == 0) {
-            Z0[o] = a;
-            Z1[o] = b;
-            Z2[o] = 0.0;
-          }
-          X[o] = r;
-          a = Dn - l * b;
-          b = en;
-          r = rn - l * r;
-        } else {
-          const double l = a / ei;
-          if (it == 0) {
-            Z0[o] = ei;
-            Z1[o] = Dn;
-            Z2[o] = en;
-          }
-          X[o] = rn;
-          const double an = b - l * Dn, bn = -l * en, rr = r - l * rn;
-          a = an;
-          b = bn;
-          r = rr;
+        if (it == 0) Z0[o] = a;
+        // without interchange: l = e_i / a (a = 0 only with e_i = 0, then
+        // taken as tiny), row i keeps (a, b); with interchange: l = a / e_i
+        const bool keep = fabs(a) >= fabs(ei);
+        const double ad = (keep && a == 0.0) ? tiny : a;
+        const double l = (keep ? ei : ad) / (keep ? ad : ei);
+        X[o] = keep ? r : rn;
+        const double p1 = keep ? Dn : b, p2 = keep ? b : Dn;
+        const double q1 = keep ? rn : r, q2 = keep ? r : rn;
+        a = p1 - l * p2;
+        b = keep ? en : -l * en;
+        r = q1 - l * q2;
+      };
+      if (it == 0) {
+        for (int i = bs; i + 1 < bt; ++i) step(i, hash_unit(uint64_t(q) * 1315423911ull + c, i + 1));
+      } else {
+        for (int i0 = bs; i0 + 1 < bt; i0 += PF) {
+          double rv[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) rv[u] = i0 + u + 1 < bt ? X[int64_t(i0 + u + 1) * mp + c] : 0.0;
+#pragma unroll
+          for (int u = 0; u < PF; ++u)
+            if (i0 + u + 1 < bt) step(i0 + u, rv[u] * scale);
         }
       }
-      if (a == 0.0) a = tiny;
       {
         const int64_t o = int64_t(bt - 1) * mp + c;
-        if (it == 0) {
-          Z0[o] = a;
-          Z1[o] = 0.0;
-          Z2[o] = 0.0;
-        }
+        if (it == 0) Z0[o] = a;
         X[o] = r;
       }
-      // back substitution
+      // back substitution: row i of the triangular factor is (e_i, D_{i+1},
+      // e_{i+1}) where row i was interchanged, else (a_i, b_i, 0) with b_i =
+      // e_i, or -(a_{i-1} / e_{i-1}) e_i after an interchange at row i-1
       double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-      for (int i = bt - 1; i >= bs; --i) {
-        const int64_t o = int64_t(i) * mp + c;
-        const double xi = (X[o] - Z1[o] * x1 - Z2[o] * x2) / Z0[o];
-        X[o] = xi;
-        x2 = x1;
-        x1 = xi;
-        nrm = fma(xi, xi, nrm);
+      double ai = Z0[int64_t(bt - 1) * mp + c];
+      for (int i0 = bt - 1; i0 >= bs; i0 -= PF) {
+        double xv[PF], av[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int i = i0 - u;
+          xv[u] = i >= bs ? X[int64_t(i) * mp + c] : 0.0;
+          av[u] = i > bs ? Z0[int64_t(i - 1) * mp + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int i = i0 - u;
+          if (i >= bs) {
+            const double ap = av[u];
+            double z0, z1 = 0.0, z2 = 0.0;
+            if (i == bt - 1) {
+              z0 = ai == 0.0 ? tiny : ai;
+            } else if (fabs(ai) >= fabs(se[i])) {
+              z0 = ai == 0.0 ? tiny : ai;
+              z1 = se[i];
+              if (i > bs && !(fabs(ap) >= fabs(se[i - 1]))) {
+                const double l = ap / se[i - 1];
+                z1 = -l * se[i];
+              }
+            } else {
+              z0 = se[i];
+              z1 = sd[i + 1] - lm;
+              z2 = (i + 2 < bt) ? se[i + 1] : 0.0;
+            }
+            const double xi = (xv[u] - z1 * x1 - z2 * x2) / z0;
+            X[int64_t(i) * mp + c] = xi;
+            x2 = x1;
+            x1 = xi;
+            nrm = fma(xi, xi, nrm);
+            ai = ap;
+          }
+        }
       }
       const double inv = 1.0 / sqrt(nrm);
       if (!isfinite(inv) || inv == 0.0) lane_bad = true;
-      if (it == 0)
+      if (it == 0) {
         scale = inv;
-      else
-        for (int i = bs; i < bt; ++i) X[int64_t(i) * mp + c] *= inv;
+      } else {
+        for (int i0 = bs; i0 < bt; i0 += PF) {
+          double xv[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) xv[u] = i0 + u < bt ? X[int64_t(i0 + u) * mp + c] : 0.0;
+#pragma unroll
+          for (int u = 0; u < PF; ++u)
+            if (i0 + u < bt) X[int64_t(i0 + u) * mp + c] = xv[u] * inv;
+        }
+      }
     }
   }
   __syncthreads();
@@ -987,13 +1025,27 @@ __global__ void flag_nonorth(const double *err, int64_t n, double tol, uint32_t 
   if (q < n && !(err[q] <= tol)) status[q] |= BE_ST_NONCONVERGED;
 }
 
-// U[q](r, c) = X[q](c, r) as complex (X: m x N column-major, leading dimension mp)
+// U[q](r, c) = X[q](c, r) as complex (X: m x N column-major, leading dimension
+// mp), by 64 x 64 tiles staged in LDS: rows of X are read along c and columns
+// of U written along r, both coalesced. Grid: (tiles of N x m, matrices).
 template <typename C>
-__global__ void z_to_u(const double *X, int64_t sX, int mp, int N, int m, C *U, int ldu, int64_t sU) {
+__global__ __launch_bounds__(256) void z_to_u(const double *X, int64_t sX, int mp, int N, int m, C *U, int ldu,
+                                              int64_t sU) {
+  __shared__ double s[64 * 65];
   const int64_t q = blockIdx.y;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < int64_t(N) * m; k += int64_t(gridDim.x) * blockDim.x) {
-    int c = int(k / N), r = int(k % N);
-    U[q * sU + r + int64_t(c) * ldu] = mk<C>(X[q * sX + int64_t(r) * mp + c], 0.0);
+  const int ntr = (N + 63) / 64;
+  const int r0 = int(blockIdx.x % ntr) * 64, c0 = int(blockIdx.x / ntr) * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double *Xq = X + q * sX;
+  for (int rr = w; rr < 64; rr += 4) {
+    const int r = r0 + rr, c = c0 + lane;
+    s[rr * 65 + lane] = (r < N && c < m) ? Xq[int64_t(r) * mp + c] : 0.0;
+  }
+  __syncthreads();
+  C *Uq = U + q * sU;
+  for (int cc = w; cc < 64; cc += 4) {
+    const int r = r0 + lane, c = c0 + cc;
+    if (r < N && c < m) Uq[r + int64_t(c) * ldu] = mk<C>(s[lane * 65 + cc], 0.0);
   }
 }
 
@@ -1249,8 +1301,9 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     }
     hipLaunchKernelGGL(flag_nonorth, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat,
                        std::max(tol_orth, 1e-10), status);
-    hipLaunchKernelGGL(z_to_u<C>, dim3(64, static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream, Xa, sZ, mp, N, m, Ut, ldt,
-                       ust);
+    const int zt = ((N + 63) / 64) * ((m + 63) / 64);
+    hipLaunchKernelGGL(z_to_u<C>, dim3(static_cast<uint32_t>(zt), static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream,
+                       Xa, sZ, mp, N, m, Ut, ldt, ust);
     BE_RET_IF(check_launch(ctx, "z_to_u"));
   }
   // ---- back-transformation by pairs of panels (pa, pb = pa + 1), last pair
