@@ -354,14 +354,13 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
 }
 
 // ---------------------------------------------------------------- tridiagonal solver
-// a / b by the hardware reciprocal and one Newton-Raphson step on it, then one
-// correction of the quotient (q + r (a - b q)); a few ulps at most, for
-// normal b (the Sturm recurrence keeps |b| >= pivmin >= DBL_MIN).
+// a / b as a times the hardware reciprocal of b refined by one Newton-Raphson
+// step: within a few ulps of the rounded quotient, for normal b (the Sturm
+// recurrence keeps |b| >= pivmin >= DBL_MIN, so 1/b and a/b stay finite).
 __device__ __forceinline__ double div_nr(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   r = fma(fma(-b, r, 1.0), r, r);
-  const double q = a * r;
-  return fma(fma(-b, q, a), r, q);
+  return a * r;
 }
 
 // Number of eigenvalues of T below x (Sturm sequence of the LDL^T
@@ -375,6 +374,23 @@ __device__ __forceinline__ int sturm_count(const double *sd, const double *se2, 
   cnt += qv < 0.0;
   for (int i = 1; i < N; ++i) {
     qv = (sd[i] - x) - div_nr(se2[i - 1], qv);
+    if (fabs(qv) < pivmin) qv = -pivmin;
+    cnt += qv < 0.0;
+  }
+  return cnt;
+}
+
+// The same count from the interleaved pairs sde[i] = (d_i, e_{i-1}^2): one
+// LDS read per step, four steps' reads issued together.
+__device__ __forceinline__ int sturm_count_i(const double2 *sde, int N, double x, double pivmin) {
+  int cnt = 0;
+  double qv = sde[0].x - x;
+  if (fabs(qv) < pivmin) qv = -pivmin;
+  cnt += qv < 0.0;
+#pragma unroll 4
+  for (int i = 1; i < N; ++i) {
+    const double2 de = sde[i];
+    qv = (de.x - x) - div_nr(de.y, qv);
     if (fabs(qv) < pivmin) qv = -pivmin;
     cnt += qv < 0.0;
   }
@@ -421,10 +437,11 @@ __device__ bool load_tridiag(const double *d, const double *e, int64_t q, int64_
 __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *e, int64_t sDE, int N, int lo, int hi,
                                                  double bis_rel, double *evals, double *lamg, double2 *U, int ldu,
                                                  int64_t sU, uint32_t *status) {
-  extern __shared__ double tsm[];
-  double *sd = tsm;          // N
-  double *se2 = sd + N;      // N
-  double *slam = se2 + N;    // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
+  extern __shared__ double2 tsm2[];
+  double2 *sde = tsm2;                                // N: (d_i, e_{i-1}^2)
+  double *sd = reinterpret_cast<double *>(sde + N);  // N
+  double *se2 = sd + N;                               // N
+  double *slam = se2 + N;  // m + 4: [lambda_0, lambda_{N-1}, lambda_{lo-1}, lambda_{hi}, lambda_lo..]
   const int m = hi - lo;
   __shared__ int s_bad;
   __shared__ double mm[3 * (PT / 64)];
@@ -440,6 +457,7 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
     }
     return;
   }
+  for (int i = tid; i < N; i += PT) sde[i] = make_double2(sd[i], i > 0 ? se2[i - 1] : 0.0);
   // Gershgorin interval and pivot threshold
   double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
   for (int i = tid; i < N; i += PT) {
@@ -478,7 +496,7 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
   // subintervals, which replaces the first ~8 bisection steps of every lane
   __shared__ int s_cnt[PT];
   const double hstep = (gu - gl) / double(PT + 1);
-  s_cnt[tid] = sturm_count(sd, se2, N, gl + double(tid + 1) * hstep, pivmin);
+  s_cnt[tid] = sturm_count_i(sde, N, gl + double(tid + 1) * hstep, pivmin);
   __syncthreads();
   const int nidx = m + 4;
   for (int t = tid; t < nidx; t += PT) {
@@ -497,7 +515,7 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
       for (int it = 0; it < 128; ++it) {
         const double mid = 0.5 * (a + b);
         if (b - a <= fmax(2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin, tol_abs) || mid <= a || mid >= b) break;
-        if (sturm_count(sd, se2, N, mid, pivmin) > k) b = mid;
+        if (sturm_count_i(sde, N, mid, pivmin) > k) b = mid;
         else a = mid;
       }
       val = 0.5 * (a + b);
@@ -1202,7 +1220,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   // ---- tridiagonal eigenpairs: bisection, inverse iteration, Gram-Schmidt of shared-block clusters
   const double clu_rel = 64.0 * DBL_EPSILON;
   {
-    const size_t smb = (2 * size_t(N) + m + 4) * sizeof(double);
+    const size_t smb = (4 * size_t(N) + m + 4) * sizeof(double);
     if (smb > 65536)
       BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&tri_bisect),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(smb)));
