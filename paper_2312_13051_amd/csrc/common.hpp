@@ -191,6 +191,10 @@ struct ZGemm {
   // below the diagonal are computed, and each strictly lower tile's conjugate
   // transpose is written to the upper triangle (the old upper values are not read)
   bool herm = false;
+  // optional real row scaling of B (opB = 'N' only): op(B_q) = diag(s_q) B_q
+  // with s_q = scaleB + (q / scaleB_div) * scaleB_ld, applied as B is loaded
+  const double *scaleB = nullptr;
+  int64_t scaleB_div = 1, scaleB_ld = 0;
 };
 
 // C = alpha op(A) op(B) + beta C, FP64 MFMA. C must not alias A or B.

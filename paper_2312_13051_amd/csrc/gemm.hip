@@ -63,6 +63,8 @@ struct GP {
   int64_t batch;
   int tiles_m, tiles_n;
   int herm;  // Hermitian C: lower tiles only, strictly lower tiles mirrored into the upper triangle
+  const double *sB;  // row scales of B (OPB == 0), or null: s_q = sB + (q / sB_div) * sB_ld
+  int64_t sB_div, sB_ld;
 };
 
 // BM x BN block tile, WM x WN waves, each wave (BM/WM) x (BN/WN).
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   const cplx *A = p.A + be::zbatch_off(p.bA, q);
   const cplx *B = p.B + be::zbatch_off(p.bB, q);
   cplx *C = p.C + be::zbatch_off(p.bC, q);
+  const double *sBq = (OPB == 0 && p.sB) ? p.sB + (q / p.sB_div) * p.sB_ld : nullptr;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -144,7 +147,14 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
       cplx v;
       v.x = 0;
       v.y = 0;
-      if (e < BN * KB && gj < p.N && gk < p.K) v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
+      if (e < BN * KB && gj < p.N && gk < p.K) {
+        v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
+        if (sBq) {
+          const T sc = T(sBq[gk]);
+          v.x *= sc;
+          v.y *= sc;
+        }
+      }
       gb[u] = v;
     }
   };
@@ -444,6 +454,10 @@ int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
   p.beta = g.beta;
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
+  BE_CHECK_ARG(ctx, !g.scaleB || (g.opB == 0 && g.scaleB_div >= 1), "zgemm: row scaling of B needs opB = 'N'");
+  p.sB = g.scaleB;
+  p.sB_div = g.scaleB_div;
+  p.sB_ld = g.scaleB_ld;
   return dispatch<double>(ctx, p, g.opA, g.opB, stream);
 }
 
@@ -466,6 +480,9 @@ int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
   p.beta = g.beta;
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
+  p.sB = nullptr;
+  p.sB_div = 1;
+  p.sB_ld = 0;
   return dispatch<float>(ctx, p, g.opA, g.opB, stream);
 }
 

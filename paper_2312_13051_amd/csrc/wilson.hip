@@ -822,18 +822,6 @@ __global__ void k_narrow(const double2 *a, int64_t n, float2 *b) {
     b[i] = make_float2(float(a[i].x), float(a[i].y));
 }
 
-// SU[k] = diag(spin) U[k] for every k of every system (N x m, ld N)
-__global__ void k_spin_scale(const double2 *U, int ldu, int64_t us, const double *spin, int N, int m, int64_t k_per_sys,
-                             int64_t n_k, double2 *SU) {
-  for (int64_t k = blockIdx.y; k < n_k; k += gridDim.y) {
-    const double *sd = spin + (k / k_per_sys) * N;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < int64_t(N) * m; e += int64_t(gridDim.x) * blockDim.x) {
-      int c = int(e / N), r = int(e % N);
-      SU[k * int64_t(N) * m + e] = be::cscale(U[k * us + r + int64_t(c) * ldu], sd[r]);
-    }
-  }
-}
-
 // Projected-spin eigenvalues: copy into the output, count negatives, flag gaps.
 __global__ void k_pso_post(const double *ev, const uint32_t *eig_st, int m, int64_t n_k, int64_t k_per_sys, double *pso,
                            int32_t *cnt, uint32_t *status) {
@@ -885,17 +873,13 @@ namespace {
 // per-k PSO_GAP test and the per-system spin-down sector size m_dn_h (read
 // back, so the stream is synchronized once).
 int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride, int32_t n_sys,
-                      int64_t kps, int32_t precision, const double *spin_diag, double *pso_evals, double2 *SU,
+                      int64_t kps, int32_t precision, const double *spin_diag, double *pso_evals, double2 *A32buf,
                       double2 *A, double2 *Q, double *ev, uint32_t *kst, int32_t *cnt, int32_t *mdn, int32_t *m_dn_h,
                       uint32_t *status, hipStream_t stream) {
   using namespace be;
   const int64_t n_k = int64_t(n_sys) * kps;
   const int64_t mm = int64_t(m) * std::max(m, 1);
-  const int64_t Nm = int64_t(N) * std::max(m, 1);
-  // ---- A = U^H S U
-  hipLaunchKernelGGL(k_spin_scale, dim3(64, static_cast<uint32_t>(std::min<int64_t>(n_k, 65535))), dim3(256), 0, stream,
-                     static_cast<const double2 *>(U), ldu, u_stride, spin_diag, N, m, kps, n_k, SU);
-  BE_RET_IF(check_launch(ctx, "spin_scale"));
+  // ---- A = U^H S U, S applied to the rows of U as the GEMM loads them
   {
     ZGemm g;
     g.M = m;
@@ -905,9 +889,12 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
     g.A = static_cast<const double2 *>(U);
     g.lda = ldu;
     g.bA = ZBatch::strided(u_stride);
-    g.B = SU;
-    g.ldb = N;
-    g.bB = ZBatch::strided(Nm);
+    g.B = static_cast<const double2 *>(U);
+    g.ldb = ldu;
+    g.bB = ZBatch::strided(u_stride);
+    g.scaleB = spin_diag;
+    g.scaleB_div = kps;
+    g.scaleB_ld = N;
     g.C = A;
     g.ldc = m;
     g.bC = ZBatch::strided(mm);
@@ -920,8 +907,8 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
   ctx->prof_scope = "pso_";  // launch-timer names of the inner eigensolver
   int erc;
   if (precision == BE_MIXED_FP32) {
-    // c64 copy of the projected operator in the (now free) S U buffer
-    float2 *A32 = reinterpret_cast<float2 *>(SU);
+    // c64 copy of the projected operator
+    float2 *A32 = reinterpret_cast<float2 *>(A32buf);
     hipLaunchKernelGGL(k_narrow, dim3(static_cast<uint32_t>(std::min<int64_t>((n_k * mm + 255) / 256, 65535))),
                        dim3(256), 0, stream, A, n_k * mm, A32);
     erc = check_launch(ctx, "k_narrow");
@@ -961,12 +948,12 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   const int64_t n_lines = int64_t(n_sys) * n_perp;
   const int64_t mm = int64_t(m) * std::max(m, 1);
   const int64_t Nm = int64_t(N) * std::max(m, 1);
-  double2 *SU = nullptr, *A = nullptr, *Q = nullptr, *V = nullptr;
+  double2 *A32buf = nullptr, *A = nullptr, *Q = nullptr, *V = nullptr;
   double *ev = nullptr;
   uint32_t *kst = nullptr, *lst = nullptr;
   int32_t *cnt = nullptr, *mdn = nullptr;
   Carve cv;
-  cv.add(&SU, size_t(n_k * Nm));
+  cv.add(&A32buf, size_t((n_k * mm + 1) / 2));  // c64 m x m per k (mixed path)
   cv.add(&A, size_t(n_k * mm));
   cv.add(&Q, size_t(n_k * mm));
   cv.add(&V, size_t(n_k * Nm));
@@ -983,7 +970,7 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   BE_RET_IF(check_launch(ctx, "zero"));
   for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
   if (m == 0) return BE_OK;
-  BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, SU, A, Q, ev,
+  BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, A32buf, A, Q, ev,
                               kst, cnt, mdn, m_dn_h, status, stream));
   hipLaunchKernelGGL(k_fill_nan, dim3(static_cast<uint32_t>((n_lines * m + 255) / 256)), dim3(256), 0, stream, theta_dn,
                      n_lines * m);
@@ -1054,12 +1041,12 @@ extern "C" int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m,
   const int64_t n_k = int64_t(n_sys) * kps;
   const int64_t mm = int64_t(m) * std::max(m, 1);
   const int64_t Nm = int64_t(N) * std::max(m, 1);
-  double2 *SU = nullptr, *A = nullptr, *Q = nullptr;
+  double2 *A32buf = nullptr, *A = nullptr, *Q = nullptr;
   double *ev = nullptr;
   uint32_t *kst = nullptr;
   int32_t *cnt = nullptr, *mdn = nullptr;
   Carve cv;
-  cv.add(&SU, size_t(n_k * Nm));
+  cv.add(&A32buf, size_t((n_k * mm + 1) / 2));  // c64 m x m per k (mixed path)
   cv.add(&A, size_t(n_k * mm));
   cv.add(&Q, size_t(n_k * mm));
   cv.add(&ev, size_t(n_k * (m + 2)));
@@ -1072,7 +1059,7 @@ extern "C" int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m,
   BE_RET_IF(check_launch(ctx, "zero"));
   for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
   if (m == 0) return BE_OK;
-  BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, SU, A, Q, ev,
+  BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, A32buf, A, Q, ev,
                               kst, cnt, mdn, m_dn_h, status, stream));
   ZGemm g;  // V = U Q: spin-down columns first (mu ascending)
   g.M = N;
