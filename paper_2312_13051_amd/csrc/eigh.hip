@@ -749,7 +749,8 @@ __device__ __forceinline__ int group_end(const double *lam, const int *mk, int m
 
 // Groups of vectors that share a block of T (inside a cluster of equal
 // eigenvalues; vectors in different blocks have disjoint supports and are
-// orthogonal already) are orthonormalized by two passes of Cholesky QR
+// orthogonal already) are orthonormalized by Cholesky QR (two passes; one
+// for groups larger than GK)
 // (G = V^T V = R^T R, V <- V R^-1), done in lanes: the groups are packed into
 // 64-lane bins (no group straddles a bin), a bin is one wave, vector c sits
 // on one lane, and the rows of X are swept with coalesced loads (the
@@ -757,7 +758,7 @@ __device__ __forceinline__ int group_end(const double *lam, const int *mk, int m
 // other members of a lane's group by cross-lane permutes; the first member of
 // each group factors G in LDS; an apply sweep solves y R = x row by row, the
 // members finalizing y in order and passing it on by permutes. Groups larger
-// than GK run the same passes with the whole workgroup; a breakdown of the
+// than GK run one such pass with the whole workgroup; a breakdown of the
 // Cholesky factorization falls back to modified Gram-Schmidt with one wave
 // per group.
 constexpr int GK = 32;
@@ -887,8 +888,10 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
       __syncthreads();
     }
   }
-  // groups larger than GK: the same two Cholesky-QR passes by the whole
-  // workgroup. The Gram matrix and its factor are kept packed (upper
+  // groups larger than GK: one Cholesky-QR pass by the whole workgroup (its
+  // O(cond^2 eps) loss of orthogonality is removed by the symmetric
+  // Newton-Schulz orthonormalization of all vectors that follows). The Gram
+  // matrix and its factor are kept packed (upper
   // triangle, row by row) in LDS next to a tile of the cluster's rows when
   // they fit (k(k+1)/2 + k <= PT*GK), else in the matrix's m x m scratch Gq.
   // The Gram matrix is accumulated tile by tile, the factorization runs one
@@ -906,7 +909,7 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
       const int RB = in_lds ? (PT * GK - npk) / k : (PT * GK) / k;
       // packed index of (s, t), s <= t
       auto pk = [k](int s2, int t) { return s2 * k - (s2 * (s2 - 1)) / 2 + (t - s2); };
-      for (int pass = 0; pass < 2 && !sfl[c0]; ++pass) {
+      for (int pass = 0; pass < 1 && !sfl[c0]; ++pass) {
         __syncthreads();
         for (int e = tid; e < npk; e += PT) Rp[e] = 0.0;
         // Gram matrix, upper triangle, tile by tile (16 threads per row s2)
