@@ -222,7 +222,7 @@ def main():
                     help="also run one plain device copy of this size (calibrates rocprof byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: berryhip has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.precision is None:
         args.precision = "fp64" if args.workload == "bbh_disorder" else "mixed"
