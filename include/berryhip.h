@@ -158,7 +158,11 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
  * is the gauge-invariant output. Workspace: the context's, grown on demand;
  * batches are processed in equal sub-batches of at most 4 GiB of it, or, for
  * large N where 4 GiB holds fewer matrices than the device runs at once, of
- * up to that many within 48 GiB (at most half the free device memory). */
+ * up to that many within 48 GiB (at most half the free device memory).
+ * Size limit: the panel vectors (2N complex values) and the tridiagonal
+ * solver's arrays ((4N + m + 4) doubles; (3N + m) doubles and N + 1 + 2m
+ * ints) are held in LDS and must fit in 160 KiB, which allows N up to about
+ * 4000 at m = N/2; a larger order returns BE_EINVAL. */
 int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, int64_t mat_stride,
                     int32_t n_mat, int32_t band_lo, int32_t band_hi, int32_t precision, double *evals,
                     void *U, int32_t ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);

@@ -1431,6 +1431,12 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                     int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
                     hipStream_t stream) {
   const int m = band_hi - band_lo;
+  // the panel vectors and the tridiagonal solver's arrays live in LDS
+  const size_t lds_need = std::max({panel_smem(N, sizeof(typename CT<T>::c), ctx->tune_panel_threads),
+                                    (4 * size_t(N) + m + 4) * sizeof(double),
+                                    (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + 2 * size_t(m)) * sizeof(int),
+                                    gs_smem(m)});
+  BE_CHECK_ARG(ctx, lds_need <= 160 * 1024, "be_eigh_batched: order too large for the LDS-resident kernels");
   if (n_mat == 0) return BE_OK;
   // sub-batches bounded to ~4 GiB of workspace; where that holds fewer than
   // one device-wide round of resident panel workgroups (large N), up to one

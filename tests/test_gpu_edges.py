@@ -61,6 +61,9 @@ def test_argument_errors():
         c.eigh_batched(z, 1, 4, 4, 16, 1, 0, 2, 0, d, z, 4, 16, i)      # FP64 needs c128
     with pytest.raises(BerryError):
         c.eigh_batched(z, 0, 4, 3, 16, 1, 0, 2, 0, d, z, 4, 16, i)      # ld < N
+    with pytest.raises(BerryError, match="too large"):                  # order beyond the LDS-resident kernels
+        c.eigh_batched(z, 0, 5000, 5000, 5000 * 5000, 0, 0, 2500, 0, d, z, 5000, 5000 * 2500, i)
+    c.eigh_batched(z, 0, 4000, 4000, 4000 * 4000, 0, 0, 2000, 0, d, z, 4000, 4000 * 2000, i)  # within it: no-op
     with pytest.raises(BerryError):
         c.wilson_loop(z, 4, 2, 4, 8, 1, 4, 4, 7, d, d, i, i)            # bad mode
     with pytest.raises(BerryError):
