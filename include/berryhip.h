@@ -13,7 +13,9 @@
  * - Pointers suffixed _h are host memory; all other array pointers are
  *   device memory owned by the caller. The library never frees caller memory.
  * - Every call is asynchronous on the given stream unless its comment says
- *   it synchronizes. Outputs are valid once the stream has completed.
+ *   it synchronizes. Outputs are valid once the stream has completed. Calls
+ *   that synchronize read convergence data back to the host between
+ *   launches; they cannot be captured into a HIP graph.
  * - Return value: BE_OK (0) or a negative error code; be_last_error() gives
  *   text. Argument errors are detected on the host before any launch.
  * - Physics conditions (closed gaps, singular overlaps, ...) are never
@@ -159,6 +161,8 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
  * batches are processed in equal sub-batches of at most 4 GiB of it, or, for
  * large N where 4 GiB holds fewer matrices than the device runs at once, of
  * up to that many within 48 GiB (at most half the free device memory).
+ * Synchronizes the stream once per sub-batch and orthonormalization step
+ * (the largest Gram error of Z is read back).
  * Size limit: the panel vectors (2N complex values) and the tridiagonal
  * solver's arrays ((4N + m + 4) doubles; (3N + m) doubles and N + 1 + 2m
  * ints) are held in LDS and must fit in 160 KiB, which allows N up to about
@@ -176,7 +180,8 @@ int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, 
  *   winding = (1/2pi) sum_i wrap(Phi_{(i+1) mod n_perp} - Phi_i).
  * U is c128. Outputs (device): theta [n_sys][n_perp][m], phi [n_sys][n_perp],
  * winding [n_sys], status [n_sys] (OVERLAP_SINGULAR, WINDING_UNRESOLVED,
- * NONCONVERGED). */
+ * NONCONVERGED). In polar mode, synchronizes the stream once per
+ * Newton-Schulz iteration (the largest Gram error is read back). */
 int be_wilson_loop(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
                    int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, double *theta, double *phi,
                    int32_t *winding, uint32_t *status, hipStream_t stream);
@@ -191,7 +196,8 @@ int be_wilson_loop(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu
  *   p [n_sys][n_par] = sum nested_theta / 2pi in (-1/2, 1/2],
  *   p_mean [n_sys] = mean of p unwrapped along j, reduced to [0, 1),
  *   s_out_h [n_sys] (host) sector sizes, status [n_sys] (WANNIER_GAP, ...).
- * Synchronizes the stream once (the sector size is read back). */
+ * Synchronizes the stream: the sector size is read back, and in polar mode
+ * each Newton-Schulz iteration reads back its Gram error. */
 int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
                      int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, double win_lo, double win_hi,
                      double *nested_theta, double *p, double *p_mean, int32_t *s_out_h, uint32_t *status,
@@ -210,7 +216,8 @@ int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t l
  * precision selects the eigensolver of A: BE_FP64, or BE_MIXED_FP32 (A
  * rounded to c64, FP32 reduction and back-transformation, FP64 tridiagonal
  * solve and orthonormalization); A, U and everything after are FP64.
- * Synchronizes the stream once (the sector sizes are read back). */
+ * Synchronizes the stream: the sector sizes are read back, and the
+ * eigensolver and the polar steps read back their convergence. */
 int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
                             int32_t n_sys, int32_t n_par, int32_t n_perp, int32_t mode, int32_t precision,
                             const double *spin_diag,
@@ -253,7 +260,8 @@ int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
  *   (host), status [n_sys] (PSO_GAP, NAN_INF, NONCONVERGED).
  * Sector flux maps: be_plaquette_flux on V (m_dn_h[s] columns) and on
  * V + m_dn_h[s]*ldv (m - m_dn_h[s] columns), with ldu = ldv, u_stride = v_stride.
- * Synchronizes the stream once (the sector sizes are read back). */
+ * Synchronizes the stream: the sector sizes are read back, and the
+ * eigensolver reads back its convergence. */
 int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride, int32_t n_sys,
                     int32_t n_k_sys, int32_t precision, const double *spin_diag, double *pso_evals, void *V,
                     int32_t ldv, int64_t v_stride, int32_t *m_dn_h, uint32_t *status, hipStream_t stream);
