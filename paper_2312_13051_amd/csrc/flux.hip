@@ -491,7 +491,7 @@ extern "C" int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t 
         double *ph = dir == 0 ? ph_par : ph_perp, *ld = dir == 0 ? ld_par : ld_perp;
         const dim3 grid(static_cast<uint32_t>(nk));
         if (m <= 128)
-          hipLaunchKernelGGL(k_det_phase_w<16>, grid, dim3(64), size_t(m) * 16 * sizeof(double2) + size_t(m) * 4,
+          hipLaunchKernelGGL(k_det_phase_w<8>, grid, dim3(64), size_t(m) * 8 * sizeof(double2) + size_t(m) * 4,
                              stream, L, m, mm, ph, ld);
         else if (nbw == 16)
           hipLaunchKernelGGL(k_det_phase<16>, grid, dim3(DT), lds, stream, L, m, mm, ph, ld);
