@@ -40,7 +40,8 @@ Method (paper references are to sections and equations):
   insulator: the coupling-matrix method on a grid of plaquettes, per spin
   sector): the phase of the product of the link
   variables det(U(k')^H U(k)) around each plaquette; the sum over the zone
-  is 2 pi times the Chern number. A link with |det| < 1e-8 is flagged.
+  is 2 pi times the Chern number. A link whose smallest singular value is
+  below 1e-8 is flagged, as an overlap of the Wilson loop is.
 * Spectrum of the projected spin operator for any spin operator S (Sec. V,
   the scan over a grid of k-points for a spin axis with a gapped spectrum):
   the eigenvalues of U^H S U in the selected bands.
@@ -355,21 +356,24 @@ def link_phases(U_grid: np.ndarray):
     """Phases of the link variables det(U(k')^H U(k)) between neighbouring
     grid points, along the loop direction (k' = k(i, j+1)) and across it
     (k' = k(i+1, j)), both closing periodically. Returns (phi_par, phi_perp,
-    smallest |det| of any link). A link variable det/|det| is undetermined
-    when |det| vanishes; |det| is the product of the link's singular values,
-    none above 1, so it never exceeds the smallest one."""
+    smallest singular value of any link). A link variable det/|det| is
+    undetermined when the link matrix is singular; the test is the one the
+    Wilson loop applies to its overlaps, sigma_min < 1e-8, which does not
+    depend on the order of the link (|det|, the product of all singular
+    values, shrinks geometrically with the order even when every singular
+    value is close to one)."""
     n_perp, n_par = U_grid.shape[:2]
     phi_par = np.empty((n_perp, n_par))
     phi_perp = np.empty((n_perp, n_par))
-    dmin = np.inf
+    smin = np.inf
     for i in range(n_perp):
         for j in range(n_par):
             for phi, Un in ((phi_par, U_grid[i, (j + 1) % n_par]), (phi_perp, U_grid[(i + 1) % n_perp, j])):
                 L = Un.conj().T @ U_grid[i, j]
-                d = np.linalg.det(L)
-                phi[i, j] = np.angle(d)
-                dmin = min(dmin, float(abs(d)))
-    return phi_par, phi_perp, dmin
+                phi[i, j] = np.angle(np.linalg.det(L))
+                if L.size:
+                    smin = min(smin, float(np.linalg.svd(L, compute_uv=False).min()))
+    return phi_par, phi_perp, smin
 
 
 def plaquette_flux_from_grid(U_grid: np.ndarray):
@@ -387,13 +391,13 @@ def plaquette_flux_from_grid(U_grid: np.ndarray):
     over the zone is an exact multiple of 2 pi (the Chern number).
     Returns flux (n_perp, n_par), chern (int), total (sum / 2 pi), status.
     """
-    phi_par, phi_perp, dmin = link_phases(U_grid)
+    phi_par, phi_perp, smin = link_phases(U_grid)
     F = np.roll(phi_par, -1, axis=0) - phi_par + phi_perp - np.roll(phi_perp, -1, axis=1)
     F = F - TWO_PI * np.round(F / TWO_PI)
     F = np.where(F <= -np.pi, np.pi, F)
     total = F.sum() / TWO_PI
     status = 0
-    if dmin < 1e-8:
+    if smin < 1e-8:
         status |= OVERLAP_SINGULAR
     if np.max(np.abs(F)) > 0.8 * np.pi or abs(total - np.round(total)) > 1e-6:
         status |= WINDING_UNRESOLVED

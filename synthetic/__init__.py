@@ -27,4 +27,9 @@ from .models import (  # noqa: F401
     write_centres,
     kplane,
     concat_hops,
+    link_grid,
+    SERVED_TYPES,
+    served_types,
+    served_model,
+    uneven_systems,
 )

@@ -490,3 +490,53 @@ def kplane(n_par: int, n_perp: int, e_par=(1.0, 0.0, 0.0), e_perp=(0.0, 1.0, 0.0
     j = np.arange(n_par, dtype=np.float64) / n_par
     i = np.arange(n_perp, dtype=np.float64) / n_perp
     return k0[None, None, :] + i[:, None, None] * e_perp[None, None, :] + j[None, :, None] * e_par[None, None, :]
+
+
+def link_grid(cosines) -> np.ndarray:
+    """A 2 x 2 grid of orthonormal bases (N = 2m, m = len(cosines)) whose links
+    along the loop direction have the given singular values: U(i, 0) spans
+    e_0 .. e_{m-1}, U(i, 1) has columns c_k e_k + sqrt(1 - c_k^2) e_{m+k}, so
+    U(i, 1)^H U(i, 0) = diag(c); the links across the loop are identities.
+    Returns (n_perp, n_par, N, m) complex128."""
+    c = np.asarray(cosines, dtype=np.float64)
+    m = c.size
+    A = np.zeros((2 * m, m), dtype=np.complex128)
+    A[np.arange(m), np.arange(m)] = 1.0
+    B = np.zeros((2 * m, m), dtype=np.complex128)
+    B[np.arange(m), np.arange(m)] = c
+    B[m + np.arange(m), np.arange(m)] = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+    return np.stack([np.stack([A, B]), np.stack([A, B])])
+
+
+# ---------------------------------------------------------------- workload mixes
+SERVED_TYPES = ("bhz8", "bhz12", "bhz16", "bhz24", "w96")
+
+
+def served_types(n: int, seed) -> list:
+    """Request types of a served stream of n requests: the five types
+    (BHZ supercells L = 8, 12, 16, 24 and the 96-orbital model) equally
+    often, in a seeded random order (each block of five holds every type once,
+    so any prefix of the stream is balanced to within one request per type)."""
+    rng = np.random.default_rng(list(seed))
+    out = []
+    while len(out) < n:
+        out += [SERVED_TYPES[i] for i in rng.permutation(len(SERVED_TYPES))]
+    return out[:n]
+
+
+def served_model(kind: str, req: int) -> HopList:
+    """The model of request number req of a served stream: a BHZ supercell
+    with Anderson disorder of strength W ~ U[0, 4] (seeded [5, 1, req]), or
+    the 96-orbital model (seeded [5, 2, req])."""
+    if kind == "w96":
+        return wannier_like(96, [5, 2, req])
+    L = int(kind[3:])
+    W = float(np.random.default_rng([5, 3, req]).uniform(0.0, 4.0))
+    return bhz_disordered(L, W, [5, 1, req])
+
+
+def uneven_systems(n: int = 64, sizes=(6, 8, 12, 16, 20), frac: float = 0.02) -> list:
+    """Uneven batch of BHZ supercells: L drawn uniformly from sizes (seeded
+    [4, 0]), round(frac L^2) vacancies each (seeded [4, 1, s]), no disorder."""
+    Ls = np.random.default_rng([4, 0]).choice(np.asarray(sizes), size=n)
+    return [bhz_vacancies(int(L), frac, [4, 1, s]) for s, L in enumerate(Ls)]

@@ -415,11 +415,8 @@ def test_spin_resolved_flux_bhz():
 
 def test_plaquette_flux_singular_link_flagged():
     """The occupied state of two uncoupled orbitals with energies +-cos 2 pi k
-    jumps from one orbital to the other: the link across the switch has
-    det = 0 and its plaquettes are flagged; a smooth grid is not. Every
-    singular value of an overlap of orthonormal bases is at most 1, so
-    |det| <= sigma_min on random overlaps (the flag covers the Wilson-loop
-    criterion sigma_min < 1e-8)."""
+    jumps from one orbital to the other: the link across the switch is the
+    zero matrix and its plaquettes are flagged; a smooth grid is not."""
     from synthetic.models import _from_blocks
     hl = _from_blocks(2, 1, {(0,): np.zeros((2, 2)), (1,): np.diag([0.5, -0.5])})
     kg = syn.kplane(8, 3, k0=(1.0 / 16, 0.0, 0.0))
@@ -427,13 +424,95 @@ def test_plaquette_flux_singular_link_flagged():
     assert f["status"] & orc.OVERLAP_SINGULAR
     f = orc.plaquette_flux(syn.qwz(1.5), syn.kplane(12, 10), 0, 1)
     assert not f["status"] & orc.OVERLAP_SINGULAR
-    rng = np.random.default_rng(5)
-    for _ in range(20):
-        a = np.linalg.qr(rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4)))[0]
-        b = np.linalg.qr(rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4)))[0]
-        L = b.conj().T @ a
-        s = np.linalg.svd(L, compute_uv=False)
-        assert s.max() <= 1 + 1e-12 and abs(np.linalg.det(L)) <= s.min() + 1e-12
+
+
+@pytest.mark.parametrize("m,c", [(100, 0.8), (640, 0.97)])
+def test_flux_singular_flag_independent_of_order(m, c):
+    """Links of order m whose singular values are all c: |det| = c^m is far
+    below 1e-8 (2e-10 and 3e-9), yet every singular value is of order one,
+    so no link is singular and the flux is defined (zero here: the link
+    matrices are real and positive). The Wilson loop's criterion for the
+    same overlaps (sigma_min < 1e-8) agrees."""
+    assert c ** m < 1e-8
+    g = syn.link_grid(np.full(m, c))
+    f = orc.plaquette_flux_from_grid(g)
+    assert not f["status"] & orc.OVERLAP_SINGULAR
+    assert np.max(np.abs(f["flux"])) < 1e-12 and f["chern"] == 0
+    assert not orc.wilson_loop_grid(g)[3] & orc.OVERLAP_SINGULAR
+
+
+@pytest.mark.parametrize("m", [1, 100])
+def test_flux_singular_flag_one_small_singular_value(m):
+    """One singular value of 1e-9 among ones: the link is singular by the
+    sigma_min < 1e-8 test (its |det| is 1e-9 too), and so is the Wilson-loop
+    overlap; 1e-7 is not."""
+    for s, flagged in ((1e-9, True), (1e-7, False)):
+        cs = np.ones(m)
+        cs[m // 2] = s
+        g = syn.link_grid(cs)
+        assert bool(orc.plaquette_flux_from_grid(g)["status"] & orc.OVERLAP_SINGULAR) == flagged
+        assert bool(orc.wilson_loop_grid(g)[3] & orc.OVERLAP_SINGULAR) == flagged
+
+
+def test_wannier_gap_flag_on_window_edge():
+    """Atomic limit: the Wilson loop is the identity, so every phase is 0,
+    exactly on the lower edge of the sector window (0, 1/2)."""
+    out = orc.nested_wilson(syn.atomic([-1.0, -0.5, 2.0]), syn.kplane(6, 4), 0, 2)
+    assert out["status"] & orc.WANNIER_GAP
+
+
+def test_wannier_gap_flag_when_sector_size_varies():
+    """Chern insulator (eq. 4, one band): the single Wilson phase winds once
+    through (-pi, pi] across the transverse direction, so the number of
+    phases inside (0, 1/2) changes from one line to the next although no
+    phase on the grid sits within 1e-6 of a window edge (the transverse grid
+    is shifted off the symmetric lines, where the phase is 0 or pi)."""
+    kg = syn.kplane(12, 16, k0=(0.0, 0.013, 0.0))
+    th = orc.wilson_surface(syn.qwz(1.5), kg, 0, 1)["theta"].ravel() / (2 * np.pi)
+    assert np.min(np.abs(np.concatenate([th, th - 0.5]))) > 1e-6
+    counts = {int(((x > 0) & (x < 0.5)).sum()) for x in th.reshape(-1, 1)}
+    assert counts == {0, 1}
+    out = orc.nested_wilson(syn.qwz(1.5), kg, 0, 1)
+    assert out["status"] & orc.WANNIER_GAP
+    # the BBH model's sector is fixed (one phase per line in (0, 1/2)): no flag
+    assert not orc.nested_wilson(syn.bbh(0.5, 1.0), syn.kplane(10, 10), 0, 2)["status"] & orc.WANNIER_GAP
+
+
+def test_pso_gap_flag_zero_eigenvalue():
+    """A spin operator that vanishes on the occupied orbital: P S P has the
+    eigenvalue 0 exactly."""
+    out = orc.spin_resolved_wilson(syn.atomic([-1.0, 2.0]), np.array([0.0, 1.0]), syn.kplane(4, 3), 0, 1)
+    assert out["status"] & orc.PSO_GAP
+    assert np.max(np.abs(out["mu"])) == 0.0
+
+
+def test_pso_gap_flag_when_sector_count_varies():
+    """Two uncoupled orbitals with energies +-cos 2 pi k and spins +1, -1:
+    the occupied orbital, hence the sign of P S P's single eigenvalue,
+    switches across the zone, so the spin-down count varies while |mu| = 1
+    everywhere."""
+    from synthetic.models import _from_blocks
+    hl = _from_blocks(2, 1, {(0,): np.zeros((2, 2)), (1,): np.diag([0.5, -0.5])})
+    kg = syn.kplane(8, 2, k0=(1.0 / 16, 0.0, 0.0))
+    out = orc.spin_resolved_wilson(hl, np.array([1.0, -1.0]), kg, 0, 1)
+    assert out["status"] & orc.PSO_GAP
+    ev, U, _ = orc.eigh_grid(hl, kg, 0, 1)
+    mus = np.array([orc.spin_sectors(u, np.array([1.0, -1.0]))[0] for u in U.reshape(-1, 2, 1)])
+    assert np.allclose(np.abs(mus), 1.0) and (mus < 0).any() and (mus > 0).any()
+    # the same switch is a PSO gap for the flux of the spin sectors too
+    assert orc.spin_resolved_flux(hl, np.array([1.0, -1.0]), kg, 0, 1)["status"] & orc.PSO_GAP
+
+
+def test_nan_inf_flag():
+    """A non-finite hopping amplitude makes H non-finite at every k: the
+    eigenpairs carry NAN_INF instead of eigenvalues."""
+    hl = syn.qwz(1.5)
+    hl.t = hl.t.copy()
+    hl.t[0] = np.nan
+    ev, U, st = orc.eigh_grid(hl, syn.kplane(3, 2), 0, 1)
+    assert st & orc.NAN_INF
+    assert np.isnan(ev).all()
+    assert not orc.eigh_grid(syn.qwz(1.5), syn.kplane(3, 2), 0, 1)[2] & orc.NAN_INF
 
 
 def test_plaquette_flux_is_local():
