@@ -239,8 +239,11 @@ int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, in
  *   flux [n_sys][n_perp][n_par], total [n_sys] = sum F / 2 pi (an integer
  *   to rounding: every link enters two plaquettes with opposite signs),
  *   chern [n_sys] = the nearest integer, status [n_sys]:
- *   OVERLAP_SINGULAR if some link has |det| < 1e-8 (its phase is then
- *   undetermined; |det| never exceeds the link's smallest singular value),
+ *   OVERLAP_SINGULAR if some link has smallest singular value < 1e-8
+ *   (its phase is then undetermined; the Wilson loop's criterion for its
+ *   overlaps). |det| never exceeds sigma_min, so |det| >= 1e-8 proves a link
+ *   regular; other links get an estimate of sigma_min from their LU factors
+ *   (inverse iteration, an upper bound that converges to it),
  *   WINDING_UNRESOLVED if some |F| > 0.8 pi or |total - chern| > 1e-6
  *   (the grid is too coarse for the flux), NAN_INF (non-finite flux; chern 0).
  * m = 0 gives zero flux; m > 2544 is rejected (BE_EINVAL). The links of one direction for as many systems as

@@ -11,11 +11,11 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_hetrd_panel_bytes_is_one_read_of_the_trailing_square_per_column():
+def test_hetrd_panel_bytes_is_one_triangle_of_the_trailing_matrix_per_column():
     N, n_mat = 37, 3
     brute = 0
-    for j in range(N - 1):
-        brute += (N - j - 1) ** 2
+    for j in range(N - 1):   # reflector column j: trailing matrix rows/cols j+1..N-1, r >= c
+        brute += sum(1 for r in range(j + 1, N) for c in range(j + 1, N) if r >= c)
     assert bench.hetrd_panel_bytes(N, n_mat, 8) == 8 * brute * n_mat
     assert bench.hetrd_panel_bytes(N, n_mat, 16) == 2 * bench.hetrd_panel_bytes(N, n_mat, 8)
 

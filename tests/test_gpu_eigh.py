@@ -53,7 +53,20 @@ def check(Hs, lo, hi, ev, U, st, expect_status=0):
             Pref = V[:, lo:hi] @ V[:, lo:hi].conj().T
             assert np.max(np.abs(P - Pref)) < 1e-10, (q, np.max(np.abs(P - Pref)))
             # U spans an invariant subspace: H U = U (U^H H U) (gauge invariant)
-            assert np.max(np.abs(H @ Uq - Uq @ (Uq.conj().T @ H @ Uq))) < 1e-11 * nrm
+            A = Uq.conj().T @ H @ Uq
+            assert np.max(np.abs(H @ Uq - Uq @ A)) < 1e-11 * nrm
+            # per column: H u_c = lambda_c u_c up to the width of lambda_c's
+            # cluster (eigenvalues of the reference spectrum whose consecutive
+            # gaps are below 1e-9 ||H||: inside such a cluster any orthonormal
+            # basis of its invariant subspace is correct), and U^H H U is
+            # block diagonal over the clusters
+            wl = w[lo:hi]
+            cid = np.concatenate([[0], np.cumsum(np.diff(wl) > 1e-9 * nrm)])
+            width = np.array([np.ptp(wl[cid == k]) for k in cid])
+            res = np.linalg.norm(H @ Uq - Uq * ev[q, 1:m + 1], axis=0)
+            assert np.all(res <= 1e-11 * nrm + width), (q, np.max(res - width))
+            off = np.abs(A) * (cid[:, None] != cid[None, :])
+            assert np.max(off, initial=0.0) < 1e-11 * nrm
         assert st[q] == expect_status, (q, st[q])
 
 
