@@ -253,6 +253,24 @@ int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
                       int32_t n_sys, int32_t n_par, int32_t n_perp, double *flux, int32_t *chern, double *total,
                       uint32_t *status, hipStream_t stream);
 
+/* The plaquette flux of be_plaquette_flux without any device allocation,
+ * for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. Same arguments, layouts,
+ * results and errors as be_plaquette_flux. Its scratch (the link matrices of
+ * one direction for as many systems per pass as fit, and 32 bytes per
+ * k-point) is a fixed array of BE_NOALLOC_SCRATCH_BYTES inside the library,
+ * one per device, held until the process ends; its address is looked up
+ * when a context is created. A call whose single system needs more
+ * (n_par*n_perp*m*m*16 bytes plus 32 per k-point, rounded) returns BE_EINVAL
+ * before any launch. Every call on a device shares that device's array and
+ * leaves its contents behind (nothing in it is read before being written):
+ * calls that overlap in time on one device (other streams or host threads)
+ * race on it and give wrong results. */
+#define BE_NOALLOC_SCRATCH_BYTES (128u << 20)
+int be_plaquette_flux_noalloc(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,
+                              int32_t n_sys, int32_t n_par, int32_t n_perp, double *flux, int32_t *chern,
+                              double *total, uint32_t *status, hipStream_t stream);
+
 /* Spin-sector bases of the occupied space (Sec. IV): the projected spin
  * operator and its eigendecomposition exactly as in be_spin_resolved_wilson,
  * on n_k_sys k-points per system (U matrix (s, k) at (s*n_k_sys + k)*u_stride),

@@ -27,7 +27,8 @@ EXPORTS = [
     "be_create", "be_destroy", "be_last_error", "be_workspace_bytes",
     "be_hk_plan_create", "be_hk_plan_destroy", "be_hk_plan_N",
     "be_build_hk", "be_eigh_batched", "be_wilson_loop", "be_nested_wilson",
-    "be_spin_resolved_wilson", "be_plaquette_flux", "be_spin_sectors", "be_zgemm_strided",
+    "be_spin_resolved_wilson", "be_plaquette_flux", "be_plaquette_flux_noalloc", "be_spin_sectors",
+    "be_zgemm_strided",
     "be_profile_enable", "be_profile_query", "be_profile_names", "be_tune_set", "be_tune_get",
 ]
 
@@ -71,6 +72,7 @@ def load():
     lib.be_spin_resolved_wilson.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp]
     lib.be_plaquette_flux.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.be_plaquette_flux_noalloc.argtypes = lib.be_plaquette_flux.argtypes
     lib.be_spin_sectors.argtypes = [vp, vp, i32, i32, i32, i64, i32, i32, i32, vp, vp, vp, i32, i64,
                                     C.POINTER(i32), vp, vp]
     lib.be_zgemm_strided.argtypes = [vp, C.c_char, C.c_char, i32, i32, i32, f64p, vp, i32, i64, vp, i32, i64,
@@ -193,6 +195,11 @@ class Context:
     def plaquette_flux(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status):
         self._check(self.lib.be_plaquette_flux(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
                                                _ptr(flux), _ptr(chern), _ptr(total), _ptr(status), _stream()))
+
+    def plaquette_flux_noalloc(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status):
+        self._check(self.lib.be_plaquette_flux_noalloc(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par,
+                                                       n_perp, _ptr(flux), _ptr(chern), _ptr(total), _ptr(status),
+                                                       _stream()))
 
     def spin_sectors(self, U, N, m, ldu, u_stride, n_sys, n_k_sys, spin_diag, pso_evals, V, ldv, v_stride, status,
                      precision=BE_FP64):

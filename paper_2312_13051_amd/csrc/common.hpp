@@ -83,6 +83,11 @@ class Carve {
   }
   size_t total() const { return total_; }
   int commit(be_ctx *ctx, hipStream_t stream, int slot);
+  // resolve the pointers into caller-provided memory of at least total() bytes
+  void place(void *base) {
+    char *b = static_cast<char *>(base);
+    for (size_t k = 0; k < slots_.size(); ++k) *slots_[k] = b + offs_[k];
+  }
 
  private:
   std::vector<void **> slots_;
@@ -241,6 +246,10 @@ struct DGemm {
   bool sym = false;  // C (square) is symmetric: as ZGemm::herm, without conjugation
 };
 int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream);
+
+// Device address of the fixed scratch of the no-allocation entry point for
+// `device` (current), looked up once; called by be_create.
+int noalloc_scratch_init(be_ctx *ctx, int device);
 
 // Batched eigensolver for bands [band_lo, band_hi) (uses slot WS_EIGH): FP64,
 // or mixed (c64 input, FP32 reduction and back-transformation, FP64

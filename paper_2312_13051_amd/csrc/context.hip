@@ -101,6 +101,12 @@ int be_create(be_ctx **ctx, int device) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  const int rc = be::noalloc_scratch_init(c, device);
+  if (rc != BE_OK) {
+    (void)hipHostFree(c->pinned);
+    delete c;
+    return rc;
+  }
   *ctx = c;
   return BE_OK;
 }

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -587,6 +588,36 @@ __global__ void k_zero_st(uint32_t *p, int64_t n) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- scratch without allocation
+// Fixed device scratch of be_plaquette_flux_noalloc (one copy per device,
+// held for the life of the process). Host code never uses the array's name
+// as an address: its device address comes from hipGetSymbolAddress, taken
+// once per device at context creation.
+static __device__ __align__(256) unsigned char scratch[BE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+namespace be {
+// Called by be_create with `device` current.
+int noalloc_scratch_init(be_ctx *ctx, int device) {
+  if (device < 0 || device >= kMaxDevices) return set_err(ctx, BE_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return BE_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return set_err(ctx, BE_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = ptr;
+  return BE_OK;
+}
+}  // namespace be
+
 namespace {
 
 // Scratch of one flux call: the links of one direction for spp systems and
@@ -712,5 +743,39 @@ extern "C" int be_plaquette_flux(be_ctx *ctx, const void *U, int32_t N, int32_t 
   Carve cv;
   fs.declare(cv, spp, kps, mm);
   BE_RET_IF(cv.commit(ctx, stream, WS_WILSON));
+  return flux_run(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status, fs, spp, stream);
+}
+
+extern "C" int be_plaquette_flux_noalloc(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu,
+                                         int64_t u_stride, int32_t n_sys, int32_t n_par, int32_t n_perp, double *flux,
+                                         int32_t *chern, double *total, uint32_t *status, hipStream_t stream) {
+  using namespace be;
+  BE_RET_IF(check_flux_args(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status));
+  if (n_sys == 0) return BE_OK;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+  }
+  if (!base) return set_err(ctx, BE_EHIP, "be_plaquette_flux_noalloc: no scratch address for this device");
+  const int64_t kps = int64_t(n_par) * n_perp;
+  const int64_t mm = int64_t(std::max(m, 1)) * std::max(m, 1);
+  // as many systems per pass as the fixed scratch holds (at least one)
+  auto bytes = [&](int64_t spp) {
+    FluxScratch f;
+    Carve c;
+    f.declare(c, spp, kps, mm);
+    return c.total();
+  };
+  const size_t cap = size_t(BE_NOALLOC_SCRATCH_BYTES);
+  if (bytes(1) > cap)
+    return set_err(ctx, BE_EINVAL, "be_plaquette_flux_noalloc: one system needs " + std::to_string(bytes(1)) +
+                                       " bytes of scratch, more than the fixed " + std::to_string(cap));
+  int64_t spp = std::min<int64_t>(n_sys, std::max<int64_t>(1, int64_t(cap / bytes(1))));
+  while (spp > 1 && bytes(spp) > cap) --spp;
+  FluxScratch fs;
+  Carve cv;
+  fs.declare(cv, spp, kps, mm);
+  cv.place(base);
   return flux_run(ctx, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status, fs, spp, stream);
 }
