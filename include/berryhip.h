@@ -139,11 +139,13 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
 /* Rows (a3)-(a5) -- batched Hermitian eigensolver (Sec. I: exact
  * diagonalization at many k-points; the selected bands, eq. 2).
  * n_mat matrices of order N (H + q*mat_stride, leading dimension ld, BE_C128
- * for BE_FP64 or BE_C64 for BE_MIXED_FP32). Both triangles are read and must
- * hold the same Hermitian matrix (as be_build_hk writes it). H is overwritten
- * (its columns hold the Householder vectors afterwards).
+ * for BE_FP64 or BE_C64 for BE_MIXED_FP32). Only the lower triangle and the
+ * diagonal are read (the diagonal's imaginary parts are taken as zero); the
+ * upper triangle is ignored. H is overwritten (its columns hold the
+ * Householder vectors afterwards; the upper triangle is left undefined).
  * Steps: blocked Householder reduction to real tridiagonal form (panel
- * kernel + MFMA rank-2k trailing updates), FP64 bisection for eigenvalues
+ * kernel whose matrix-vector products read the lower triangle once per
+ * column + MFMA rank-2k trailing updates of the lower triangle), FP64 bisection for eigenvalues
  * [lo-1, hi], FP64 inverse iteration for bands [lo, hi) (Cholesky QR inside
  * clusters of eigenvalues equal within 64 eps ||T||), FP64 Newton-Schulz
  * orthonormalization of the tridiagonal eigenvectors, back-transformation

@@ -194,8 +194,10 @@ struct ZGemm {
   const char *tag = "zgemm";  // profiling label of the call site
   // C (square) is Hermitian and the update keeps it so: only tiles on or
   // below the diagonal are computed, and each strictly lower tile's conjugate
-  // transpose is written to the upper triangle (the old upper values are not read)
+  // transpose is written to the upper triangle (the old upper values are not
+  // read), unless herm_mirror is false (callers that read the lower triangle only)
   bool herm = false;
+  bool herm_mirror = true;
   // optional real row scaling of B (opB = 'N' only): op(B_q) = diag(s_q) B_q
   // with s_q = scaleB + (q / scaleB_div) * scaleB_ld, applied as B is loaded
   const double *scaleB = nullptr;
@@ -223,6 +225,7 @@ struct CGemm {
   int64_t batch = 0;
   const char *tag = "cgemm";
   bool herm = false;  // as in ZGemm
+  bool herm_mirror = true;
 };
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
 

@@ -5,10 +5,11 @@
 //    One workgroup per matrix runs a panel of nb columns (hetrd_panel): for
 //    each column it applies the panel's earlier reflectors to that column,
 //    builds the reflector, forms the matrix-vector product with the trailing
-//    matrix (full square, (64-row block x column slice) work items, v
-//    broadcast from LDS) and the symmetric rank-2 correction vector w. The
-//    trailing matrix is then updated once per panel by a rank-2nb MFMA GEMM,
-//    C -= [V W] [W V]^H (lower tiles, mirrored into the upper triangle). The
+//    matrix from its lower triangle only (each 64 x 64 tile read once and
+//    applied as A v and A^H v) and the symmetric rank-2 correction vector w.
+//    The trailing matrix is then updated once per panel by a rank-2nb MFMA
+//    GEMM, C -= [V W] [W V]^H, on its lower tiles only (the upper triangle is
+//    never read again). The
 //    panel's compact-WY factor T (Q_panel = I - V T V^H) is accumulated on the
 //    fly from the same dot products.
 // 2. FP64 tridiagonal eigensolver (tri_bisect, tri_invit, tri_gs): bisection with Sturm counts,
@@ -30,6 +31,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -56,6 +58,18 @@ __host__ __device__ __forceinline__ C mk(double x, double y) {
   r.y = y;
   return r;
 }
+
+// Byte offset of the panel kernel's partial vectors in its dynamic LDS: after
+// v, y (N each), four NB vectors, the NB x NB T factor and the reduction
+// scratch (2 values per wave), 64-byte aligned.
+__host__ __device__ inline size_t panel_part_offset(int N, size_t csize, int nt) {
+  return ((2 * size_t(N) + 4 * NB + NB * NB) * csize + 2 * size_t(nt / 64) * (csize / 2) + 63) & ~size_t(63);
+}
+
+// Column groups per tile of the panel's matrix-vector product for a trailing
+// matrix of nrb 64-row blocks: small trailing matrices have few tiles, so each
+// tile is split into S groups of 64/S columns to give every wave work.
+__host__ __device__ inline int panel_split(int nrb) { return nrb >= 5 ? 1 : nrb >= 3 ? 2 : 4; }
 
 // ---------------------------------------------------------------- reductions
 template <typename T>
@@ -87,15 +101,57 @@ __device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
   __syncthreads();
 }
 
+// Column sums over the 64 lanes of a wave for CW columns at once (CW = 8 or
+// 16): lane L holds the products of its row with the CW columns in
+// (pr[c], pi[c]). Butterfly transpose: at offset o (32, 16, ...) each lane
+// keeps the half of its columns selected by bit o of L, adds the partner's
+// copy of that half and passes on the other half, so every exchange halves
+// the columns a lane holds; after log2(CW) exchanges lane L holds one column,
+// c = L >> log2(64/CW), summed over the lanes that differ in the upper bits,
+// and the remaining offsets (lanes holding the same column) are summed
+// plainly. Every lane returns the complete sum of its column c; the order of
+// the additions is fixed.
+template <int CW, typename C>
+__device__ __forceinline__ C xpose_colsum(C (&p)[CW], int lane) {
+  constexpr int LOG = CW == 16 ? 4 : CW == 8 ? 3 : CW == 4 ? 2 : 1;
+#pragma unroll
+  for (int st = 0; st < LOG; ++st) {
+    const int h = CW >> (st + 1), o = 32 >> st;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int t = 0; t < h; ++t) {
+      const C lo = p[t], hi = p[t + h];
+      const C send = up ? lo : hi;
+      const C keep = up ? hi : lo;
+      p[t].x = keep.x + __shfl_xor(send.x, o, 64);
+      p[t].y = keep.y + __shfl_xor(send.y, o, 64);
+    }
+  }
+  C a = p[0];
+#pragma unroll
+  for (int o = 32 / CW; o >= 1; o >>= 1) {
+    a.x += __shfl_xor(a.x, o, 64);
+    a.y += __shfl_xor(a.y, o, 64);
+  }
+  return a;
+}
+
 // ---------------------------------------------------------------- panel kernel
-// A: matrices (full Hermitian storage), VW: [V | W | V] panel buffers (N x 3NB,
-// leading dimension N), Tm: per-matrix NB x NB compact-WY factor of each
-// panel, d/e: FP64 tridiagonal output.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
+// A: matrices (lower triangle and diagonal read; the upper triangle is
+// ignored), VW: [V | W | V] panel buffers (N x 3NB, leading dimension N), Tm:
+// per-matrix NB x NB compact-WY factor of each panel, d/e: FP64 tridiagonal
+// output. Partial vectors of the matrix-vector product: in LDS after the
+// panel's other arrays (PL), else at Pg + q*sPg (global scratch of
+// (nrb+1)*nrb*64 elements, nrb = ceil((N-1)/64)).
+template <typename T, int NT, bool PL>
+__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 6 : 1) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
                                                   typename CT<T>::c *VW, int64_t sVW, typename CT<T>::c *Tm,
-                                                  int64_t sTm, double *d, double *e, int64_t sDE, uint32_t *status) {
+                                                  int64_t sTm, double *d, double *e, int64_t sDE,
+                                                  typename CT<T>::c *Pg, int64_t sPg, uint32_t *status) {
   typedef typename CT<T>::c C;
+  // columns per transposed column sum = loads in flight per lane (64 bytes)
+  constexpr int CW = 4;
+  constexpr int CSH = 4;  // lane -> column shift of xpose_colsum<CW>
   extern __shared__ unsigned char smem_raw[];
   C *sv = reinterpret_cast<C *>(smem_raw);  // v, length N
   C *sy = sv + N;                           // y / w, length N
@@ -104,13 +160,13 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
   C *st1 = sWr + NB;                        // W^H v (NB)
   C *st2 = st1 + NB;                        // V^H v (NB)
   C *sT = st2 + NB;                         // NB x NB, column-major
-  C *spart = sT + NB * NB;                  // per-lane partial sums of H v (NT)
-  T *red = reinterpret_cast<T *>(spart + NT);  // 2 * waves
+  T *red = reinterpret_cast<T *>(sT + NB * NB);  // 2 * waves
   __shared__ C s_tau, s_scal;
   __shared__ T s_beta;
 
   const int64_t q = blockIdx.x;
   C *Aq = A + q * sA;
+  C *part = PL ? reinterpret_cast<C *>(smem_raw + panel_part_offset(N, sizeof(C), NT)) : Pg + q * sPg;
   C *V = VW + q * sVW;
   C *W = V + int64_t(NB) * N;
   C *V2 = W + int64_t(NB) * N;
@@ -208,68 +264,101 @@ __global__ __launch_bounds__(NT) void hetrd_panel(typename CT<T>::c *A, int64_t 
       V2[r + int64_t(jj) * N] = v;
     }
     __syncthreads();
-    // ---- (3) y = A(j+1:N, j+1:N) v over the full trailing square. Work items
-    // are (64-row block, column slice) pairs, enough of them to give every
-    // wave one; each lane owns one row, v is broadcast from LDS and every load
-    // is one coalesced 64-row column segment. With several slices each wave
-    // holds at most one item; the slices' partial sums are combined in a fixed
-    // order through LDS, so the result does not depend on scheduling.
+    // ---- (3) y = A(j+1:N, j+1:N) v from the lower triangle only. The
+    // trailing matrix is cut into 64 x 64 tiles (bi, bj), bi >= bj, counted
+    // from row j+1, each split into S groups of columns (S = 1 unless the
+    // trailing matrix is small); a work item (tile, group) is read once, by one
+    // wave (lane = row, coalesced 64-row column segments), and applied twice:
+    // A_t v (row sums in the lane) to block bi and A_t^H v (column sums over
+    // lanes, xpose_colsum) to block bj. A diagonal tile reads only its entries
+    // on and below the diagonal. The partial vectors go to slots of 64
+    // elements, per block b: first a row slot for each (bj <= b, group), then
+    // a column slot for each bi >= b (bi = b: the diagonal tile's column
+    // part); the slots of a row are summed in this order, so the result does
+    // not depend on scheduling.
     const int r0 = j + 1;
-    const int nrow = N - r0;
-    const int nrb = (nrow + 63) / 64;
-    const int ncs = max(1, nw / nrb);
-    const int clen = (nrow + ncs - 1) / ncs;
-    auto slice_dot = [&](int rb, int cs, T &yr, T &yi) {
-      const int r = r0 + rb * 64 + lane;
-      const int cb = r0 + cs * clen, ce = min(N, cb + clen);
-      yr = 0;
-      yi = 0;
-      if (r >= N) return;
-      const C *col = Aq + r;
-      int c = cb;
-      // UN independent column loads in flight per lane (64 B in c64, 128 B in
-      // c128: measured faster than 16 c64 loads, which cost registers and
-      // occupancy)
-      constexpr int UN = 8;
-      for (; c + UN <= ce; c += UN) {
-        C a[UN];
+    const int nrb = (N - r0 + 63) >> 6;
+    const int S = panel_split(nrb), gw = 64 / S;  // groups per tile, columns per group
+    const int nslot = nrb * S + 1;                // slots per block (at most)
+    {
+      // items it = t S + g over tiles t = bi (bi + 1) / 2 + bj in row-major
+      // order of the lower triangle, dealt round-robin to the waves; all
+      // indices stay wave-uniform (scalar)
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
+      const int nitem = nrb * (nrb + 1) / 2 * S;
+      int it = wv, t = it / S, bi = 0, bj = t;
+      while (bj > bi) {
+        bj -= bi + 1;
+        ++bi;
+      }
+      while (it < nitem) {
+        const int g = it - t * S;
+        const bool diag = bi == bj;
+        const int r = r0 + 64 * bi + lane, cb0 = r0 + 64 * bj + g * gw;
+        const bool rok = r < N;
+        const C vr = rok ? sv[r] : mk<C>(0, 0);
+        const uint32_t roff = uint32_t(rok ? r : r0) * uint32_t(sizeof(C));
+        C *pcol = part + (bj * nslot + (bj + 1) * S + (bi - bj)) * 64 + g * gw;
+        T yr = 0, yi = 0;
+        // one chunk of CW columns: loads (all in flight), row part, column part
+        auto chunk = [&](const int k, auto full_tag) {
+          constexpr bool full = decltype(full_tag)::value;  // interior tile: nothing masked
+          const int c0 = cb0 + k;
+          const C *cp = Aq + int64_t(c0) * lda;  // uniform: column c0, row 0
+          C a[CW];
 #pragma unroll
-        for (int u = 0; u < UN; ++u) a[u] = col[int64_t(c + u) * lda];
+          for (int u = 0; u < CW; ++u) {
+            const int c = c0 + u;
+            // uniform column base plus one 32-bit per-lane row offset
+            const C *ap = reinterpret_cast<const C *>(reinterpret_cast<const char *>(cp + int64_t(u) * lda) + roff);
+            if (full)
+              a[u] = *ap;
+            else
+              a[u] = (c < N && rok && (!diag || r >= c)) ? *ap : mk<C>(0, 0);
+          }
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          const C v = sv[c + u];
-          yr += a[u].x * v.x - a[u].y * v.y;
-          yi += a[u].x * v.y + a[u].y * v.x;
+          for (int u = 0; u < CW; ++u) {
+            const int c = c0 + u;
+            const C vc = (full || c < N) ? sv[c] : mk<C>(0, 0);
+            const bool dg = !full && diag && r == c;
+            const T ax = a[u].x, ay = dg ? T(0) : a[u].y;  // the diagonal is real
+            yr += ax * vc.x - ay * vc.y;
+            yi += ax * vc.y + ay * vc.x;
+            // column part: conj(a) v_r (the diagonal entry is in the row part)
+            a[u] = dg ? mk<C>(0, 0) : mk<C>(ax * vr.x + ay * vr.y, ax * vr.y - ay * vr.x);
+          }
+          const C sc = xpose_colsum<CW>(a, lane);
+          if ((lane & ((1 << CSH) - 1)) == 0) pcol[k + (lane >> CSH)] = sc;
+        };
+        if (!diag && 64 * (bi + 1) <= N - r0) {
+#pragma unroll 1
+          for (int k = 0; k < gw; k += CW) chunk(k, std::true_type{});
+        } else {
+#pragma unroll 1
+          for (int k = 0; k < gw; k += CW) chunk(k, std::false_type{});
+        }
+        part[(bi * nslot + bj * S + g) * 64 + lane] = mk<C>(yr, yi);
+        it += nw;
+        const int t2 = it / S;
+        bj += t2 - t;
+        t = t2;
+        while (bj > bi) {
+          bj -= bi + 1;
+          ++bi;
         }
       }
-      for (; c < ce; ++c) {
-        C a = col[int64_t(c) * lda], v = sv[c];
-        yr += a.x * v.x - a.y * v.y;
-        yi += a.x * v.y + a.y * v.x;
+    }
+    __syncthreads();
+    for (int r = r0 + tid; r < N; r += NT) {
+      const int b = (r - r0) >> 6, l = (r - r0) & 63;
+      const C *pb = part + b * nslot * 64 + l;
+      T sr = 0, si = 0;
+      for (int s2 = 0; s2 < (b + 1) * S + nrb - b; ++s2) {  // row slots, then column slots
+        const C x = pb[s2 * 64];
+        sr += x.x;
+        si += x.y;
       }
-    };
-    if (ncs == 1) {
-      for (int rb = wave; rb < nrb; rb += nw) {
-        T yr, yi;
-        slice_dot(rb, 0, yr, yi);
-        const int r = r0 + rb * 64 + lane;
-        if (r < N) sy[r] = mk<C>(yr, yi);
-      }
-    } else {
-      T yr = 0, yi = 0;
-      if (wave < nrb * ncs) slice_dot(wave % nrb, wave / nrb, yr, yi);
-      spart[tid] = mk<C>(yr, yi);
-      __syncthreads();
-      for (int r = r0 + tid; r < N; r += NT) {
-        const int rb = (r - r0) >> 6, l = (r - r0) & 63;
-        T sr = 0, si = 0;
-        for (int cs = 0; cs < ncs; ++cs) {
-          const C pp = spart[(rb + cs * nrb) * 64 + l];
-          sr += pp.x;
-          si += pp.y;
-        }
-        sy[r] = mk<C>(sr, si);
-      }
+      sy[r] = mk<C>(sr, si);
     }
     // ---- (4) t1 = W^H v, t2 = V^H v over rows j+1..N-1 (one wave per column c)
     for (int c = wave; c < jj; c += nw) {
@@ -1115,8 +1204,38 @@ __global__ void assemble_tpair(const C *T1, const C *T2, int64_t sT, C *Tb, int 
   }
 }
 
-size_t panel_smem(int N, size_t csize, int nt) {
-  return (2 * size_t(N) + 4 * NB + NB * NB + nt) * csize + 2 * (nt / 64) * (csize / 2) + 64;
+size_t panel_smem(int N, size_t csize, int nt) { return panel_part_offset(N, csize, nt) + 64; }
+
+// Bytes of the matrix-vector product's partial vectors for trailing matrices
+// of order up to n: nrb S + 1 slots of 64 elements per 64-row block, the
+// largest over nrb <= ceil(n / 64).
+size_t panel_part_bytes(int n, size_t csize) {
+  const int nrb_max = (std::max(n, 0) + 63) / 64;
+  size_t slots = 0;
+  for (int nrb = 1; nrb <= nrb_max; ++nrb) slots = std::max(slots, size_t(nrb) * (size_t(nrb) * panel_split(nrb) + 1));
+  return slots * 64 * csize;
+}
+
+// The partial vectors stay in LDS while the panel's LDS remains within
+// 53 KiB (three workgroups per compute unit); larger orders keep them in a
+// global scratch slot per matrix (written and read back through L2).
+constexpr size_t kPanelLdsMax = 53 * 1024;
+bool panel_part_lds(int N, size_t csize, int nt) {
+  return panel_smem(N, csize, nt) + panel_part_bytes(N - 1, csize) <= kPanelLdsMax;
+}
+size_t panel_lds(int N, size_t csize, int nt) {
+  return panel_smem(N, csize, nt) + (panel_part_lds(N, csize, nt) ? panel_part_bytes(N - 1, csize) : 0);
+}
+
+template <typename T>
+using PanelFn = void (*)(typename CT<T>::c *, int64_t, int, int, int, int, typename CT<T>::c *, int64_t,
+                         typename CT<T>::c *, int64_t, double *, double *, int64_t, typename CT<T>::c *, int64_t,
+                         uint32_t *);
+
+template <typename T>
+PanelFn<T> panel_kernel(int nt, bool pl) {
+  if (pl) return nt == 256 ? &hetrd_panel<T, 256, true> : nt == 512 ? &hetrd_panel<T, 512, true> : &hetrd_panel<T, 1024, true>;
+  return nt == 256 ? &hetrd_panel<T, 256, false> : nt == 512 ? &hetrd_panel<T, 512, false> : &hetrd_panel<T, 1024, false>;
 }
 
 }  // namespace
@@ -1173,16 +1292,20 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   cv.add(&Sw, size_t(nb_mat) * NB * NB);
   cv.add(&Ww, size_t(nb_mat) * NB * NB);
   if (mixed) cv.add(&Uw, size_t(nb_mat) * N * std::max(m, 1));
+  // panel kernel: 256, 512 or 1024 threads per matrix; partial vectors of its
+  // matrix-vector product in LDS or in global scratch
+  const int pnt = ctx->tune_panel_threads;
+  const bool pl = panel_part_lds(N, sizeof(C), pnt);
+  const size_t psm = panel_lds(N, sizeof(C), pnt);
+  const int64_t sPg = pl ? 0 : int64_t(panel_part_bytes(N - 1, 1));
+  C *Pg = nullptr;
+  if (!pl) cv.add(&Pg, size_t(nb_mat) * sPg);
   BE_RET_IF(cv.commit(ctx, stream, WS_EIGH));
   hipLaunchKernelGGL(zero_u32, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, status, nb_mat);
   BE_RET_IF(check_launch(ctx, "zero_u32"));
   const int64_t sVW = int64_t(N) * 3 * NB;
   const int64_t sT = int64_t(P) * NB * NB;
-  // panel kernel: 256, 512 or 1024 threads per matrix
-  const int pnt = ctx->tune_panel_threads;
-  const size_t psm = panel_smem(N, sizeof(C), pnt);
-  void (*panel)(C *, int64_t, int, int, int, int, C *, int64_t, C *, int64_t, double *, double *, int64_t, uint32_t *) =
-      pnt == 256 ? &hetrd_panel<T, 256> : pnt == 512 ? &hetrd_panel<T, 512> : &hetrd_panel<T, 1024>;
+  PanelFn<T> panel = panel_kernel<T>(pnt, pl);
   if (psm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)));
@@ -1192,7 +1315,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     {
       ProfScope prof(ctx, "hetrd_panel", stream);
       hipLaunchKernelGGL(panel, dim3(nb_mat), dim3(pnt), psm, stream, H, ms, ld, N, p0, nbp, VW, sVW,
-                         Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), status);
+                         Tm + int64_t(p) * NB * NB, sT, dd, ee, int64_t(N), Pg, sPg, status);
     }
     BE_RET_IF(check_launch(ctx, "hetrd_panel"));
     const int n2 = N - p0 - NB;
@@ -1217,6 +1340,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.batch = nb_mat;
       g.tag = "her2k";
       g.herm = true;
+      g.herm_mirror = false;  // the panel reads the lower triangle only
       BE_RET_IF(GemmOf<T>::run(ctx, g, stream));
     }
   }
@@ -1412,9 +1536,8 @@ template <typename T>
 static int64_t panel_slots(be_ctx *ctx, int N) {
   typedef typename CT<T>::c C;
   const int pnt = ctx->tune_panel_threads;
-  const size_t psm = panel_smem(N, sizeof(C), pnt);
-  void (*panel)(C *, int64_t, int, int, int, int, C *, int64_t, C *, int64_t, double *, double *, int64_t, uint32_t *) =
-      pnt == 256 ? &hetrd_panel<T, 256> : pnt == 512 ? &hetrd_panel<T, 512> : &hetrd_panel<T, 1024>;
+  const size_t psm = panel_lds(N, sizeof(C), pnt);
+  PanelFn<T> panel = panel_kernel<T>(pnt, panel_part_lds(N, sizeof(C), pnt));
   int per_cu = 0;
   if (psm > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)) != hipSuccess)
@@ -1433,7 +1556,7 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
                     hipStream_t stream) {
   const int m = band_hi - band_lo;
   // the panel vectors and the tridiagonal solver's arrays live in LDS
-  const size_t lds_need = std::max({panel_smem(N, sizeof(typename CT<T>::c), ctx->tune_panel_threads),
+  const size_t lds_need = std::max({panel_lds(N, sizeof(typename CT<T>::c), ctx->tune_panel_threads),
                                     (4 * size_t(N) + m + 4) * sizeof(double),
                                     (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + 2 * size_t(m)) * sizeof(int),
                                     gs_smem(m)});
@@ -1447,6 +1570,7 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   const size_t cs = sizeof(typename CT<T>::c);
   const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 4 * size_t(NB) * std::max(m, 1) +
                            6 * size_t(NB) * NB + size_t(N) * std::max(m, 1)) +
+                     (panel_part_lds(N, cs, ctx->tune_panel_threads) ? 0 : panel_part_bytes(N - 1, cs)) +
                      sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) +
                                        size_t(m) + 1) +
                      sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;

@@ -62,7 +62,8 @@ struct GP {
   cplx alpha, beta;
   int64_t batch;
   int tiles_m, tiles_n;
-  int herm;  // Hermitian C: lower tiles only, strictly lower tiles mirrored into the upper triangle
+  int herm;  // Hermitian C: lower tiles only, strictly lower tiles mirrored into the upper triangle (if mirror)
+  int mirror;
   const double *sB;  // row scales of B (OPB == 0), or null: s_q = sB + (q / sB_div) * sB_ld
   int64_t sB_div, sB_ld;
 };
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
             out.y += p.beta.x * c.y + p.beta.y * c.x;
           }
           C[idx] = out;
-          if (p.herm && tm > tn) {
+          if (p.herm && p.mirror && tm > tn) {
             cplx o2 = out;
             o2.y = -out.y;
             C[gj + int64_t(gi) * p.ldc] = o2;
@@ -454,6 +455,7 @@ int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
   p.beta = g.beta;
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
+  p.mirror = g.herm_mirror ? 1 : 0;
   BE_CHECK_ARG(ctx, !g.scaleB || (g.opB == 0 && g.scaleB_div >= 1), "zgemm: row scaling of B needs opB = 'N'");
   p.sB = g.scaleB;
   p.sB_div = g.scaleB_div;
@@ -480,6 +482,7 @@ int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
   p.beta = g.beta;
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
+  p.mirror = g.herm_mirror ? 1 : 0;
   p.sB = nullptr;
   p.sB_div = 1;
   p.sB_ld = 0;
