@@ -34,6 +34,13 @@ import synthetic as syn  # noqa: E402
 
 METRIC = "Wilson-loop k-point solves/s at ≤1e-6 phase err vs FP64; p50/p99 latency"
 METRIC_FLUX = "Berry-flux (plaquette) k-point solves/s at ≤1e-6 flux err vs FP64; p50/p99 latency"
+
+PRECISION_TEXT = {
+    "fp64": "FP64 path",
+    "mixed": "mixed path: FP32 Householder reduction and back-transformation on MFMA, FP64 elsewhere",
+    "refined": "refined mixed path: FP32 Householder reduction and back-transformation on MFMA for all bands, "
+               "FP64 first-order correction of the occupied subspace from the other bands on MFMA, FP64 elsewhere",
+}
 L_SC, N_PAR, N_PERP = 10, 24, 24
 W_VALUES = (0.0, 1.0, 2.0, 3.0)
 REALIZATIONS = 16
@@ -90,14 +97,23 @@ def _oracle_strip(args):
     return (w_idx, r, i, out["flux_dn"][0], out["flux_up"][0])
 
 
-def cpu_baseline(sample, workers, fn=_oracle_line):
+def _warm_worker(_):
+    """Imports of an oracle worker (timed outside the sample)."""
+    from oracle import berry  # noqa: F401
+    return 0
+
+
+def cpu_baseline(sample, workers, fn=_oracle_line, warm_with_sample=True):
     ctx = mp.get_context("spawn")
     old = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     try:
         with ctx.Pool(workers) as pool:
-            pool.map(fn, sample[:workers])  # warm the workers (imports)
+            if warm_with_sample:
+                pool.map(fn, sample[:workers])  # warm the workers (imports, first calls)
+            else:
+                pool.map(_warm_worker, range(workers))
             t0 = time.perf_counter()
             res = pool.map(fn, sample)
             dt = time.perf_counter() - t0
@@ -199,9 +215,13 @@ def traffic_from_profile(path, source, precision):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["spin_wilson", "spin_flux", "bbh_disorder", "choti_nested"],
-                    default="spin_wilson",
-                    help="spin_wilson: spin-resolved Wilson loops (the headline metric); spin_flux: spin-resolved "
+    ap.add_argument("--workload", choices=["served", "uneven", "spin_wilson", "spin_flux", "bbh_disorder",
+                                           "choti_nested"],
+                    default="served",
+                    help="served: Poisson stream of Wilson-loop requests of mixed supercell sizes (BHZ L = 8..24 and "
+                         "a 96-orbital model, 32x32 k-grids; the metric's own workload, with p50/p99 latency); "
+                         "uneven: 64 vacancy supercells of five sizes, mixed and FP64 paths; "
+                         "spin_wilson: spin-resolved Wilson loops of 64 disordered BHZ 10x10 supercells; spin_flux: spin-resolved "
                          "Berry flux per plaquette (coupling-matrix method) on the same systems and grid; "
                          "bbh_disorder: the disordered quadrupolar-insulator study (spinful BBH, 21x21 supercell, "
                          "20x20 plaquettes, W = 1 and 9); choti_nested: nested Wilson loop of the chiral HOTI on "
@@ -211,24 +231,34 @@ def main():
     ap.add_argument("--chunk-systems", type=int, default=8)
     ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample size (transverse lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+    ap.add_argument("--precision", choices=["fp64", "mixed", "refined"], default=None,
                     help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere; "
-                         "its phases are checked against the FP64 oracle at 1e-6 rad). Default: mixed, except "
-                         "fp64 for bbh_disorder (N = 1764, m = 882: the c64 Hamiltonian alone puts the summed "
-                         "phases of 882 bands near 1e-6 rad)")
+                         "refined: the mixed path for all bands, then an FP64 correction of the occupied "
+                         "subspace; phases are checked against the FP64 oracle at 1e-6 rad). Default: mixed, "
+                         "except refined for bbh_disorder (N = 1764, m = 882: the c64 Hamiltonian alone puts the "
+                         "summed phases of 882 bands near 1e-6 rad on the mixed path)")
     ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
     ap.add_argument("--tune", action="append", default=[], metavar="KNOB=VALUE",
                     help="set a library tuning knob (be_tune_set) before timing")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device copy of this size (calibrates rocprof byte counters)")
+    ap.add_argument("--requests", type=int, default=30, help="served: requests in the stream")
+    ap.add_argument("--load", type=float, default=1.0,
+                    help="served: arrival rate as a multiple of the one-request-at-a-time capacity")
+    ap.add_argument("--lanes", type=int, default=2, help="served: GPU lanes (host threads with a stream each)")
+    ap.add_argument("--hbm-gib", type=int, default=150, help="served: HBM budget of admitted requests (GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: berryhip has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.precision is None:
-        args.precision = "fp64" if args.workload == "bbh_disorder" else "mixed"
+        args.precision = "refined" if args.workload == "bbh_disorder" else "mixed"
     if args.workload in ("bbh_disorder", "choti_nested"):
         return main_study(args)
+    if args.workload == "served":
+        return main_served(args)
+    if args.workload == "uneven":
+        return main_uneven(args)
 
     hls, tags = systems()
     if args.systems:
@@ -292,9 +322,11 @@ def main():
     spin = torch.from_numpy(np.stack([syn.bhz_spin_diag(h) for h in hls])).to(dev)
     cs = args.chunk_systems
     nmat = cs * n_k
-    mixed = args.precision == "mixed"
-    hdt, hcode = (torch.complex64, L.BE_C64) if mixed else (torch.complex128, L.BE_C128)
-    prec = L.BE_MIXED_FP32 if mixed else L.BE_FP64
+    # mixed: FP32 reduction and back-transformation; refined: the same for all
+    # bands of an FP32 copy of the FP64 H, then the FP64 subspace correction
+    mixed = args.precision in ("mixed", "refined")
+    hdt, hcode = (torch.complex64, L.BE_C64) if args.precision == "mixed" else (torch.complex128, L.BE_C128)
+    prec = {"fp64": L.BE_FP64, "mixed": L.BE_MIXED_FP32, "refined": L.BE_MIXED_FP32_REFINED}[args.precision]
     H = torch.empty((nmat, N, N), dtype=hdt, device=dev)
     U = torch.empty((nmat, m, N), dtype=torch.complex128, device=dev)
     ev = torch.empty((nmat, m + 2), dtype=torch.float64, device=dev)
@@ -383,8 +415,9 @@ def main():
         elem = 8 if mixed else 16
         byts = hetrd_panel_bytes(N, total_k, elem) * steps
         ach = byts / (ms_tot * 1e-3) / 1e9
-        traffic = traffic_from_profile(os.path.join(ROOT, "profiles", f"hetrd_panel_bhz400_{args.precision}.md"),
-                                       os.path.join(ROOT, "paper_2312_13051_amd", "csrc", "eigh.hip"), args.precision)
+        pp = "mixed" if mixed else "fp64"  # the refined path runs the mixed path's panel kernel
+        traffic = traffic_from_profile(os.path.join(ROOT, "profiles", f"hetrd_panel_bhz400_{pp}.md"),
+                                       os.path.join(ROOT, "paper_2312_13051_amd", "csrc", "eigh.hip"), pp)
         roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": round(byts / launches, 1)})
@@ -469,8 +502,7 @@ def main():
                                "realizations, 24x24 supercell k-grid, half filling, " +
                                ("spin-resolved Berry flux per plaquette (coupling-matrix method, eig of P S_z P, "
                                 "link determinants in both directions), " if flux_wl else
-                                "spin-resolved Wilson loop (eig of P S_z P), ") + ("mixed path: FP32 Householder reduction and "
-                               "back-transformation on MFMA, FP64 elsewhere" if mixed else "FP64 path"),
+                                "spin-resolved Wilson loop (eig of P S_z P), ") + PRECISION_TEXT[args.precision],
                    "systems": n_sys, "k_points": total_k, "N": N, "m": m, "chunk_systems": cs, "tuning": tuning},
         "roofline": roof,
         "gemm_phases": gemm_phases,
@@ -544,8 +576,8 @@ def main_study(args):
         sys.exit(1)
     dev = torch.device("cuda", 0)
     ctx = L.Context(0)
-    mixed = args.precision == "mixed"
-    prec = L.BE_MIXED_FP32 if mixed else L.BE_FP64
+    mixed = args.precision in ("mixed", "refined")
+    prec = {"fp64": L.BE_FP64, "mixed": L.BE_MIXED_FP32, "refined": L.BE_MIXED_FP32_REFINED}[args.precision]
     if bbh:
         hls = [syn.spinful_bbh_disordered(BBH_L, W, [7, w]) for w, W in enumerate(BBH_W)]
         plan = ctx.hk_plan(hls)
@@ -629,7 +661,8 @@ def main_study(args):
                  "status": {f"W={W}": int(res[w][1]["status"][0]) for w, W in enumerate(BBH_W)}}
         metric, cfg = METRIC_FLUX, {"workload": "spinful BBH (eq. 10) 21x21 supercell (N=1764, m=882) with chiral "
                                                 "disorder w s0(x)t3, W in {1, 9}, one realization each, 20x20 "
-                                                "plaquettes, spin-resolved Berry flux (s = s0(x)t3)",
+                                                "plaquettes, spin-resolved Berry flux (s = s0(x)t3), " +
+                                                PRECISION_TEXT[args.precision],
                                     "systems": len(BBH_W), "k_points": total_k, "N": N, "m": m}
     else:
         p = res[0][1]["p"].cpu().numpy()
@@ -658,6 +691,342 @@ def main_study(args):
 
 def circ_dist(a, b):
     return np.abs(np.mod(np.asarray(a) - np.asarray(b) + np.pi, 2 * np.pi) - np.pi)
+
+# ---------------------------------------------------------------- served stream (the metric's own workload)
+SERVED_GRID = 32
+
+
+def _served_request_model(kind, req):
+    return syn.served_model(kind, req)
+
+
+def _oracle_served_segment(args):
+    """FP64 oracle on a segment of one transverse line of a served request:
+    eigenvectors at n_pts consecutive k-points, the overlaps between them
+    (polar), and, for a whole line, the Wilson phases. Returns (kind, req,
+    n_pts, seconds, phases or None)."""
+    kind, req, i, n_pts = args
+    t0 = time.perf_counter()
+    from oracle import berry as orc
+    hl = _served_request_model(kind, req)
+    kg = syn.kplane(SERVED_GRID, SERVED_GRID)[i]
+    m = hl.N // 2
+    ev, U, st = orc.eigh_grid(hl, kg[:n_pts], 0, m)
+    th = None
+    if n_pts == SERVED_GRID:
+        W, _ = orc.wilson_matrix(U)
+        th = orc.eigphases(W)
+    else:
+        for j in range(n_pts - 1):
+            orc.polar_factor(U[j + 1].conj().T @ U[j])
+    return (kind, req, n_pts, time.perf_counter() - t0, th)
+
+
+def main_served(args):
+    """Served stream: Poisson arrivals of Wilson-loop requests (BHZ supercells
+    L in {8, 12, 16, 24} with W ~ U[0, 4], and the 96-orbital model), 32 x 32
+    k-grids, continuous batching with HBM admission on two GPU lanes."""
+    from collections import Counter
+    n_req = args.requests
+    kinds = syn.served_types(n_req, [5, 0])
+    first = {}
+    for q, k in enumerate(kinds):
+        first.setdefault(k, q)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    # ---- CPU oracle on a bounded sample (before the GPU is touched): whole
+    # lines of the two smallest types (their phases also gate the GPU
+    # results), line segments of bhz12 and bhz16; bhz24 is extrapolated from
+    # bhz16 by the N^3 cost of dense diagonalization
+    seg = {"w96": SERVED_GRID, "bhz8": SERVED_GRID, "bhz12": 6, "bhz16": 2}
+    sample = [(k, first[k], 0, seg[k]) for k in seg if k in first]
+    cpu, oracle_lines = None, {}
+    if not args.no_cpu_baseline:
+        res, cdt = cpu_baseline(sample, min(workers, len(sample)), _oracle_served_segment, warm_with_sample=False)
+        per_k = {}
+        for kind, req, n_pts, secs, th in res:
+            a = per_k.setdefault(kind, [0.0, 0])
+            a[0] += secs
+            a[1] += n_pts
+            if th is not None:
+                oracle_lines[kind] = th
+        # single-core seconds per k-point of each type, and the mix's rate on
+        # the pool (the stream's k-points over the pool's total core time)
+        sec_k = {k: v[0] / v[1] for k, v in per_k.items()}
+        if "bhz16" in sec_k:
+            sec_k["bhz24"] = sec_k["bhz16"] * (2304 / 1024) ** 3
+        cnt = Counter(kinds)
+        core_s = sum(cnt[k] * SERVED_GRID * SERVED_GRID * sec_k[k] for k in cnt if k in sec_k)
+        rate = sum(cnt[k] for k in cnt if k in sec_k) * SERVED_GRID * SERVED_GRID / core_s * workers
+        cpu = {"value": rate, "unit": "k-point solves/s", "cores": workers, "kind": "oracle",
+               "sample": "whole lines (32 k-points: eigenvectors, polar overlaps, Wilson phases) of one w96 and one "
+                         "bhz8 request, line segments of 6 (bhz12) and 2 (bhz16) k-points; bhz24 extrapolated from "
+                         "bhz16 by (2304/1024)^3; single-core seconds per k-point of each type "
+                         f"({', '.join(f'{k}: {v:.3g}' for k, v in sorted(sec_k.items()))}) weighted by the "
+                         f"stream's mix and scaled to {workers} worker processes (OMP_NUM_THREADS=1); pool wall "
+                         f"{cdt:.1f} s",
+               "cpu_model": _cpu_model(), "numpy": np.__version__}
+
+    import torch
+    from paper_2312_13051_amd import _lib as L
+    from paper_2312_13051_amd import serve as S
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    mixed = args.precision in ("mixed", "refined")
+    kg = syn.kplane(SERVED_GRID, SERVED_GRID)
+
+    def make(q):
+        hl = _served_request_model(kinds[q], q)
+        # mixed: the per-type choice (refined where the mixed path misses the gate)
+        prec = {"mixed": S.served_precision(kinds[q]), "refined": L.BE_MIXED_FP32_REFINED,
+                "fp64": L.BE_FP64}[args.precision]
+        return S.Request(hoplist=hl, kappa=kg, lo=0, hi=hl.N // 2, kind=S.KIND_WILSON, precision=prec, tag=kinds[q])
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    ex = S.GpuExecutor(n_lanes=args.lanes)
+    budget = int(args.hbm_gib) << 30
+
+    def progress(ev):
+        if ev["kind"] == "eig":
+            note(f"lane {ev['lane']}: eigensolver N={ev['N']} k={ev['k_points']} {ev['t'] - ev['t0']:.2f} s")
+        else:
+            note(f"lane {ev['lane']}: request {ev['request']} ({ev['tag']}) done, latency {ev['latency']:.2f} s")
+    # ---- warm-up and service times: one request of each type alone
+    svc = {}
+    for k in syn.SERVED_TYPES:
+        if k not in first:
+            continue
+        eng = S.Engine(ex, hbm_budget=budget, on_event=progress)
+        r = make(first[k])
+        t0 = time.perf_counter()
+        eng.submit(r)
+        eng.run_until_idle()
+        torch.cuda.synchronize()
+        svc[k] = time.perf_counter() - t0
+        if r.error is not None:
+            raise r.error
+        note(f"warm-up {k}: {svc[k]:.2f} s")
+    cnt = Counter(kinds)
+    mean_svc = sum(cnt[k] * svc[k] for k in cnt) / n_req
+    capacity = 1.0 / mean_svc   # requests/s with one request in flight at a time
+    rate = args.load * capacity
+    # ---- the stream
+    reqs = [make(q) for q in range(n_req)]
+    arrivals = S.poisson_arrivals(rate, n_req, [5, 0])
+    for lane_ctx, _ in ex.lanes:
+        lane_ctx.profile_enable(True)
+    eng = S.Engine(ex, hbm_budget=budget, on_event=progress)
+    note(f"stream: {n_req} requests at {rate:.3f}/s ({args.load} x the one-at-a-time capacity)")
+    wall = S.drive(eng, reqs, arrivals)
+    torch.cuda.synchronize()
+    prof = {}
+    for lane_ctx, _ in ex.lanes:
+        for name, (ms, n) in lane_ctx.profile().items():
+            a = prof.setdefault(name, [0.0, 0])
+            a[0] += ms
+            a[1] += n
+        lane_ctx.profile_enable(False)
+    errs = [r for r in reqs if r.error is not None]
+    if errs:
+        raise errs[0].error
+    t_first = min(r.t_submit for r in reqs)
+    t_last = max(r.t_done for r in reqs)
+    span = t_last - t_first
+    total_k = sum(r.n_k for r in reqs)
+    value = total_k / span
+    lat = S.latency_stats(reqs)
+    by_type = {k: S.latency_stats([r for r in reqs if r.tag == k]) for k in syn.SERVED_TYPES}
+    note(f"stream done: {total_k} k-points in {span:.2f} s")
+
+    # ---- phase error of sampled lines: oracle lines (small types), the GPU
+    # FP64 path on the same line (large types)
+    from paper_2312_13051_amd import pipeline as PL
+    from tests.phase_metrics import phase_set_error
+    gate = {}
+    for k in syn.SERVED_TYPES:
+        if k not in first:
+            continue
+        r = reqs[first[k]]
+        got = r.result["theta"][0, 0, :r.m]
+        if k in oracle_lines:
+            gate[k] = {"vs": "oracle", "err": float(phase_set_error(got, oracle_lines[k]))}
+        else:
+            c0 = ex.lanes[0][0]
+            g = PL.eig_grid(c0, c0.hk_plan([r.hoplist]), 0, 1, kg[:1], 0, r.m, L.BE_FP64)
+            ref = PL.wilson(c0, g)["theta"][0, 0, :r.m].cpu().numpy()
+            gate[k] = {"vs": "gpu_fp64", "err": float(phase_set_error(got, ref))}
+    max_err = max((v["err"] for v in gate.values()), default=None)
+
+    # ---- dominant kernel and its roofline over the stream
+    name, (ms_tot, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+    if name == "hetrd_panel":
+        byts = sum(hetrd_panel_bytes(r.N, r.n_k, 8 if mixed else 16) for r in reqs)
+        ach = byts / (ms_tot * 1e-3) / 1e9
+        roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": round(byts / launches, 1),
+                     "note": "durations of launches that may overlap with the other lane's work"})
+    kernels = {k: {"ms": round(v[0], 1), "launches": v[1]} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "k-point solves/s", "n_gpus": 1,
+        "steps": n_req, "warmup": len(svc), "ms_per_step": round(span / n_req * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": "served stream (Poisson arrivals) of Wilson-loop requests: BHZ supercells L in "
+                               "{8, 12, 16, 24} (N = 256, 576, 1024, 2304) with Anderson disorder W ~ U[0, 4] and "
+                               "a 96-orbital Wannier-like model (|R| <= 3, exp(-|R|/1.5) Gaussian hoppings), "
+                               "equally mixed, 32x32 k-grid each, half filling, Wilson loop on all occupied bands, "
+                               "HBM-admitted continuous batching on two GPU lanes, " +
+                               (PRECISION_TEXT["mixed"] + " (refined mixed path for the 96-orbital model)"
+                                if args.precision == "mixed" else PRECISION_TEXT[args.precision]),
+                   "requests": n_req, "k_points": total_k, "types": dict(Counter(kinds)),
+                   "arrival_rate_per_s": round(rate, 4), "load": args.load, "lanes": args.lanes,
+                   "hbm_budget_gib": args.hbm_gib},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": round(lat["p50_ms"], 1), "p99": round(lat["p99_ms"], 1), "unit": "per request",
+                       "by_type": {k: {"p50": round(v["p50_ms"], 1), "p99": round(v["p99_ms"], 1), "n": v["n"]}
+                                   for k, v in by_type.items() if v["n"]}},
+        "service_s_alone": {k: round(v, 3) for k, v in svc.items()},
+        "peak_admitted_gib": round(eng.peak_used / 2 ** 30, 1),
+        "phase_err_vs_fp64_rad": gate, "phase_gate_1e-6_ok": None if max_err is None else bool(max_err <= 1e-6),
+        "valid_requests": int(sum(1 for r in reqs if int(np.asarray(r.result["status"]).max()) == 0
+                                  and not r.result["eig_status"])),
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# ---------------------------------------------------------------- uneven batch
+UNEVEN_GRID = 16
+
+
+def _oracle_uneven_line(args):
+    """FP64 oracle Wilson phases of one transverse line of system s of the uneven batch."""
+    s, i = args
+    from oracle import berry as orc
+    hl = syn.uneven_systems()[s]
+    kg = syn.kplane(UNEVEN_GRID, UNEVEN_GRID)[i]
+    ev, U, st = orc.eigh_grid(hl, kg, 0, hl.N // 2)
+    W, _ = orc.wilson_matrix(U)
+    return (s, i, orc.eigphases(W))
+
+
+def main_uneven(args):
+    """Uneven batch: 64 BHZ supercells L in {6, 8, 12, 16, 20} with 2 %
+    vacancies (N = 140 ... 1568), 16 x 16 k-grids, Wilson loop on all occupied
+    bands; the mixed path and the FP64 path on the same batch."""
+    from collections import defaultdict
+    hls = syn.uneven_systems()
+    groups = defaultdict(list)
+    for s, h in enumerate(hls):
+        groups[h.N].append(s)
+    sizes = sorted(groups)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    # oracle: two lines of the first system of each of the three smallest sizes
+    sample = [(groups[N][0], i) for N in sizes[:3] for i in (0, 7)]
+    cpu, oracle_res = None, []
+    if not args.no_cpu_baseline:
+        oracle_res, cdt = cpu_baseline(sample, min(workers, len(sample)), _oracle_uneven_line, warm_with_sample=False)
+        cpu = {"value": len(sample) * UNEVEN_GRID / cdt, "unit": "k-point solves/s", "cores": min(workers, len(sample)),
+               "kind": "oracle", "sample": f"{len(sample)} transverse lines ({len(sample) * UNEVEN_GRID} k-points) of "
+                                           f"the three smallest sizes (N = {sizes[:3]}), NumPy/LAPACK FP64, one worker "
+                                           f"process per line, OMP_NUM_THREADS=1, wall {cdt:.2f} s",
+               "cpu_model": _cpu_model(), "numpy": np.__version__}
+
+    import torch
+    from paper_2312_13051_amd import _lib as L
+    from paper_2312_13051_amd import pipeline as PL
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    ctx = L.Context(0)
+    kg = syn.kplane(UNEVEN_GRID, UNEVEN_GRID)
+    n_k = UNEVEN_GRID * UNEVEN_GRID
+    plans = {N: ctx.hk_plan([hls[s] for s in groups[N]]) for N in sizes}
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    def step(prec):
+        out = {}
+        hb = 8 if prec == L.BE_MIXED_FP32 else 16
+        for N in sizes:
+            ns = len(groups[N])
+            chunk = max(n_k, min(ns * n_k, (16 << 30) // (N * N * hb) // n_k * n_k))
+            g = PL.eig_grid(ctx, plans[N], 0, ns, kg, 0, N // 2, prec, chunk=chunk)
+            out[N] = (None, PL.wilson(ctx, g))
+            del g  # the eigenvectors of one size at a time (the N = 1568 group alone holds 65 GB)
+        return out
+
+    res, timing, profs = {}, {}, {}
+    for pname, prec in (("mixed", L.BE_MIXED_FP32), ("fp64", L.BE_FP64)):
+        for _ in range(args.warmup):
+            step(prec)
+            torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            res[pname] = step(prec)
+        torch.cuda.synchronize()
+        timing[pname] = (time.perf_counter() - t0) / args.steps
+        profs[pname] = ctx.profile()
+        ctx.profile_enable(False)
+        note(f"{pname}: {timing[pname]:.2f} s per step")
+    total_k = len(hls) * n_k
+    # gate: mixed against FP64 on every line; FP64 against the oracle's lines
+    from tests.phase_metrics import phase_set_error
+    err_mixed = 0.0
+    for N in sizes:
+        a = res["mixed"][N][1]["theta"].cpu().numpy()
+        b = res["fp64"][N][1]["theta"].cpu().numpy()
+        for s in range(a.shape[0]):
+            for i in range(a.shape[1]):
+                err_mixed = max(err_mixed, phase_set_error(a[s, i], b[s, i]))
+    err_fp64 = 0.0
+    for (s, i, th) in oracle_res:
+        N = hls[s].N
+        loc = groups[N].index(s)
+        err_fp64 = max(err_fp64, phase_set_error(res["fp64"][N][1]["theta"][loc, i].cpu().numpy(), th))
+    prof = profs["mixed"]
+    name, (ms_tot, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    roof = {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": round(ms_tot / launches, 4), "launches": launches}
+    if name == "hetrd_panel":
+        byts = sum(hetrd_panel_bytes(N, len(groups[N]) * n_k, 8) for N in sizes) * args.steps
+        ach = byts / (ms_tot * 1e-3) / 1e9
+        roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": round(byts / launches, 1)})
+    st = np.concatenate([res["mixed"][N][1]["status"].cpu().numpy() for N in sizes])
+    out = {
+        "metric": METRIC, "value": round(total_k / timing["mixed"], 1), "unit": "k-point solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(timing["mixed"] * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "uneven batch: 64 BHZ L x L supercells, L drawn from {6, 8, 12, 16, 20}, 2 % vacancies "
+                               "(N = 140, 252, 564, 1004, 1568), 16x16 k-grids, half filling, Wilson loop on all "
+                               "occupied bands; mixed path (FP32 reduction and back-transformation) and FP64 path",
+                   "systems": len(hls), "sizes": {str(N): len(groups[N]) for N in sizes}, "k_points": total_k},
+        "fp64_value": round(total_k / timing["fp64"], 1), "mixed_over_fp64": round(timing["fp64"] / timing["mixed"], 3),
+        "roofline": roof, "cpu_baseline": cpu,
+        "phase_err_mixed_vs_fp64_rad": err_mixed, "phase_err_fp64_vs_oracle_rad": err_fp64 if oracle_res else None,
+        "phase_gate_1e-6_ok": bool(err_mixed <= 1e-6),
+        "valid_systems": int((st == 0).sum()),
+        "kernels_mixed": {k: {"ms_per_step": round(v[0] / args.steps, 2), "launches_per_step": v[1] // args.steps}
+                          for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
+    }
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -14,8 +14,19 @@
  *   device memory owned by the caller. The library never frees caller memory.
  * - Every call is asynchronous on the given stream unless its comment says
  *   it synchronizes. Outputs are valid once the stream has completed. Calls
- *   that synchronize read convergence data back to the host between
- *   launches; they cannot be captured into a HIP graph.
+ *   that synchronize read convergence counts back to the host between
+ *   launches, only to stop their iterations early.
+ * - HIP graph capture: while the stream is being captured, be_build_hk,
+ *   be_eigh_batched, be_wilson_loop, be_plaquette_flux(_noalloc),
+ *   be_spin_resolved_wilson and be_spin_sectors read nothing back: their
+ *   Newton-Schulz iterations run the whole fixed schedule (8 steps for the
+ *   eigenvectors, 51 for the polar factors) with converged matrices skipped
+ *   on the device, so a replay reproduces the uncaptured results exactly.
+ *   The workspace must not grow under capture (BE_ENOMEM): run the same call
+ *   once outside capture first. be_spin_resolved_wilson and be_spin_sectors
+ *   then take m_dn_h as input (the sector sizes of an earlier uncaptured
+ *   call; at most 256 systems) and flag PSO_GAP where a system's actual size
+ *   differs. be_nested_wilson and be_hk_plan_create cannot be captured.
  * - Return value: BE_OK (0) or a negative error code; be_last_error() gives
  *   text. Argument errors are detected on the host before any launch.
  * - Physics conditions (closed gaps, singular overlaps, ...) are never
@@ -61,6 +72,12 @@ extern "C" {
 #define BE_MIXED_FP32 1 /* FP32 Householder reduction and back-transformation on
                            MFMA with FP32 accumulation; FP64 tridiagonal solve,
                            FP64 re-orthonormalization of the eigenvectors       */
+#define BE_MIXED_FP32_REFINED 2 /* BE_MIXED_FP32 for all N bands of an FP32
+                           copy of H, then an FP64 correction of the selected
+                           bands' subspace from the other bands (first order
+                           in the FP32 error, so that error enters squared),
+                           FP64 Rayleigh-quotient eigenvalues and FP64
+                           orthonormalization; H (BE_C128) is not modified   */
 
 /* ---- overlap mode ---- */
 #define BE_OVL_POLAR 0 /* each overlap replaced by its unitary polar factor */
@@ -139,10 +156,24 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
 /* Rows (a3)-(a5) -- batched Hermitian eigensolver (Sec. I: exact
  * diagonalization at many k-points; the selected bands, eq. 2).
  * n_mat matrices of order N (H + q*mat_stride, leading dimension ld, BE_C128
- * for BE_FP64 or BE_C64 for BE_MIXED_FP32). Only the lower triangle and the
- * diagonal are read (the diagonal's imaginary parts are taken as zero); the
- * upper triangle is ignored. H is overwritten (its columns hold the
- * Householder vectors afterwards; the upper triangle is left undefined).
+ * for BE_FP64 and BE_MIXED_FP32_REFINED, BE_C64 for BE_MIXED_FP32). Only the
+ * lower triangle and the diagonal are read (the diagonal's imaginary parts
+ * are taken as zero); the upper triangle is ignored. H is overwritten (its
+ * columns hold the Householder vectors afterwards; the upper triangle is left
+ * undefined), except with BE_MIXED_FP32_REFINED, which works on copies.
+ * BE_MIXED_FP32_REFINED: the mixed path for all N bands of an FP32 copy of
+ * H; then, with H in FP64, for each selected band j and each other band i,
+ * s_ij = v_i^H H u_j and p_ij = v_i^H u_j (FP64 MFMA GEMMs) give the error of
+ * u_j along v_i, (s_ij - lambda_j p_ij) / (lambda_i - lambda_j), which is
+ * removed (U += V F); U is then orthonormalized by Newton-Schulz in FP64 and
+ * the eigenvalues are the Rayleigh quotients u_j^H H u_j / u_j^H u_j of the
+ * uncorrected vectors. The FP32 error of the subspace enters squared: the
+ * projector U U^H agrees with the FP64 path's to about 1e-12 where the
+ * window is separated from the other bands by a gap well above 1e-6 ||H||;
+ * single columns inside the window are eigenvectors to the FP32 path's
+ * accuracy only, and the eigenvalues are within about 1e-9 ||H||
+ * (eigenvalues lo-1 and hi: the FP32 path's). Workspace per matrix: about
+ * 40 N^2 + 32 N m + 32 (N - m) m bytes besides the mixed path's for m = N.
  * Steps: blocked Householder reduction to real tridiagonal form (panel
  * kernel whose matrix-vector products read the lower triangle once per
  * column + MFMA rank-2k trailing updates of the lower triangle), FP64 bisection for eigenvalues
@@ -217,7 +248,9 @@ int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t l
  *   (PSO_GAP if min |mu| < 1e-6 or the count of mu < 0 varies).
  * precision selects the eigensolver of A: BE_FP64, or BE_MIXED_FP32 (A
  * rounded to c64, FP32 reduction and back-transformation, FP64 tridiagonal
- * solve and orthonormalization); A, U and everything after are FP64.
+ * solve and orthonormalization); BE_MIXED_FP32_REFINED (for U from the
+ * refined eigensolver) takes the FP64 solver; A, U and everything after are
+ * FP64.
  * Synchronizes the stream: the sector sizes are read back, and the
  * eigensolver and the polar steps read back their convergence. */
 int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libberryhip.so")
 
 BE_OK, BE_EINVAL, BE_ENOMEM, BE_EHIP, BE_ENOTIMPL = 0, -1, -2, -3, -4
 BE_C128, BE_C64 = 0, 1
-BE_FP64, BE_MIXED_FP32 = 0, 1
+BE_FP64, BE_MIXED_FP32, BE_MIXED_FP32_REFINED = 0, 1, 2
 BE_OVL_POLAR, BE_OVL_RAW = 0, 1
 ST_GAP_CLOSED, ST_OVERLAP_SINGULAR, ST_WINDING_UNRESOLVED = 1, 2, 4
 ST_PSO_GAP, ST_WANNIER_GAP, ST_NONCONVERGED, ST_NAN_INF = 8, 16, 32, 64
@@ -184,8 +184,10 @@ class Context:
         return [int(x) for x in s_out]
 
     def spin_resolved_wilson(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, spin_diag, pso_evals,
-                             theta_dn, theta_up, C_dn, C_up, C_s, status, precision=BE_FP64):
-        m_dn = (C.c_int32 * n_sys)()
+                             theta_dn, theta_up, C_dn, C_up, C_s, status, precision=BE_FP64, m_dn_in=None):
+        """m_dn_in: sector sizes to pass in (required while the stream is
+        being captured into a graph)."""
+        m_dn = (C.c_int32 * n_sys)(*(m_dn_in or []))
         self._check(self.lib.be_spin_resolved_wilson(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
                                                      mode, precision, _ptr(spin_diag), _ptr(pso_evals), _ptr(theta_dn),
                                                      _ptr(theta_up), _ptr(C_dn), _ptr(C_up), _ptr(C_s), m_dn,

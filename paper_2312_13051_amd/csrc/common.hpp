@@ -116,6 +116,18 @@ void prof_resolve_all(be_ctx *ctx);
 // Kernel launch error check (after hipLaunchKernelGGL).
 int check_launch(be_ctx *ctx, const char *what);
 
+// True while `stream` is being captured into a HIP graph: calls then take no
+// host read-back (fixed iteration schedules with per-item predicates) and
+// may not grow the workspace.
+inline bool stream_capturing(hipStream_t stream) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st == hipStreamCaptureStatusActive;
+}
+
 // Number of workgroups for an XCD-aware 1D grid over `work` items: rounded
 // up to a multiple of 8 so that item w maps to XCD w / per_xcd.
 inline uint32_t xcd_grid(int64_t work) {
@@ -198,6 +210,8 @@ struct ZGemm {
   // read), unless herm_mirror is false (callers that read the lower triangle only)
   bool herm = false;
   bool herm_mirror = true;
+  // optional per-item predicate: items with act[q] == 0 are skipped (C left as it is)
+  const int *act = nullptr;
   // optional real row scaling of B (opB = 'N' only): op(B_q) = diag(s_q) B_q
   // with s_q = scaleB + (q / scaleB_div) * scaleB_ld, applied as B is loaded
   const double *scaleB = nullptr;
@@ -226,6 +240,7 @@ struct CGemm {
   const char *tag = "cgemm";
   bool herm = false;  // as in ZGemm
   bool herm_mirror = true;
+  const int *act = nullptr;  // as in ZGemm
 };
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
 
@@ -247,6 +262,7 @@ struct DGemm {
   int64_t batch = 0;
   const char *tag = "dgemm";
   bool sym = false;  // C (square) is symmetric: as ZGemm::herm, without conjugation
+  const int *act = nullptr;  // as in ZGemm
 };
 int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream);
 

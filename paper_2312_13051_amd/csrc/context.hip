@@ -13,6 +13,10 @@ int set_err(be_ctx *ctx, int code, const std::string &msg) {
 int Carve::commit(be_ctx *ctx, hipStream_t stream, int slot) {
   size_t need = std::max<size_t>(total_, 256);
   if (need > ctx->ws_bytes[slot]) {
+    if (stream_capturing(stream))
+      return set_err(ctx, BE_ENOMEM, "workspace of " + std::to_string(ctx->ws_bytes[slot]) + " bytes too small for a "
+                                     "call under graph capture (" + std::to_string(need) + " needed): run the same "
+                                     "call once outside capture first (it sizes the workspace)");
     // Growing: wait for work that may still use the old buffer.
     BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
     BE_HIP_TRY(ctx, hipDeviceSynchronize());

@@ -720,12 +720,15 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
     // recomputed by the same operations in the back substitution.
     // The loads of each sweep are issued PF rows ahead of the recurrence that
     // consumes them, so the serial chain waits on memory once per PF rows.
+    // The start vector depends on the column only, not on the matrix's place
+    // in the batch: a matrix gets the same eigenvectors, bit for bit, in any
+    // batch (inside a degenerate cluster the start decides the basis).
     constexpr int PF = 4;
     double scale = 1.0;
     for (int it = 0; it < 2; ++it) {
       // forward elimination with partial pivoting on [T_block - lm I | rhs]
       double a = sd[bs] - lm, b = bt - bs > 1 ? se[bs] : 0.0;
-      double r = it == 0 ? hash_unit(uint64_t(q) * 1315423911ull + c, bs) : X[int64_t(bs) * mp + c] * scale;
+      double r = it == 0 ? hash_unit(uint64_t(c) + 1, bs) : X[int64_t(bs) * mp + c] * scale;
       // one elimination step at row i (i + 1 < bt) with right-hand side entry rn of row i + 1
       auto step = [&](int i, double rn) {
         const double ei = se[i], Dn = sd[i + 1] - lm, en = (i + 2 < bt) ? se[i + 1] : 0.0;
@@ -744,7 +747,7 @@ __global__ __launch_bounds__(PT) void tri_invit(const double *d, const double *e
         r = q1 - l * q2;
       };
       if (it == 0) {
-        for (int i = bs; i + 1 < bt; ++i) step(i, hash_unit(uint64_t(q) * 1315423911ull + c, i + 1));
+        for (int i = bs; i + 1 < bt; ++i) step(i, hash_unit(uint64_t(c) + 1, i + 1));
       } else {
         for (int i0 = bs; i0 + 1 < bt; i0 += PF) {
           double rv[PF];
@@ -1102,12 +1105,15 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
   }
 }
 
-// One Newton-Schulz step of the symmetric orthonormalization of X (m x N):
-// G = X X^T is replaced by (3 I - G) / 2; err[q] = max |G - I| (before the
-// update) and, atomically, the maximum over matrices into *gmax (the bit
-// pattern of a non-negative double orders like an integer).
-__global__ __launch_bounds__(PT) void ns_prep_real(double *G, int m, double *err, unsigned long long *gmax) {
+// One Newton-Schulz step of the symmetric orthonormalization of X (m x N),
+// with a state per matrix (act): 1 iterating, 2 taking its last step, 0 done.
+// G = X X^T is replaced by (3 I - G) / 2 and err[q] = max |G - I| (before the
+// update); the next state is 0 (done, no step) once err <= tol, 2 once err <
+// 1e-8 (the step leaves about (3/4) err^2 < 1e-16), else 1. Matrices in state
+// 0 are skipped here and by the two GEMMs of the step.
+__global__ __launch_bounds__(PT) void ns_prep_real(double *G, int m, double *err, int *act, double tol) {
   const int64_t q = blockIdx.x;
+  if (act[q] == 0) return;
   double *Gq = G + q * int64_t(m) * m;
   double e = 0.0;
   for (int k = threadIdx.x; k < m * m; k += PT) {
@@ -1125,9 +1131,38 @@ __global__ __launch_bounds__(PT) void ns_prep_real(double *G, int m, double *err
     for (int w = 1; w < PT / 64; ++w) t = fmax(t, red[w]);
     if (!(t == t)) t = INFINITY;
     err[q] = t;
-    atomicMax(gmax, (unsigned long long)__double_as_longlong(t));
+    act[q] = t <= tol ? 0 : t < 1e-8 ? 2 : 1;
   }
 }
+
+// After the step into buffer `parity`: matrices that took it have their
+// iterate there; those in their last step are done (error taken as zero).
+// *n_left (zeroed before) counts the matrices still iterating.
+__global__ void ns_post_real(int *act, unsigned char *loc, double *err, int64_t n, unsigned char parity, int *n_left) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int left = 0;
+  if (q < n && act[q] != 0) {
+    loc[q] = parity;
+    if (act[q] == 2) {
+      act[q] = 0;
+      err[q] = 0.0;
+    } else {
+      left = 1;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) left += __shfl_xor(left, o, 64);
+  if ((threadIdx.x & 63) == 0 && left) atomicAdd(n_left, left);
+}
+
+__global__ void ns_init_real(int *act, unsigned char *loc, int64_t n) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < n) {
+    act[q] = 1;
+    loc[q] = 0;
+  }
+}
+
+__global__ void zero_i32(int *p) { *p = 0; }
 
 // status[q] |= NONCONVERGED where the last orthonormality error stayed above tol
 __global__ void flag_nonorth(const double *err, int64_t n, double tol, uint32_t *status) {
@@ -1139,14 +1174,14 @@ __global__ void flag_nonorth(const double *err, int64_t n, double tol, uint32_t 
 // mp), by 64 x 64 tiles staged in LDS: rows of X are read along c and columns
 // of U written along r, both coalesced. Grid: (tiles of N x m, matrices).
 template <typename C>
-__global__ __launch_bounds__(256) void z_to_u(const double *X, int64_t sX, int mp, int N, int m, C *U, int ldu,
-                                              int64_t sU) {
+__global__ __launch_bounds__(256) void z_to_u(const double *X0, const double *X1, const unsigned char *loc, int64_t sX,
+                                              int mp, int N, int m, C *U, int ldu, int64_t sU) {
   __shared__ double s[64 * 65];
   const int64_t q = blockIdx.y;
   const int ntr = (N + 63) / 64;
   const int r0 = int(blockIdx.x % ntr) * 64, c0 = int(blockIdx.x / ntr) * 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double *Xq = X + q * sX;
+  const double *Xq = (loc[q] ? X1 : X0) + q * sX;  // the buffer holding matrix q's latest iterate
   for (int rr = w; rr < 64; rr += 4) {
     const int r = r0 + rr, c = c0 + lane;
     s[rr * 65 + lane] = (r < N && c < m) ? Xq[int64_t(r) * mp + c] : 0.0;
@@ -1167,11 +1202,6 @@ __global__ void widen_u(const float2 *Uw, int64_t sW, int N, int m, double2 *U, 
     float2 v = Uw[q * sW + k];
     U[q * sU + r + int64_t(c) * ldu] = make_double2(double(v.x), double(v.y));
   }
-}
-
-__global__ void zero_d(double *p, int64_t n) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
 }
 
 __global__ void zero_u32(uint32_t *p, int64_t n) {
@@ -1238,6 +1268,178 @@ PanelFn<T> panel_kernel(int nt, bool pl) {
   return nt == 256 ? &hetrd_panel<T, 256, false> : nt == 512 ? &hetrd_panel<T, 512, false> : &hetrd_panel<T, 1024, false>;
 }
 
+
+// ---------------------------------------------------------------- FP64 refinement of the mixed path
+// Full Hermitian FP64 copy of H (upper triangle mirrored from the lower one,
+// diagonal taken real) and its FP32 rounding (the FP32 reduction's input),
+// by 32 x 32 tile pairs staged in LDS: tile (bi, bj), bi >= bj, is read once
+// with coalesced columns and written to (bi, bj) and, conjugate-transposed,
+// to (bj, bi). Matrices q = blockIdx.y, blockIdx.y + gridDim.y, ...
+__global__ __launch_bounds__(256) void split_h(const double2 *H, int64_t ms, int ld, int N, int64_t n_mat, double2 *Hf,
+                                               float2 *Hc) {
+  __shared__ double2 t[32][33];  // t[column][row] of the lower tile
+  const int nt = (N + 31) / 32;
+  int p = blockIdx.x, bj = 0;
+  while (p >= nt - bj) {
+    p -= nt - bj;
+    ++bj;
+  }
+  const int bi = bj + p;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t NN = int64_t(N) * N;
+  for (int64_t q = blockIdx.y; q < n_mat; q += gridDim.y) {
+    const double2 *Hq = H + q * ms;
+    double2 *F = Hf + q * NN;
+    float2 *Cq = Hc + q * NN;
+    __syncthreads();
+    for (int c = ty; c < 32; c += 8) {
+      const int r = bi * 32 + tx, col = bj * 32 + c;
+      t[c][tx] = (r < N && col < N) ? Hq[r + int64_t(col) * ld] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int c = ty; c < 32; c += 8) {
+      const int r = bi * 32 + tx, col = bj * 32 + c;
+      if (r >= N || col >= N) continue;
+      double2 v = (bi != bj || tx >= c) ? t[c][tx] : be::cconj(t[tx][c]);
+      if (r == col) v.y = 0.0;
+      F[r + int64_t(col) * N] = v;
+      Cq[r + int64_t(col) * N] = make_float2(float(v.x), float(v.y));
+    }
+    if (bi != bj) {
+      for (int c = ty; c < 32; c += 8) {
+        const int r = bj * 32 + tx, col = bi * 32 + c;
+        if (r >= N || col >= N) continue;
+        const double2 v = be::cconj(t[tx][c]);
+        F[r + int64_t(col) * N] = v;
+        Cq[r + int64_t(col) * N] = make_float2(float(v.x), float(v.y));
+      }
+    }
+  }
+}
+
+// Window columns lo .. lo+m-1 of the all-band eigenvectors (N x N, ld N)
+// into the right half of GU (N x 2m, ld N) and into the output U.
+__global__ void refine_copy_u(const double2 *Uall, int N, int lo, int m, int64_t n_mat, double2 *GU, double2 *U,
+                              int ldu, int64_t us) {
+  for (int64_t q = blockIdx.y; q < n_mat; q += gridDim.y) {
+    const double2 *Uq = Uall + q * int64_t(N) * N + int64_t(lo) * N;
+    double2 *G = GU + q * int64_t(N) * 2 * m + int64_t(m) * N;
+    double2 *O = U + q * us;
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < int64_t(N) * m;
+         k += int64_t(gridDim.x) * blockDim.x) {
+      const int r = int(k % N), c = int(k / N);
+      const double2 v = Uq[k];
+      G[k] = v;
+      O[r + int64_t(c) * ldu] = v;
+    }
+  }
+}
+
+// First-order correction of the window's invariant subspace from the
+// complement (bands outside [lo, hi)), for approximate eigenvectors that
+// are not exactly orthonormal: with s_ij = v_i^H H u_j and p_ij = v_i^H u_j
+// (both in FP64 from the stored vectors), the error of u_j along v_i is
+// e_ij = (s_ij - lambda_j p_ij) / (lambda_i - lambda_j); the correction
+// coefficient f_ij = -e_ij replaces s_ij in S2. S2: nc x 2m (ld nc), left
+// half S, right half P; complement row i is band i (i < lo) or i + m.
+__global__ void refine_coef(double2 *S2, int nc, int m, int lo, int N, const double *lam_all, int64_t n_mat) {
+  const int64_t per = int64_t(nc) * m;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n_mat * per;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t q = k / per;
+    const int64_t e = k % per;
+    const int i = int(e % nc), j = int(e / nc);
+    const double *lam = lam_all + q * (N + 2) + 1;
+    const double li = lam[i < lo ? i : i + m], lj = lam[lo + j];
+    double2 *Sq = S2 + q * int64_t(nc) * 2 * m;
+    const double2 s = Sq[i + int64_t(j) * nc], pp = Sq[i + int64_t(m + j) * nc];
+    const double d = lj - li;
+    double2 f = make_double2(0.0, 0.0);
+    if (d != 0.0 && d == d) f = make_double2((s.x - lj * pp.x) / d, (s.y - lj * pp.y) / d);
+    Sq[i + int64_t(j) * nc] = f;
+  }
+}
+
+// Refined eigenvalues of the window (Rayleigh quotients u_j^H H u_j / u_j^H u_j
+// of the uncorrected vectors: errors of second order in the vectors' error),
+// the neighbours lo-1 and hi from the FP32 reduction's spectrum, and the gap
+// flag of the window. One workgroup per matrix, a wave per column.
+__global__ __launch_bounds__(PT) void refine_evals(const double2 *GU, int N, int m, int lo, const double *lam_all,
+                                                   double *evals, uint32_t *status) {
+  const int64_t q = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double2 *G = GU + q * int64_t(N) * 2 * m, *Uo = G + int64_t(m) * N;
+  const double *lam = lam_all + q * (N + 2) + 1;
+  double *ev = evals + q * (m + 2);
+  for (int j = wave; j < m; j += PT / 64) {
+    double num = 0.0, den = 0.0;
+    for (int r = lane; r < N; r += 64) {
+      const double2 u = Uo[r + int64_t(j) * N], g = G[r + int64_t(j) * N];
+      num += u.x * g.x + u.y * g.y;
+      den += u.x * u.x + u.y * u.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      num += __shfl_xor(num, o, 64);
+      den += __shfl_xor(den, o, 64);
+    }
+    if (lane == 0) ev[1 + j] = num / den;
+  }
+  if (threadIdx.x == 0) {
+    const int hi = lo + m;
+    ev[0] = lo > 0 ? lam[lo - 1] : NAN;
+    ev[m + 1] = hi < N ? lam[hi] : NAN;
+    const double scale = fmax(1.0, fmax(fabs(lam[0]), fabs(lam[N - 1])));
+    double g = INFINITY;
+    if (lo > 0 && m > 0) g = fmin(g, lam[lo] - lam[lo - 1]);
+    if (hi < N && m > 0) g = fmin(g, lam[hi] - lam[hi - 1]);
+    if (g < 1e-9 * scale) status[q] |= BE_ST_GAP_CLOSED;
+  }
+}
+
+// Newton-Schulz step preparation for complex N x m matrices (as ns_prep_real):
+// err = max |G - I|, G <- (3 I - G) / 2, state 0 (done, err <= tol), 2 (last
+// step, err < last: the step leaves about 3/4 err^2), 1 (iterating).
+__global__ __launch_bounds__(PT) void ns_prep_cplx(double2 *G, int m, double *err, int *act, double tol, double last) {
+  const int64_t q = blockIdx.x;
+  if (act[q] == 0) return;
+  double2 *Gq = G + q * int64_t(m) * m;
+  double e = 0.0;
+  for (int k = threadIdx.x; k < m * m; k += PT) {
+    const int r = k % m, c = k / m;
+    const double2 g = Gq[k];
+    const double dr = g.x - (r == c ? 1.0 : 0.0);
+    e = fmax(e, sqrt(dr * dr + g.y * g.y));
+    Gq[k] = make_double2((r == c ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, 64));
+  __shared__ double red[PT / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < PT / 64; ++w) t = fmax(t, red[w]);
+    if (!(t == t)) t = INFINITY;
+    err[q] = t;
+    act[q] = t <= tol ? 0 : t < last ? 2 : 1;
+  }
+}
+
+// Matrices whose latest Newton-Schulz iterate is in the scratch buffer
+// (loc = 1) copy it back to the output.
+__global__ void refine_copy_back(const double2 *Ub, int64_t sUb, int N, int m, const unsigned char *loc, int64_t n_mat,
+                                 double2 *U, int ldu, int64_t us) {
+  for (int64_t q = blockIdx.y; q < n_mat; q += gridDim.y) {
+    if (loc[q] != 1) continue;
+    const double2 *B = Ub + q * sUb;
+    double2 *O = U + q * us;
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < int64_t(N) * m;
+         k += int64_t(gridDim.x) * blockDim.x) {
+      const int r = int(k % N), c = int(k / N);
+      O[r + int64_t(c) * ldu] = B[k];
+    }
+  }
+}
+
 }  // namespace
 
 namespace be {
@@ -1281,10 +1483,13 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   cv.add(&lamg, size_t(nb_mat) * (m + 1));
   cv.add(&marks, size_t(nb_mat) * std::max(m, 1));
   double *Gm = nullptr, *oerr = nullptr;
-  unsigned long long *gmax = nullptr;
+  int *nact = nullptr, *n_left = nullptr;
+  unsigned char *nloc = nullptr;
   cv.add(&Gm, size_t(nb_mat) * std::max(m, 1) * std::max(m, 1));
   cv.add(&oerr, size_t(nb_mat));
-  cv.add(&gmax, 1);
+  cv.add(&nact, size_t(nb_mat));
+  cv.add(&nloc, size_t(nb_mat));
+  cv.add(&n_left, 1);
   cv.add(&Xb, size_t(nb_mat) * 2 * NB * std::max(m, 1));
   cv.add(&Yb, size_t(nb_mat) * 2 * NB * std::max(m, 1));
   C *Tb = nullptr, *Sw = nullptr, *Ww = nullptr;  // paired back-transformation: T of a pair, V1^H V2, T1 V1^H V2
@@ -1385,18 +1590,24 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   const int ldt = mixed ? N : ldu;
   const int64_t ust = mixed ? int64_t(N) * m : us;
   // ---- symmetric orthonormalization of Z (Newton-Schulz on the Gram matrix),
-  // Z held as X = Z^T (m x N, leading dim mp); iterated until max |X X^T - I|
+  // Z held as X = Z^T (m x N, leading dim mp), each matrix until max |X X^T - I|
   // is below 1e-14 (FP64 path), or 2e-7 on the mixed path, whose FP32
   // back-transformation leaves errors of that order in U = QZ anyway (inverse
   // iteration alone typically gives 1e-8 there: no Newton-Schulz step is
-  // then taken)
+  // then taken). At most 8 steps; outside graph capture the host stops once no
+  // matrix is left (read back after every step), under capture every step is
+  // launched and finished matrices skip it.
   {
     const double tol_orth = mixed ? 2e-7 : 1e-14;
+    const bool capturing = stream_capturing(stream);
     const int64_t sZ = int64_t(4) * N * mp;
-    double *Xa = Zs + int64_t(3) * N * mp, *Xt = Zs;
-    double *hmax = static_cast<double *>(ctx->pinned);
+    double *const X0 = Zs + int64_t(3) * N * mp, *const X1 = Zs;
+    double *Xa = X0, *Xt = X1;
+    unsigned char parity = 0;
+    int *hleft = static_cast<int *>(ctx->pinned);
+    hipLaunchKernelGGL(ns_init_real, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, nact, nloc, nb_mat);
+    BE_RET_IF(check_launch(ctx, "ns_init_real"));
     for (int it = 0; it < 8; ++it) {
-      BE_HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), stream));
       DGemm g;  // G = X X^T
       g.M = m;
       g.N = m;
@@ -1415,13 +1626,10 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.batch = nb_mat;
       g.tag = "reorth";
       g.sym = true;
+      g.act = nact;
       BE_RET_IF(dgemm(ctx, g, stream));
-      hipLaunchKernelGGL(ns_prep_real, dim3(nb_mat), dim3(PT), 0, stream, Gm, m, oerr, gmax);
+      hipLaunchKernelGGL(ns_prep_real, dim3(nb_mat), dim3(PT), 0, stream, Gm, m, oerr, nact, tol_orth);
       BE_RET_IF(check_launch(ctx, "ns_prep_real"));
-      BE_HIP_TRY(ctx, hipMemcpyAsync(hmax, gmax, sizeof(double), hipMemcpyDeviceToHost, stream));
-      BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
-      const double e = *hmax;
-      if (e <= tol_orth) break;
       DGemm h;  // X <- (3 I - G) X / 2
       h.M = m;
       h.N = N;
@@ -1437,19 +1645,25 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       h.bC = ZBatch::strided(sZ);
       h.batch = nb_mat;
       h.tag = "reorth";
+      h.act = nact;
       BE_RET_IF(dgemm(ctx, h, stream));
+      hipLaunchKernelGGL(zero_i32, dim3(1), dim3(1), 0, stream, n_left);
+      hipLaunchKernelGGL(ns_post_real, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, nact, nloc, oerr, nb_mat,
+                         static_cast<unsigned char>(parity ^ 1), n_left);
+      BE_RET_IF(check_launch(ctx, "ns_post_real"));
       std::swap(Xa, Xt);
-      if (e < 1e-8) {  // quadratic convergence: this step brought it below 1e-16
-        hipLaunchKernelGGL(zero_d, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat);
-        BE_RET_IF(check_launch(ctx, "zero_d"));
-        break;
+      parity ^= 1;
+      if (!capturing) {
+        BE_HIP_TRY(ctx, hipMemcpyAsync(hleft, n_left, sizeof(int), hipMemcpyDeviceToHost, stream));
+        BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+        if (*hleft == 0) break;
       }
     }
     hipLaunchKernelGGL(flag_nonorth, dim3((nb_mat + 255) / 256), dim3(256), 0, stream, oerr, nb_mat,
                        std::max(tol_orth, 1e-10), status);
     const int zt = ((N + 63) / 64) * ((m + 63) / 64);
     hipLaunchKernelGGL(z_to_u<C>, dim3(static_cast<uint32_t>(zt), static_cast<uint32_t>(nb_mat)), dim3(256), 0, stream,
-                       Xa, sZ, mp, N, m, Ut, ldt, ust);
+                       X0, X1, nloc, sZ, mp, N, m, Ut, ldt, ust);
     BE_RET_IF(check_launch(ctx, "z_to_u"));
   }
   // ---- back-transformation by pairs of panels (pa, pb = pa + 1), last pair
@@ -1550,53 +1764,248 @@ static int64_t panel_slots(be_ctx *ctx, int N) {
   return int64_t(std::max(per_cu, 1)) * ctx->n_cu;
 }
 
-template <typename T>
-static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo,
-                    int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
-                    hipStream_t stream) {
-  const int m = band_hi - band_lo;
-  // the panel vectors and the tridiagonal solver's arrays live in LDS
-  const size_t lds_need = std::max({panel_lds(N, sizeof(typename CT<T>::c), ctx->tune_panel_threads),
-                                    (4 * size_t(N) + m + 4) * sizeof(double),
+// The panel vectors and the tridiagonal solver's arrays live in LDS.
+static int check_eigh_lds(be_ctx *ctx, int N, int m, size_t cs) {
+  const size_t lds_need = std::max({panel_lds(N, cs, ctx->tune_panel_threads), (4 * size_t(N) + m + 4) * sizeof(double),
                                     (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + 2 * size_t(m)) * sizeof(int),
                                     gs_smem(m)});
   BE_CHECK_ARG(ctx, lds_need <= 160 * 1024, "be_eigh_batched: order too large for the LDS-resident kernels");
-  if (n_mat == 0) return BE_OK;
-  // sub-batches bounded to ~4 GiB of workspace; where that holds fewer than
-  // one device-wide round of resident panel workgroups (large N), up to one
-  // round within 48 GiB (or half the free device memory)
+  return BE_OK;
+}
+
+// Workspace bytes per matrix of eigh_chunk for order N and m bands.
+template <typename T>
+static size_t eigh_chunk_bytes(be_ctx *ctx, int N, int m) {
   const int P = (N + NB - 1) / NB;
   const int mp = std::max(64, (m + 63) / 64 * 64);
   const size_t cs = sizeof(typename CT<T>::c);
-  const size_t per = cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 4 * size_t(NB) * std::max(m, 1) +
-                           6 * size_t(NB) * NB + size_t(N) * std::max(m, 1)) +
-                     (panel_part_lds(N, cs, ctx->tune_panel_threads) ? 0 : panel_part_bytes(N - 1, cs)) +
-                     sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) +
-                                       size_t(m) + 1) +
-                     sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
+  return cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 4 * size_t(NB) * std::max(m, 1) + 6 * size_t(NB) * NB +
+               size_t(N) * std::max(m, 1)) +
+         (panel_part_lds(N, cs, ctx->tune_panel_threads) ? 0 : panel_part_bytes(N - 1, cs)) +
+         sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) + size_t(m) +
+                           1) +
+         sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
+}
+
+// Matrices per sub-batch for `per` workspace bytes per matrix: at most ~4 GiB
+// of workspace; where that holds fewer than one device-wide round of resident
+// panel workgroups (large N), up to one round within 48 GiB (or half the free
+// device memory plus the `reusable` bytes the context already holds). The
+// panel kernel streams at full bandwidth only while the device is full: a
+// sub-batch is a whole number of device-wide rounds of resident workgroups
+// where the cap allows one, and the sub-batches are made equal, so that no
+// short remainder costs a full round per panel (4,608 matrices of order 400
+// with 768 resident: six sub-batches of 768; 9,216: twelve).
+template <typename T>
+static int64_t eigh_sub_batch(be_ctx *ctx, int N, size_t per, size_t reusable, int64_t n_mat) {
   const int64_t slots = panel_slots<T>(ctx, N);
   int64_t cap = std::max<int64_t>(1, int64_t((size_t(4) << 30) / per));
   if (cap < slots) {
     size_t free_b = 0, total_b = 0;
     size_t budget = size_t(48) << 30;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
-      budget = std::min(budget, free_b / 2 + ctx->ws_bytes[WS_EIGH]);  // the slot's current size is reusable
+      budget = std::min(budget, free_b / 2 + reusable);
     else
       (void)hipGetLastError();
     cap = std::max<int64_t>(cap, std::min<int64_t>(slots, int64_t(budget / per)));
   }
-  // The panel kernel streams at full bandwidth only while the device is full:
-  // a sub-batch is a whole number of device-wide rounds of resident
-  // workgroups where the cap allows one, and the sub-batches are made equal,
-  // so that no short remainder costs a full round per panel (4,608 matrices
-  // of order 400 with 768 resident: six sub-batches of 768; 9,216: twelve).
   if (cap >= slots) cap = cap / slots * slots;
   const int64_t n_sub = (n_mat + cap - 1) / cap;
-  cap = (n_mat + n_sub - 1) / n_sub;
+  return (n_mat + n_sub - 1) / n_sub;
+}
+
+template <typename T>
+static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo,
+                    int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
+                    hipStream_t stream) {
+  const int m = band_hi - band_lo;
+  BE_RET_IF(check_eigh_lds(ctx, N, m, sizeof(typename CT<T>::c)));
+  if (n_mat == 0) return BE_OK;
+  const size_t per = eigh_chunk_bytes<T>(ctx, N, m);
+  const int64_t cap = eigh_sub_batch<T>(ctx, N, per, ctx->ws_bytes[WS_EIGH], n_mat);
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
     BE_RET_IF(eigh_chunk<T>(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo, band_hi, evals + b0 * (m + 2),
                             U + b0 * u_stride, ldu, u_stride, status + b0, stream));
+  }
+  return BE_OK;
+}
+
+// Refined mixed precision (BE_MIXED_FP32_REFINED), one sub-batch: the mixed
+// path for all N bands of an FP32 copy of H, then, in FP64 with the FP64 H,
+// one first-order correction of the window's invariant subspace from the
+// complement's vectors V (G = H U_w, [S | P] = V^H [G | U_w], F from S, P and
+// the eigenvalues, U_w += V F), Rayleigh-quotient eigenvalues and a
+// Newton-Schulz orthonormalization of U_w. The error of the FP32 subspace
+// (~1e-6 relative) enters the result squared.
+static int eigh_refined_chunk(be_ctx *ctx, const double2 *H, int N, int ld, int64_t ms, int64_t nb, int lo, int hi,
+                              double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream) {
+  const int m = hi - lo, nc = N - m;
+  const int mm = std::max(m, 1);
+  const int64_t NN = int64_t(N) * N, sGU = int64_t(N) * 2 * mm, sS2 = int64_t(std::max(nc, 1)) * 2 * mm;
+  double2 *Hf = nullptr, *Uall = nullptr, *GU = nullptr, *S2 = nullptr, *Gm = nullptr;
+  float2 *Hc = nullptr;
+  double *lam = nullptr, *err = nullptr;
+  int *act = nullptr, *n_left = nullptr;
+  unsigned char *loc = nullptr;
+  Carve cv;
+  cv.add(&Hf, size_t(nb * NN));
+  cv.add(&Hc, size_t(nb * NN));
+  cv.add(&Uall, size_t(nb * NN));
+  cv.add(&lam, size_t(nb * (N + 2)));
+  cv.add(&GU, size_t(nb * sGU));
+  cv.add(&S2, size_t(nb * sS2));
+  cv.add(&Gm, size_t(nb) * mm * mm);
+  cv.add(&err, size_t(nb));
+  cv.add(&act, size_t(nb));
+  cv.add(&loc, size_t(nb));
+  cv.add(&n_left, 1);
+  BE_RET_IF(cv.commit(ctx, stream, WS_MISC));
+  const uint32_t gy = static_cast<uint32_t>(std::min<int64_t>(nb, 65535));
+  {
+    const int nt = (N + 31) / 32;
+    hipLaunchKernelGGL(split_h, dim3(static_cast<uint32_t>(nt * (nt + 1) / 2), gy), dim3(256), 0, stream, H, ms, ld,
+                       N, nb, Hf, Hc);
+    BE_RET_IF(check_launch(ctx, "split_h"));
+  }
+  // all bands on the mixed path (zeroes status)
+  BE_RET_IF(eigh_chunk<float>(ctx, Hc, N, N, NN, nb, 0, N, lam, Uall, N, NN, status, stream));
+  auto zg = [&](int M_, int N_, int K_, int opA, const double2 *A_, int lda_, int64_t sA_, const double2 *B_, int ldb_,
+                int64_t sB_, double2 *C_, int ldc_, int64_t sC_, double beta, const char *tag) {
+    ZGemm g;
+    g.M = M_;
+    g.N = N_;
+    g.K = K_;
+    g.opA = opA;
+    g.opB = 0;
+    g.A = A_;
+    g.lda = lda_;
+    g.bA = ZBatch::strided(sA_);
+    g.B = B_;
+    g.ldb = ldb_;
+    g.bB = ZBatch::strided(sB_);
+    g.C = C_;
+    g.ldc = ldc_;
+    g.bC = ZBatch::strided(sC_);
+    g.alpha = make_double2(1.0, 0.0);
+    g.beta = make_double2(beta, 0.0);
+    g.batch = nb;
+    g.tag = tag;
+    return zgemm(ctx, g, stream);
+  };
+  if (m > 0) {
+    hipLaunchKernelGGL(refine_copy_u, dim3(64, gy), dim3(256), 0, stream, Uall, N, lo, m, nb, GU, U, ldu, us);
+    BE_RET_IF(check_launch(ctx, "refine_copy_u"));
+    // G = H U_w into the left half of GU
+    BE_RET_IF(zg(N, m, N, 0, Hf, N, NN, Uall + int64_t(lo) * N, N, NN, GU, N, sGU, 0.0, "refine_hu"));
+  }
+  hipLaunchKernelGGL(refine_evals, dim3(static_cast<uint32_t>(nb)), dim3(PT), 0, stream, GU, N, m, lo, lam, evals,
+                     status);
+  BE_RET_IF(check_launch(ctx, "refine_evals"));
+  if (m == 0) return BE_OK;
+  if (nc > 0) {
+    // [S | P] = V^H [G | U_w]: the complement's rows, bands below lo then above hi
+    if (lo > 0) BE_RET_IF(zg(lo, 2 * m, N, 1, Uall, N, NN, GU, N, sGU, S2, nc, sS2, 0.0, "refine_proj"));
+    if (hi < N)
+      BE_RET_IF(zg(N - hi, 2 * m, N, 1, Uall + int64_t(hi) * N, N, NN, GU, N, sGU, S2 + lo, nc, sS2, 0.0,
+                   "refine_proj"));
+    const int64_t work = nb * int64_t(nc) * m;
+    hipLaunchKernelGGL(refine_coef, dim3(static_cast<uint32_t>(std::min<int64_t>((work + 255) / 256, 65536))),
+                       dim3(256), 0, stream, S2, nc, m, lo, N, lam, nb);
+    BE_RET_IF(check_launch(ctx, "refine_coef"));
+    // U_w += V F
+    if (lo > 0) BE_RET_IF(zg(N, m, lo, 0, Uall, N, NN, S2, nc, sS2, U, ldu, us, 1.0, "refine_corr"));
+    if (hi < N)
+      BE_RET_IF(zg(N, m, N - hi, 0, Uall + int64_t(hi) * N, N, NN, S2 + lo, nc, sS2, U, ldu, us, 1.0, "refine_corr"));
+  }
+  // Newton-Schulz orthonormalization in FP64, ping-pong between U (buffer 0)
+  // and the left half of GU (buffer 1); a matrix whose error is below 1e-6
+  // takes its last step, which leaves about 1e-12
+  struct Buf {
+    double2 *p;
+    int ld;
+    int64_t s;
+  } buf[2] = {{U, ldu, us}, {GU, N, sGU}};
+  const bool capturing = stream_capturing(stream);
+  int *hleft = static_cast<int *>(ctx->pinned);
+  hipLaunchKernelGGL(ns_init_real, dim3(static_cast<uint32_t>((nb + 255) / 256)), dim3(256), 0, stream, act, loc, nb);
+  BE_RET_IF(check_launch(ctx, "ns_init_real"));
+  int cur = 0;
+  for (int it = 0; it < 4; ++it) {
+    const Buf &X = buf[cur], &Y = buf[cur ^ 1];
+    ZGemm g;  // Gm = X^H X
+    g.M = m;
+    g.N = m;
+    g.K = N;
+    g.opA = 1;
+    g.opB = 0;
+    g.A = X.p;
+    g.lda = X.ld;
+    g.bA = ZBatch::strided(X.s);
+    g.B = X.p;
+    g.ldb = X.ld;
+    g.bB = ZBatch::strided(X.s);
+    g.C = Gm;
+    g.ldc = m;
+    g.bC = ZBatch::strided(int64_t(m) * m);
+    g.batch = nb;
+    g.tag = "refine_orth";
+    g.herm = true;
+    g.act = act;
+    BE_RET_IF(zgemm(ctx, g, stream));
+    hipLaunchKernelGGL(ns_prep_cplx, dim3(static_cast<uint32_t>(nb)), dim3(PT), 0, stream, Gm, m, err, act, 1e-14,
+                       1e-6);
+    BE_RET_IF(check_launch(ctx, "ns_prep_cplx"));
+    ZGemm h;  // Y = X (3 I - Gm) / 2
+    h.M = N;
+    h.N = m;
+    h.K = m;
+    h.A = X.p;
+    h.lda = X.ld;
+    h.bA = ZBatch::strided(X.s);
+    h.B = Gm;
+    h.ldb = m;
+    h.bB = ZBatch::strided(int64_t(m) * m);
+    h.C = Y.p;
+    h.ldc = Y.ld;
+    h.bC = ZBatch::strided(Y.s);
+    h.batch = nb;
+    h.tag = "refine_orth";
+    h.act = act;
+    BE_RET_IF(zgemm(ctx, h, stream));
+    hipLaunchKernelGGL(zero_i32, dim3(1), dim3(1), 0, stream, n_left);
+    hipLaunchKernelGGL(ns_post_real, dim3(static_cast<uint32_t>((nb + 255) / 256)), dim3(256), 0, stream, act, loc, err,
+                       nb, static_cast<unsigned char>(cur ^ 1), n_left);
+    BE_RET_IF(check_launch(ctx, "ns_post_real"));
+    cur ^= 1;
+    if (!capturing) {
+      BE_HIP_TRY(ctx, hipMemcpyAsync(hleft, n_left, sizeof(int), hipMemcpyDeviceToHost, stream));
+      BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+      if (*hleft == 0) break;
+    }
+  }
+  hipLaunchKernelGGL(flag_nonorth, dim3(static_cast<uint32_t>((nb + 255) / 256)), dim3(256), 0, stream, err, nb, 1e-10,
+                     status);
+  hipLaunchKernelGGL(refine_copy_back, dim3(64, gy), dim3(256), 0, stream, GU, sGU, N, m, loc, nb, U, ldu, us);
+  return check_launch(ctx, "refine_copy_back");
+}
+
+static int eigh_refined(be_ctx *ctx, const double2 *H, int N, int ld, int64_t ms, int64_t n_mat, int lo, int hi,
+                        double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream) {
+  const int m = hi - lo, nc = N - m;
+  BE_RET_IF(check_eigh_lds(ctx, N, N, sizeof(float2)));
+  if (n_mat == 0) return BE_OK;
+  const int mm = std::max(m, 1);
+  const size_t own = 16 * (3 * size_t(N) * N + size_t(N) * 2 * mm + size_t(std::max(nc, 1)) * 2 * mm +
+                           size_t(mm) * mm) -
+                     8 * size_t(N) * N + 8 * (size_t(N) + 2) + 16 + 6 * 256;
+  const size_t per = eigh_chunk_bytes<float>(ctx, N, N) + own;
+  const int64_t cap =
+      eigh_sub_batch<float>(ctx, N, per, ctx->ws_bytes[WS_EIGH] + ctx->ws_bytes[WS_MISC], n_mat);
+  for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
+    const int64_t nb = std::min<int64_t>(cap, n_mat - b0);
+    BE_RET_IF(eigh_refined_chunk(ctx, H + b0 * ms, N, ld, ms, nb, lo, hi, evals + b0 * (m + 2), U + b0 * us, ldu, us,
+                                 status + b0, stream));
   }
   return BE_OK;
 }
@@ -1627,6 +2036,11 @@ extern "C" int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, i
     BE_CHECK_ARG(ctx, dtype == BE_C128, "be_eigh_batched: BE_FP64 needs BE_C128 matrices");
     return eigh_run<double>(ctx, static_cast<double2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
                             static_cast<double2 *>(U), ldu, u_stride, status, stream);
+  }
+  if (precision == BE_MIXED_FP32_REFINED) {
+    BE_CHECK_ARG(ctx, dtype == BE_C128, "be_eigh_batched: BE_MIXED_FP32_REFINED needs BE_C128 matrices");
+    return eigh_refined(ctx, static_cast<const double2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
+                        static_cast<double2 *>(U), ldu, u_stride, status, stream);
   }
   if (precision == BE_MIXED_FP32) {
     BE_CHECK_ARG(ctx, dtype == BE_C64, "be_eigh_batched: BE_MIXED_FP32 needs BE_C64 matrices");

@@ -64,6 +64,7 @@ struct GP {
   int tiles_m, tiles_n;
   int herm;  // Hermitian C: lower tiles only, strictly lower tiles mirrored into the upper triangle (if mirror)
   int mirror;
+  const int *act;  // per batch item: 0 skips the item (its C is left untouched), or null
   const double *sB;  // row scales of B (OPB == 0), or null: s_q = sB + (q / sB_div) * sB_ld
   int64_t sB_div, sB_ld;
 };
@@ -90,6 +91,7 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   const int i0 = tm * BM, j0 = tn * BN;
   static_assert(BM == BN, "square tiles (Hermitian mode pairs tile (tm, tn) with (tn, tm))");
   if (p.herm && tm < tn) return;
+  if (p.act && p.act[q] == 0) return;
   const cplx *A = p.A + be::zbatch_off(p.bA, q);
   const cplx *B = p.B + be::zbatch_off(p.bB, q);
   cplx *C = p.C + be::zbatch_off(p.bC, q);
@@ -299,6 +301,7 @@ struct DP {
   int64_t batch;
   int tiles_m, tiles_n;
   int sym;  // symmetric C: lower tiles only, strictly lower tiles mirrored into the upper triangle
+  const int *act;  // per batch item: 0 skips the item, or null
 };
 
 template <int BM, int BN, int WM, int WN, int OPA, int OPB>
@@ -320,6 +323,7 @@ __global__ __launch_bounds__(64 * WM * WN) void dgemm_kernel(DP p) {
   const int i0 = tm * BM, j0 = tn * BN;
   static_assert(BM == BN, "square tiles (symmetric mode pairs tile (tm, tn) with (tn, tm))");
   if (p.sym && tm < tn) return;
+  if (p.act && p.act[q] == 0) return;
   const double *A = p.A + be::zbatch_off(p.bA, q);
   const double *B = p.B + be::zbatch_off(p.bB, q);
   double *C = p.C + be::zbatch_off(p.bC, q);
@@ -430,6 +434,7 @@ int dgemm(be_ctx *ctx, const DGemm &g, hipStream_t stream) {
   p.beta = g.beta;
   p.batch = g.batch;
   p.sym = g.sym ? 1 : 0;
+  p.act = g.act;
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
   if (use_big_tiles(p.M, p.N)) return dlaunch<64, 64, 4, 2>(ctx, p, g.opA, g.opB, stream);
   if (p.M >= 24 && p.N >= 24) return dlaunch<32, 32, 2, 2>(ctx, p, g.opA, g.opB, stream);
@@ -456,6 +461,7 @@ int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
   p.mirror = g.herm_mirror ? 1 : 0;
+  p.act = g.act;
   BE_CHECK_ARG(ctx, !g.scaleB || (g.opB == 0 && g.scaleB_div >= 1), "zgemm: row scaling of B needs opB = 'N'");
   p.sB = g.scaleB;
   p.sB_div = g.scaleB_div;
@@ -483,6 +489,7 @@ int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
   p.mirror = g.herm_mirror ? 1 : 0;
+  p.act = g.act;
   p.sB = nullptr;
   p.sB_div = 1;
   p.sB_ld = 0;

@@ -66,17 +66,22 @@ __global__ void k_zero_u32(uint32_t *p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-// G <- 1.5 I - 0.5 G for every m x m matrix; per-matrix err = max |G - I|
-// (before the update) into err[q] and atomically into *gmax (bit pattern of a
-// non-negative double orders like an integer).
-// tpm threads per matrix (64 for m*m <= 64: four matrices per block of 256;
-// else 256), one atomicMax per block.
-__global__ void k_ns_prep(double2 *G, int m, int64_t n_mat, int tpm, double *err, unsigned long long *gmax) {
+// Newton-Schulz polar iteration with a state per matrix (act): 1 iterating,
+// 2 taking its last step, 0 done. One step is G = X^H X, then k_ns_prep
+// (G <- 1.5 I - 0.5 G, err = max |G - I| before it, and the next state: done
+// without a step once err < 1e-30; a last step once err < 1e-7, which leaves
+// about (3/4) err^2 < 1e-14), then X_new = X G and k_ns_post. Matrices in
+// state 0 are skipped by both GEMMs, so each matrix stops at its own
+// convergence. loc[q] records which of the two buffers holds matrix q's
+// latest iterate. tpm threads per matrix (64 for m*m <= 64: four matrices per
+// block of 256; else 256: one matrix per block).
+__global__ void k_ns_prep(double2 *G, int m, int64_t n_mat, int tpm, double *err, int *act) {
   const int per_blk = blockDim.x / tpm;
   const int sub = threadIdx.x / tpm, t = threadIdx.x % tpm;
   const int64_t q = int64_t(blockIdx.x) * per_blk + sub;
+  const bool live = q < n_mat && act[q] != 0;  // uniform over the matrix's threads
   double e = 0.0;
-  if (q < n_mat) {
+  if (live) {
     double2 *Gq = G + q * int64_t(m) * m;
     for (int k = t; k < m * m; k += tpm) {
       int r = k % m, c = k / m;
@@ -90,18 +95,50 @@ __global__ void k_ns_prep(double2 *G, int m, int64_t n_mat, int tpm, double *err
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
   __syncthreads();
-  if (tpm == 64) {  // one wave per matrix
-    if ((threadIdx.x & 63) == 0 && q < n_mat) err[q] = e == e ? e : INFINITY;
-  } else if (threadIdx.x == 0 && q < n_mat) {
-    double v = red[0];
+  double v = e;
+  if (tpm != 64) {
+    v = red[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
-    err[q] = v == v ? v : INFINITY;
   }
-  if (threadIdx.x == 0) {
-    double v = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+  if (live && t == 0) {
     if (!(v == v)) v = INFINITY;
-    atomicMax(gmax, (unsigned long long)__double_as_longlong(v));
+    err[q] = v;
+    act[q] = v < 1e-30 ? 0 : v < 1e-7 ? 2 : 1;
+  }
+}
+
+// After the step into buffer `parity`: the matrices that took it have their
+// iterate there; those in their last step are done. *n_left (zeroed before)
+// counts the matrices still iterating.
+__global__ void k_ns_post(int *act, unsigned char *loc, int64_t n, unsigned char parity, int *n_left) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int left = 0;
+  if (q < n && act[q] != 0) {
+    loc[q] = parity;
+    if (act[q] == 2) act[q] = 0;
+    else left = 1;
+  }
+  for (int o = 32; o > 0; o >>= 1) left += __shfl_xor(left, o, 64);
+  if ((threadIdx.x & 63) == 0 && left) atomicAdd(n_left, left);
+}
+
+__global__ void k_ns_init(int *act, unsigned char *loc, int64_t n) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < n) {
+    act[q] = 1;
+    loc[q] = 0;
+  }
+}
+
+__global__ void k_zero_i32(int *p) { *p = 0; }
+
+// dst[q] = src[q] for the matrices whose latest iterate is in src (loc[q] == 1)
+__global__ void k_copy_mats_loc(const double2 *src, double2 *dst, int64_t mm, int64_t n, const unsigned char *loc) {
+  int64_t q = blockIdx.y;
+  for (; q < n; q += gridDim.y) {
+    if (!loc[q]) continue;
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < mm; k += int64_t(gridDim.x) * blockDim.x)
+      dst[q * mm + k] = src[q * mm + k];
   }
 }
 
@@ -336,6 +373,282 @@ __global__ __launch_bounds__(64) void k_unitary_eig(const double2 *W, int m, int
   if (failed && lane == 0) atomicOr(&flags[q / flag_div], BE_ST_NONCONVERGED);
 }
 
+// LDS ordering between the lanes of one wave (the wave's LDS operations
+// complete in program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Window of the QR sweep held in LDS: rows and columns rb .. rb + QW - 1.
+constexpr int QW = 64, QLD = QW + 1;
+constexpr int kUnitaryWgLds = QW * QLD;  // double2 entries of the window
+
+// The same eigenphases for large orders (no Schur vectors): one workgroup of
+// NT threads per matrix, H held row-major in global scratch so that the
+// reduction's accesses are coalesced: the Householder step's left update
+// runs with threads over columns, its right update with a wave per row
+// (lanes over columns, wave sums). A QR sweep chases its bulge through
+// windows of QW rows and columns copied to LDS: one wave applies the
+// window's rotations there (no workgroup barrier per rotation), and the
+// parts of those rotations outside the window (the rows' entries to the
+// right of it, the columns' entries above it) are applied afterwards by the
+// whole workgroup, each thread streaming one column (or row) through the
+// window's rotations in order. Shifts and deflation tests are computed
+// redundantly by every thread from the same entries, between barriers.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, int64_t n_mat, double2 *Hs,
+                                                       double *theta_sorted, int ldt, double *theta_raw,
+                                                       uint32_t *flags, int flag_div) {
+  // Householder vector (m) during the reduction, the QR window (QW x QLD)
+  // afterwards; then the eigenvalues (m)
+  extern __shared__ double2 sv[];
+  double2 *const Bw = sv;
+  double2 *slam = sv + max(m, kUnitaryWgLds);
+  __shared__ double rot_c[QW];
+  __shared__ double2 rot_s[QW];
+  __shared__ double red[NT / 64];
+  __shared__ int redi[NT / 64];
+  const int64_t q = blockIdx.x;
+  if (q >= n_mat) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NT / 64;
+  const double2 *Wq = W + q * int64_t(m) * m;
+  double2 *H = Hs + q * int64_t(m) * m;  // row-major: H[r * m + c]
+  for (int64_t k = tid; k < int64_t(m) * m; k += NT) {
+    const int r = int(k % m), c = int(k / m);
+    H[int64_t(r) * m + c] = Wq[k];
+  }
+  __syncthreads();
+  auto at = [&](int r, int c) -> double2 & { return H[int64_t(r) * m + c]; };
+  auto bsum = [&](double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    return t;
+  };
+  // ---- Hessenberg reduction: H <- P^H H P, P = I - tau v v^H
+  for (int k = 0; k + 2 < m; ++k) {
+    double xn = 0.0;
+    for (int r = k + 2 + tid; r < m; r += NT) {
+      const double2 a = at(r, k);
+      xn = fma(a.x, a.x, fma(a.y, a.y, xn));
+    }
+    xn = bsum(xn);
+    const double2 alpha = at(k + 1, k);
+    double2 tau, scal;
+    double beta;
+    if (xn == 0.0 && alpha.y == 0.0) {
+      tau = make_double2(0.0, 0.0);
+      scal = make_double2(0.0, 0.0);
+      beta = alpha.x;
+    } else {
+      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn);
+      beta = alpha.x >= 0.0 ? -nrm : nrm;
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      scal = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+    }
+    for (int r = tid; r < m; r += NT) {
+      double2 v;
+      if (r <= k) v = make_double2(0.0, 0.0);
+      else if (r == k + 1) v = make_double2(1.0, 0.0);
+      else v = be::cmul(at(r, k), scal);
+      sv[r] = v;
+    }
+    __syncthreads();
+    for (int r = k + 1 + tid; r < m; r += NT) at(r, k) = r == k + 1 ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+    if (tau.x != 0.0 || tau.y != 0.0) {
+      const double2 ctau = be::cconj(tau);
+      // left: rows k+1..m-1, threads over columns k+1..m-1
+      for (int c = k + 1 + tid; c < m; c += NT) {
+        double2 sacc = make_double2(0.0, 0.0);
+        for (int r = k + 1; r < m; ++r) sacc = be::cadd(sacc, be::cmulc(sv[r], at(r, c)));
+        const double2 f = be::cmul(ctau, sacc);
+        for (int r = k + 1; r < m; ++r) at(r, c) = be::csub(at(r, c), be::cmul(sv[r], f));
+      }
+      __syncthreads();
+      // right: every row, columns k+1..m-1: a wave per row, lanes over columns
+      for (int i = wave; i < m; i += nw) {
+        double sr = 0.0, si = 0.0;
+        for (int c = k + 1 + lane; c < m; c += 64) {
+          const double2 h = at(i, c), v = sv[c];
+          sr += h.x * v.x - h.y * v.y;
+          si += h.x * v.y + h.y * v.x;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          sr += __shfl_xor(sr, o, 64);
+          si += __shfl_xor(si, o, 64);
+        }
+        const double2 f = be::cmul(tau, make_double2(sr, si));
+        for (int c = k + 1 + lane; c < m; c += 64) at(i, c) = be::csub(at(i, c), be::cmul(f, be::cconj(sv[c])));
+      }
+    }
+    __syncthreads();
+  }
+  // ---- single-shift QR on the Hessenberg matrix
+  const double tol = 4.0 * DBL_EPSILON;
+  int ihi = m - 1, its = 0, total = 0;
+  bool failed = false;
+  while (ihi >= 0) {
+    // deflation: the largest k <= ihi with a negligible subdiagonal (block max)
+    int lk = 0;
+    for (int k = 1 + tid; k <= ihi; k += NT)
+      if (cabs1(at(k, k - 1)) <= tol) lk = max(lk, k);
+    for (int o = 32; o > 0; o >>= 1) lk = max(lk, __shfl_xor(lk, o, 64));
+    if (lane == 0) redi[wave] = lk;
+    __syncthreads();
+    int l = 0;
+    for (int w = 0; w < nw; ++w) l = max(l, redi[w]);
+    __syncthreads();
+    if (l == ihi) {
+      if (tid == 0) {
+        slam[ihi] = at(ihi, ihi);
+        if (ihi > 0) at(ihi, ihi - 1) = make_double2(0.0, 0.0);
+      }
+      --ihi;
+      its = 0;
+      __syncthreads();
+      continue;
+    }
+    __syncthreads();
+    if (l > 0 && tid == 0) at(l, l - 1) = make_double2(0.0, 0.0);
+    double2 mu;
+    const double2 dd = at(ihi, ihi);
+    if (its == 10 || its == 20) {
+      mu = make_double2(dd.x + 0.75 * cabs1(at(ihi, ihi - 1)), dd.y);
+    } else {
+      const double2 a = at(ihi - 1, ihi - 1), b = at(ihi - 1, ihi), c = at(ihi, ihi - 1);
+      const double2 t = make_double2(0.5 * (a.x - dd.x), 0.5 * (a.y - dd.y));
+      const double2 disc = csqrt_d(be::cadd(be::cmul(t, t), be::cmul(b, c)));
+      const double sgn = (t.x * disc.x + t.y * disc.y) >= 0.0 ? -1.0 : 1.0;
+      mu = make_double2(dd.x + t.x + sgn * disc.x, dd.y + t.y + sgn * disc.y);
+    }
+    __syncthreads();
+    // the sweep's rotations k = l .. ihi-1, window by window: a window holds
+    // rows and columns rb .. k1 and takes the rotations k0 <= k < ke whose
+    // rows (k, k+1) and column updates (down to row k+2) stay inside it
+    for (int k0 = l; k0 < ihi;) {
+      const int rb = k0 == l ? l : k0 - 1;
+      const int k1 = min(ihi, rb + QW - 1);
+      const int ke = k1 == ihi ? ihi : k1 - 1;
+      const int nb = k1 - rb + 1;
+      auto B = [&](int r, int c) -> double2 & { return Bw[(r - rb) * QLD + (c - rb)]; };
+      for (int e = tid; e < nb * nb; e += NT) {
+        const int r = rb + e / nb, c = rb + e % nb;
+        B(r, c) = at(r, c);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        for (int k = k0; k < ke; ++k) {
+          double2 f, g;
+          if (k == l) {
+            f = be::csub(B(l, l), mu);
+            g = B(l + 1, l);
+          } else {
+            f = B(k, k - 1);
+            g = B(k + 1, k - 1);
+          }
+          double cr;
+          double2 sn, rr;
+          const double af = hypot(f.x, f.y), ag = hypot(g.x, g.y);
+          if (ag == 0.0) {
+            cr = 1.0;
+            sn = make_double2(0.0, 0.0);
+            rr = f;
+          } else if (af == 0.0) {
+            cr = 0.0;
+            sn = make_double2(g.x / ag, -g.y / ag);
+            rr = make_double2(ag, 0.0);
+          } else {
+            const double nrm = hypot(af, ag);
+            const double2 fu = make_double2(f.x / af, f.y / af);
+            cr = af / nrm;
+            sn = be::cscale(be::cmul(fu, be::cconj(g)), 1.0 / nrm);
+            rr = be::cscale(fu, nrm);
+          }
+          wave_lds_sync();
+          if (lane == 0) {
+            rot_c[k - k0] = cr;
+            rot_s[k - k0] = sn;
+            if (k > l) {
+              B(k, k - 1) = rr;
+              B(k + 1, k - 1) = make_double2(0.0, 0.0);
+            }
+          }
+          // rows k, k+1 over the window's columns k..k1
+          for (int c = k + lane; c <= k1; c += 64) {
+            const double2 x = B(k, c), y = B(k + 1, c);
+            B(k, c) = be::cadd(be::cscale(x, cr), be::cmul(sn, y));
+            B(k + 1, c) = be::csub(be::cscale(y, cr), be::cmul(be::cconj(sn), x));
+          }
+          wave_lds_sync();
+          // columns k, k+1 over the window's rows rb..min(k+2, ihi)
+          const int rmax = min(k + 2, ihi);
+          for (int r = rb + lane; r <= rmax; r += 64) {
+            const double2 x = B(r, k), y = B(r, k + 1);
+            B(r, k) = be::cadd(be::cscale(x, cr), be::cmul(be::cconj(sn), y));
+            B(r, k + 1) = be::csub(be::cscale(y, cr), be::cmul(sn, x));
+          }
+          wave_lds_sync();
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < nb * nb; e += NT) {
+        const int r = rb + e / nb, c = rb + e % nb;
+        at(r, c) = B(r, c);
+      }
+      // rows k0..ke right of the window: each thread a column, the rotations in order
+      for (int c = k1 + 1 + tid; c <= ihi; c += NT) {
+        double2 x = at(k0, c);
+        for (int k = k0; k < ke; ++k) {
+          const double cr = rot_c[k - k0];
+          const double2 sn = rot_s[k - k0], y = at(k + 1, c);
+          at(k, c) = be::cadd(be::cscale(x, cr), be::cmul(sn, y));
+          x = be::csub(be::cscale(y, cr), be::cmul(be::cconj(sn), x));
+        }
+        at(ke, c) = x;
+      }
+      // columns k0..ke above the window: each thread a row
+      for (int r = l + tid; r < rb; r += NT) {
+        double2 x = at(r, k0);
+        for (int k = k0; k < ke; ++k) {
+          const double cr = rot_c[k - k0];
+          const double2 sn = rot_s[k - k0], y = at(r, k + 1);
+          at(r, k) = be::cadd(be::cscale(x, cr), be::cmul(be::cconj(sn), y));
+          x = be::csub(be::cscale(y, cr), be::cmul(sn, x));
+        }
+        at(r, ke) = x;
+      }
+      __syncthreads();
+      k0 = ke;
+    }
+    ++its;
+    ++total;
+    if (total > 60 * m + 60) {
+      failed = true;
+      for (int r = tid; r <= ihi; r += NT) slam[r] = at(r, r);
+      __syncthreads();
+      break;
+    }
+  }
+  __syncthreads();
+  // ---- phases, ascending rank sort
+  for (int n = tid; n < m; n += NT) {
+    const double th = arg_pi(slam[n]);
+    if (theta_raw) theta_raw[q * m + n] = th;
+    int rank = 0;
+    for (int k = 0; k < m; ++k) {
+      const double tk = arg_pi(slam[k]);
+      rank += (tk < th) || (tk == th && k < n);
+    }
+    theta_sorted[q * int64_t(ldt) + rank] = th;
+  }
+  if (failed && tid == 0) atomicOr(&flags[q / flag_div], BE_ST_NONCONVERGED);
+}
+
 // Chern winding of each system from theta [line][ldt] (first m valid).
 __global__ void k_winding(const double *theta, int ldt, int m, int n_sys, int n_perp, double *phi, int32_t *winding,
                           uint32_t *status) {
@@ -382,6 +695,9 @@ __global__ void k_or_lines(const uint32_t *line_st, int64_t n_lines, int per_sys
 
 namespace be {
 
+static int unitary_phases(be_ctx *ctx, const double2 *cur, int m, int64_t n_lines, double2 *Hs, double2 *Zout,
+                          double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream);
+
 // Wilson loops of n_lines closed lines of a grid of N x m matrices.
 // theta_sorted: [line][ldt]; Zout/theta_raw: optional eigenvectors of each W
 // (m x m per line) and the phase of each column. Fkeep: if non-null receives
@@ -389,21 +705,24 @@ namespace be {
 // call that uses slot WS_WILSON. line_status: [n_lines], OR-ed.
 static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n_loop, int mode, double *theta_sorted,
                        int ldt, double2 *Zout, double *theta_raw, uint32_t *line_status, const double2 **Fkeep,
-                       hipStream_t stream) {
+                       hipStream_t stream, double2 *Wout = nullptr) {
   if (n_lines == 0) return BE_OK;
   if (m == 0) return BE_OK;
   const int64_t mm = int64_t(m) * m;
   const int64_t nm = n_lines * n_loop;
   double2 *F = nullptr, *B1 = nullptr, *B2 = nullptr, *Hs = nullptr;
   double *err = nullptr;
-  unsigned long long *gmax = nullptr;
+  int *act = nullptr, *n_left = nullptr;
+  unsigned char *loc = nullptr;
   Carve cv;
   cv.add(&F, size_t(nm * mm));
   cv.add(&B1, size_t(nm * mm));
   cv.add(&B2, size_t(nm * mm));
   cv.add(&Hs, size_t(n_lines * mm));
   cv.add(&err, size_t(nm));
-  cv.add(&gmax, 1);
+  cv.add(&act, size_t(nm));
+  cv.add(&loc, size_t(nm));
+  cv.add(&n_left, 1);
   BE_RET_IF(cv.commit(ctx, stream, WS_WILSON));
   // ---- overlaps
   {
@@ -426,14 +745,20 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
     g.tag = "overlap";
     BE_RET_IF(zgemm(ctx, g, stream));
   }
-  // ---- polar factors (Newton-Schulz)
+  // ---- polar factors (Newton-Schulz, per-matrix convergence). Up to 51
+  // steps (sigma_min = 1e-8 converges at the 51st check); outside graph
+  // capture the host stops the schedule once no matrix is left (read back
+  // every other step from the fourth on), under capture every step is
+  // launched and finished matrices skip it.
   if (mode == BE_OVL_POLAR) {
+    const bool capturing = stream_capturing(stream);
+    int *hleft = static_cast<int *>(ctx->pinned);
     double2 *X = F, *Xn = B2;
-    double *hmax = static_cast<double *>(ctx->pinned);
-    int it = 0;
-    bool converged = false;
-    for (; it < 51; ++it) {  // sigma_min = 1e-8 converges at the 51st check
-      BE_HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), stream));
+    unsigned char parity = 0;  // buffer of X: 0 = F, 1 = B2
+    hipLaunchKernelGGL(k_ns_init, dim3(static_cast<uint32_t>((nm + 255) / 256)), dim3(256), 0, stream, act, loc, nm);
+    BE_RET_IF(check_launch(ctx, "ns_init"));
+    const int tpm = m * m <= 64 ? 64 : 256;
+    for (int it = 0; it < 51; ++it) {
       ZGemm g;  // G = X^H X
       g.M = m;
       g.N = m;
@@ -451,14 +776,11 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       g.batch = nm;
       g.tag = "polar";
       g.herm = true;  // X^H X: lower tiles, mirrored
+      g.act = act;
       BE_RET_IF(zgemm(ctx, g, stream));
-      const int tpm = m * m <= 64 ? 64 : 256;
       hipLaunchKernelGGL(k_ns_prep, dim3(static_cast<uint32_t>((nm + 256 / tpm - 1) / (256 / tpm))), dim3(256), 0,
-                         stream, B1, m, nm, tpm, err, gmax);
+                         stream, B1, m, nm, tpm, err, act);
       BE_RET_IF(check_launch(ctx, "ns_prep"));
-      BE_HIP_TRY(ctx, hipMemcpyAsync(hmax, gmax, sizeof(double), hipMemcpyDeviceToHost, stream));
-      BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
-      const double e = *hmax;
       ZGemm h;  // Xn = X (1.5 I - 0.5 G)
       h.M = m;
       h.N = m;
@@ -474,27 +796,28 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
       h.bC = ZBatch::strided(mm);
       h.batch = nm;
       h.tag = "polar";
-      if (e < 1e-30) break;  // already unitary to working precision
+      h.act = act;
       BE_RET_IF(zgemm(ctx, h, stream));
+      hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, stream, n_left);
+      hipLaunchKernelGGL(k_ns_post, dim3(static_cast<uint32_t>((nm + 255) / 256)), dim3(256), 0, stream, act, loc, nm,
+                         static_cast<unsigned char>(parity ^ 1), n_left);
+      BE_RET_IF(check_launch(ctx, "ns_post"));
       std::swap(X, Xn);
-      if (e < 1e-7) {
-        // quadratic convergence: the step just taken leaves a Gram error of
-        // about (3/4) e^2 < 1e-14
-        converged = true;
-        ++it;
-        break;
+      parity ^= 1;
+      if (!capturing && it >= 3 && (it & 1)) {
+        BE_HIP_TRY(ctx, hipMemcpyAsync(hleft, n_left, sizeof(int), hipMemcpyDeviceToHost, stream));
+        BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
+        if (*hleft == 0) break;
       }
     }
-    if (X != F) {
-      hipLaunchKernelGGL(k_copy_mats, dim3(64, static_cast<uint32_t>(std::min<int64_t>(nm, 65535))), dim3(256), 0, stream,
-                         X, mm, F, mm, mm, nm);
-      BE_RET_IF(check_launch(ctx, "copy_mats"));
-    }
-    (void)converged;
-    // matrices whose Gram error before the last step stayed above 1e-7 did
-    // not converge: (near) singular overlaps
+    // every matrix's latest iterate into F
+    hipLaunchKernelGGL(k_copy_mats_loc, dim3(64, static_cast<uint32_t>(std::min<int64_t>(nm, 65535))), dim3(256), 0,
+                       stream, B2, F, mm, nm, loc);
+    BE_RET_IF(check_launch(ctx, "copy_mats_loc"));
+    // matrices whose last Gram error stayed at or above 1e-7 did not
+    // converge: (near) singular overlaps
     hipLaunchKernelGGL(k_flag_err, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, err,
-                       n_lines, n_loop, 1e-7, BE_ST_OVERLAP_SINGULAR, line_status);
+                       n_lines, n_loop, 1e-7 * (1.0 - 1e-12), BE_ST_OVERLAP_SINGULAR, line_status);
     BE_RET_IF(check_launch(ctx, "flag_err"));
   }
   if (Fkeep) *Fkeep = F;
@@ -532,9 +855,33 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
     n = n2;
   }
   // cur now holds W per line (n_loop == 1 means W = F_0)
+  if (Wout) {  // the caller takes the eigenphases of all lines at once
+    hipLaunchKernelGGL(k_copy_mats, dim3(64, static_cast<uint32_t>(std::min<int64_t>(n_lines, 65535))), dim3(256), 0,
+                       stream, cur, mm, Wout, mm, mm, n_lines);
+    return check_launch(ctx, "copy_w");
+  }
+  return unitary_phases(ctx, cur, m, n_lines, Hs, Zout, theta_sorted, ldt, theta_raw, line_status, stream);
+}
+
+// Eigenphases of n_lines unitary m x m matrices W (ascending into
+// theta_sorted [line][ldt]); Zout/theta_raw as for wilson_core; Hs: scratch of
+// n_lines m x m matrices (unused when the matrices fit LDS).
+static int unitary_phases(be_ctx *ctx, const double2 *cur, int m, int64_t n_lines, double2 *Hs, double2 *Zout,
+                          double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream) {
   // ---- eigenphases
   const size_t esm_lds = (size_t(m) * m + 2 * size_t(m)) * sizeof(double2);
   const bool inlds = Zout == nullptr && esm_lds <= 160 * 1024;
+  if (Zout == nullptr && !inlds) {  // large order: a workgroup per matrix, row-major scratch
+    const size_t esm = (size_t(std::max(m, kUnitaryWgLds)) + size_t(m)) * sizeof(double2);
+    BE_CHECK_ARG(ctx, esm <= 150 * 1024, "Wilson loop: order of the Wilson matrices too large for the eigenphase kernel");
+    if (esm > 65536)
+      BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig_wg<256>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
+    ProfScope prof(ctx, "unitary_eig", stream);
+    hipLaunchKernelGGL(k_unitary_eig_wg<256>, dim3(static_cast<uint32_t>(n_lines)), dim3(256), esm, stream, cur, m,
+                       n_lines, Hs, theta_sorted, ldt, theta_raw, line_status, 1);
+    return check_launch(ctx, "unitary_eig");
+  }
   const size_t esm = inlds ? esm_lds : 2 * size_t(m) * sizeof(double2);
   auto kern = inlds ? &k_unitary_eig<true> : &k_unitary_eig<false>;
   if (esm > 65536)
@@ -581,8 +928,31 @@ extern "C" int be_wilson_loop(be_ctx *ctx, const void *U, int32_t N, int32_t m, 
   hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
                      int64_t(n_sys));
   BE_RET_IF(check_launch(ctx, "zero"));
-  Grid g{static_cast<const double2 *>(U), ldu, u_stride};
-  BE_RET_IF(wilson_core(ctx, g, N, m, n_lines, n_par, mode, theta, m, nullptr, nullptr, line_st, nullptr, stream));
+  // lines in passes whose overlaps, polar and product buffers (three m x m
+  // matrices per link) stay within about 4 GiB of workspace; with more than
+  // one pass, each pass leaves its Wilson matrices and the eigenphases of all
+  // lines are taken in one launch (the eigenphase kernel runs a workgroup per
+  // line: one launch keeps as many compute units busy as there are lines)
+  const int64_t mm = int64_t(std::max(m, 1)) * std::max(m, 1);
+  const int64_t per_line = int64_t(n_par) * 3 * mm * 16 + 4096;
+  const int64_t lp = std::max<int64_t>(1, std::min<int64_t>(n_lines, (int64_t(4) << 30) / per_line));
+  if (lp >= n_lines || m == 0) {
+    Grid g{static_cast<const double2 *>(U), ldu, u_stride};
+    BE_RET_IF(wilson_core(ctx, g, N, m, n_lines, n_par, mode, theta, m, nullptr, nullptr, line_st, nullptr, stream));
+  } else {
+    double2 *Wall = nullptr, *Hs = nullptr;
+    Carve cw;
+    cw.add(&Wall, size_t(n_lines * mm));
+    cw.add(&Hs, size_t(n_lines * mm));
+    BE_RET_IF(cw.commit(ctx, stream, WS_MISC));
+    for (int64_t l0 = 0; l0 < n_lines; l0 += lp) {
+      const int64_t nl = std::min<int64_t>(lp, n_lines - l0);
+      Grid g{static_cast<const double2 *>(U) + l0 * n_par * u_stride, ldu, u_stride};
+      BE_RET_IF(wilson_core(ctx, g, N, m, nl, n_par, mode, theta + l0 * m, m, nullptr, nullptr, line_st + l0, nullptr,
+                            stream, Wall + l0 * mm));
+    }
+    BE_RET_IF(unitary_phases(ctx, Wall, m, n_lines, Hs, nullptr, theta, m, nullptr, line_st, stream));
+  }
   hipLaunchKernelGGL(k_or_lines, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, line_st,
                      n_lines, n_perp, status);
   hipLaunchKernelGGL(k_winding, dim3((n_sys + 63) / 64), dim3(64), 0, stream, theta, m, m, n_sys, n_perp, phi, winding,
@@ -854,6 +1224,19 @@ __global__ void k_pso_sys(const int32_t *cnt, int n_sys, int64_t k_per_sys, int3
   m_dn[s] = c0;
 }
 
+// Sector sizes given by the caller for a captured call (at most 256 systems).
+struct SectorSizes {
+  int32_t v[256];
+};
+
+// Under graph capture the spin-down sector sizes are the caller's (the
+// graph's shapes depend on them): a system whose actual count differs is
+// flagged PSO_GAP (its sector results are then invalid).
+__global__ void k_pso_expect(const int32_t *mdn, int n_sys, SectorSizes want, uint32_t *status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_sys && mdn[s] != want.v[s]) atomicOr(&status[s], BE_ST_PSO_GAP);
+}
+
 __global__ void k_spin_chern(const int32_t *cd, const int32_t *cu, int n, double *cs) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < n) cs[s] = 0.5 * double(cu[s] - cd[s]);
@@ -871,7 +1254,8 @@ namespace {
 // The projected spin operator A = U^H S U of every k-point and its
 // eigendecomposition (mu ascending, eigenvectors Q, m x m per k-point), the
 // per-k PSO_GAP test and the per-system spin-down sector size m_dn_h (read
-// back, so the stream is synchronized once).
+// back, so the stream is synchronized once; under graph capture m_dn_h is
+// the caller's input instead, checked on the device).
 int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride, int32_t n_sys,
                       int64_t kps, int32_t precision, const double *spin_diag, double *pso_evals, double2 *A32buf,
                       double2 *A, double2 *Q, double *ev, uint32_t *kst, int32_t *cnt, int32_t *mdn, int32_t *m_dn_h,
@@ -906,6 +1290,8 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
   // ---- eigh of the m x m projected spin operator (all bands)
   ctx->prof_scope = "pso_";  // launch-timer names of the inner eigensolver
   int erc;
+  // BE_MIXED_FP32_REFINED takes the FP64 solver here (order m: the sectors'
+  // subspaces are then FP64-accurate, as the refined eigenvectors U are)
   if (precision == BE_MIXED_FP32) {
     // c64 copy of the projected operator
     float2 *A32 = reinterpret_cast<float2 *>(A32buf);
@@ -922,6 +1308,17 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
                      kps, pso_evals, cnt, status);
   hipLaunchKernelGGL(k_pso_sys, dim3((n_sys + 63) / 64), dim3(64), 0, stream, cnt, n_sys, kps, mdn, status);
   BE_RET_IF(check_launch(ctx, "pso"));
+  if (stream_capturing(stream)) {
+    BE_CHECK_ARG(ctx, n_sys <= 256, "spin sectors under graph capture: at most 256 systems per call");
+    SectorSizes want{};
+    for (int s = 0; s < n_sys; ++s) {
+      BE_CHECK_ARG(ctx, m_dn_h[s] >= 0 && m_dn_h[s] <= m, "spin sectors under graph capture: m_dn_h[s] must hold "
+                                                           "the sector sizes (0..m) of an earlier uncaptured call");
+      want.v[s] = m_dn_h[s];
+    }
+    hipLaunchKernelGGL(k_pso_expect, dim3((n_sys + 63) / 64), dim3(64), 0, stream, mdn, n_sys, want, status);
+    return check_launch(ctx, "pso_expect");
+  }
   int32_t *hm = static_cast<int32_t *>(ctx->pinned);
   BE_HIP_TRY(ctx, hipMemcpyAsync(hm, mdn, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost, stream));
   BE_HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -941,7 +1338,8 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   BE_CHECK_ARG(ctx, spin_diag && pso_evals && theta_dn && theta_up && C_dn && C_up && C_s && m_dn_h && status,
                "be_spin_resolved_wilson: null argument");
   BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_resolved_wilson: at most 1024 systems per call");
-  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32, "be_spin_resolved_wilson: bad precision");
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED,
+               "be_spin_resolved_wilson: bad precision");
   if (n_sys == 0) return BE_OK;
   const int64_t kps = int64_t(n_par) * n_perp;
   const int64_t n_k = int64_t(n_sys) * kps;
@@ -968,7 +1366,8 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((2 * n_lines + 255) / 256)), dim3(256), 0, stream, lst,
                      2 * n_lines);
   BE_RET_IF(check_launch(ctx, "zero"));
-  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
+  if (!stream_capturing(stream))  // under capture m_dn_h holds the caller's sector sizes
+    for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
   if (m == 0) return BE_OK;
   BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, A32buf, A, Q, ev,
                               kst, cnt, mdn, m_dn_h, status, stream));
@@ -1035,7 +1434,8 @@ extern "C" int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m,
   BE_CHECK_ARG(ctx, spin_diag && pso_evals && V && m_dn_h && status, "be_spin_sectors: null argument");
   BE_CHECK_ARG(ctx, ldv >= N && v_stride >= int64_t(ldv) * std::max(m, 1), "be_spin_sectors: ldv < N or v_stride < ldv*m");
   BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_sectors: at most 1024 systems per call");
-  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32, "be_spin_sectors: bad precision");
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED,
+               "be_spin_sectors: bad precision");
   if (n_sys == 0) return BE_OK;
   const int64_t kps = n_k_sys;
   const int64_t n_k = int64_t(n_sys) * kps;
@@ -1057,7 +1457,8 @@ extern "C" int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m,
   hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<uint32_t>((n_sys + 255) / 256)), dim3(256), 0, stream, status,
                      int64_t(n_sys));
   BE_RET_IF(check_launch(ctx, "zero"));
-  for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
+  if (!stream_capturing(stream))  // under capture m_dn_h holds the caller's sector sizes
+    for (int s = 0; s < n_sys; ++s) m_dn_h[s] = 0;
   if (m == 0) return BE_OK;
   BE_RET_IF(spin_operator_eig(ctx, U, N, m, ldu, u_stride, n_sys, kps, precision, spin_diag, pso_evals, A32buf, A, Q, ev,
                               kst, cnt, mdn, m_dn_h, status, stream));

@@ -121,6 +121,19 @@ def test_spinful_bbh_paper_size_W1_mixed():
         pytest.xfail(f"mixed path at N = 1764: {err:.3e} rad on {n} plaquettes, above the 1e-6 gate")
 
 
+def test_spinful_bbh_paper_size_W1_refined():
+    """The same on the refined mixed path (FP32 reduction and
+    back-transformation for all bands, FP64 correction of the occupied
+    subspace): C_s = 1 and the sampled plaquettes within the FP64 path's
+    1e-10 rad."""
+    gu.need_gpu()
+    out = _paper_size(gu.ctx(), 1.0, [7, 0], 2)
+    assert int(out["status"][0]) == 0
+    assert float(out["C_s"][0]) == 1.0
+    err, n = _sample_errors(out, 1.0)
+    assert n == 8 and err < TOL, err
+
+
 def test_spinful_bbh_paper_size_W9():
     """W = 9 (past the closing of the average gap): no |C_s| = 1; either 0 or a
     closed PSO gap, flagged. Where the PSO is gapped at a sampled plaquette's

@@ -241,3 +241,97 @@ def test_eigh_tridiagonal_inputs(case):
     c = gu.ctx()
     ev, U, st = run_eigh(c, Hs, lo, hi)
     check(Hs, lo, hi, ev, U, st)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eigh_batch_invariant(precision):
+    """A matrix's eigenvectors do not depend on the batch it is solved in: the
+    same k-points solved in one call, and in two calls at other batch
+    positions, give the same bits (spin-degenerate BHZ spectrum, where the
+    basis inside each degenerate pair is decided by the inverse iteration's
+    start vector)."""
+    gu.need_gpu()
+    hl = syn.bhz_disordered(3, 2.0, [5, 1, 3])
+    kap = syn.kplane(8, 5).reshape(-1, 3)
+    Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in kap])
+    c = gu.ctx()
+    m = hl.N // 2
+    run = run_eigh_mixed if precision else (lambda c_, H_, lo_, hi_: run_eigh(c_, H_, lo_, hi_))
+    ev, U, st = run(c, Hs, 0, m)
+    ev1, U1, st1 = run(c, Hs[:17], 0, m)
+    ev2, U2, st2 = run(c, Hs[17:], 0, m)
+    assert np.array_equal(U, np.concatenate([U1, U2]))
+    assert np.array_equal(ev[:, 1:m + 1], np.concatenate([ev1, ev2])[:, 1:m + 1])
+    assert not st.any()
+
+
+def run_eigh_refined(c, Hs, lo, hi):
+    n, N, _ = Hs.shape
+    m = hi - lo
+    dH = gu.from_np(Hs, N + 3)
+    H0 = dH.clone()
+    U = gu.colmajor(n, N, max(m, 1), N + 1, fill=0)
+    ev = torch.empty((n, m + 2), dtype=torch.float64, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    c.eigh_batched(dH, 0, N, N + 3, dH.stride(0), n, lo, hi, 2, ev, U, N + 1, U.stride(0), st)
+    torch.cuda.synchronize()
+    assert torch.equal(dH, H0), "the refined path must leave H unchanged"
+    return ev.cpu().numpy(), gu.to_np(U, N)[:, :, :m], st.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,lo,hi", [("bhz_L10_W2", 0, 200), ("bhz_vac_L6", 0, 70), ("wannier96", 0, 48),
+                                        ("wannier96", 20, 48), ("bhz_L10_W2", 150, 400)])
+def test_eigh_refined_precision(name, lo, hi):
+    """Mixed path with the FP64 subspace correction: the window's projector
+    within 1e-10 of LAPACK's and U orthonormal to 5e-12 (the FP32 path alone
+    reaches 1e-4 and 1e-5), the invariant-subspace residual H U - U (U^H H U)
+    within 1e-10 ||H||, Rayleigh-quotient eigenvalues within 1e-9 ||H||
+    (second order in the FP32 vectors' error), H left unchanged."""
+    gu.need_gpu()
+    hl = {"bhz_L10_W2": lambda: syn.bhz_disordered(10, 2.0, [3, 2, 1]),
+          "bhz_vac_L6": lambda: syn.bhz_vacancies(6, 0.05, [4, 1, 3]),
+          "wannier96": lambda: syn.wannier_like(96, [5, 2, 1])}[name]()
+    kap = syn.kplane(2, 2).reshape(-1, 3)
+    Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in kap])
+    c = gu.ctx()
+    m = hi - lo
+    ev, U, st = run_eigh_refined(c, Hs, lo, hi)
+    for q in range(Hs.shape[0]):
+        w, V = np.linalg.eigh(Hs[q])
+        nrm = max(1.0, np.max(np.abs(w)))
+        assert np.max(np.abs(ev[q, 1:m + 1] - w[lo:hi])) <= 1e-9 * nrm, q
+        if lo > 0:
+            assert abs(ev[q, 0] - w[lo - 1]) <= 1e-4 * nrm
+        else:
+            assert np.isnan(ev[q, 0])
+        if hi < hl.N:
+            assert abs(ev[q, m + 1] - w[hi]) <= 1e-4 * nrm
+        else:
+            assert np.isnan(ev[q, m + 1])
+        Uq = U[q]
+        # one Newton-Schulz step from the FP32 level (~1e-6) leaves ~3/4 (1e-6)^2
+        assert np.max(np.abs(Uq.conj().T @ Uq - np.eye(m))) < 5e-12
+        P = Uq @ Uq.conj().T
+        assert np.max(np.abs(P - V[:, lo:hi] @ V[:, lo:hi].conj().T)) < 1e-10, (q, np.max(np.abs(P - V[:, lo:hi] @ V[:, lo:hi].conj().T)))
+        A = Uq.conj().T @ Hs[q] @ Uq
+        assert np.max(np.abs(Hs[q] @ Uq - Uq @ A)) < 1e-10 * nrm
+        assert st[q] == 0, (q, st[q])
+
+
+def test_eigh_refined_gap_flag_and_batch_invariance():
+    """The refined path flags a closed gap at the window's edge like the FP64
+    path, and gives the same bits in any batch."""
+    gu.need_gpu()
+    c = gu.ctx()
+    Ha = np.stack([orc.bloch_hamiltonian(syn.atomic([0.0, 0.0, 1.0, 2.0]), [0, 0])])
+    ev, U, st = run_eigh_refined(c, Ha, 0, 1)
+    assert st[0] & 1
+    hl = syn.bhz_disordered(3, 2.0, [5, 1, 3])
+    kap = syn.kplane(6, 5).reshape(-1, 3)
+    Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in kap])
+    m = hl.N // 2
+    ev, U, st = run_eigh_refined(c, Hs, 0, m)
+    ev1, U1, _ = run_eigh_refined(c, Hs[:11], 0, m)
+    ev2, U2, _ = run_eigh_refined(c, Hs[11:], 0, m)
+    assert np.array_equal(U, np.concatenate([U1, U2]))
+    assert not st.any()

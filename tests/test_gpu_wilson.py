@@ -210,3 +210,25 @@ def test_mixed_precision_phases_within_gate(name):
         assert md == sref["m_minus"]
         assert phase_set_error(sp["theta_dn"][0, :, :md].cpu().numpy(), sref["theta_dn"]) < 1e-6
         assert phase_set_error(sp["theta_up"][0, :, :m - md].cpu().numpy(), sref["theta_up"]) < 1e-6
+
+
+@pytest.mark.parametrize("N,m,n_par", [(202, 101, 3), (260, 130, 4), (700, 420, 3)])
+def test_wilson_large_order_random_bases(N, m, n_par):
+    """Wilson loops whose matrices are too large for LDS (the workgroup
+    eigenphase kernel): random orthonormal bases on an n_par x 2 grid, phases
+    and windings against the oracle."""
+    gu.need_gpu()
+    c = gu.ctx()
+    rng = np.random.default_rng([31, N, m])
+    g = np.linalg.qr(rng.standard_normal((2, n_par, N, m)) + 1j * rng.standard_normal((2, n_par, N, m)))[0]
+    U = gu.from_np(g.reshape(2 * n_par, N, m), N)
+    th = torch.empty((2, m), dtype=torch.float64, device="cuda")
+    ph = torch.empty(2, dtype=torch.float64, device="cuda")
+    w = torch.empty(1, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    c.wilson_loop(U, N, m, N, U.stride(0), 1, n_par, 2, 0, th, ph, w, st)
+    torch.cuda.synchronize()
+    ref_th, ref_phi, ref_C, ref_st = orc.wilson_loop_grid(g)
+    for i in range(2):
+        assert phase_set_error(th[i].cpu().numpy(), ref_th[i]) < 1e-10
+    assert (int(st[0]) & orc.OVERLAP_SINGULAR) == (ref_st & orc.OVERLAP_SINGULAR)

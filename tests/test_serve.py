@@ -1,4 +1,7 @@
-"""Serving loop: admission, continuous batching and latency accounting (CPU, fake executor)."""
+"""Serving loop: admission, continuous batching, lanes and latency accounting
+(CPU, simulated executor)."""
+import threading
+
 import numpy as np
 import pytest
 
@@ -13,18 +16,19 @@ def req(L, n=4, kind=S.KIND_WILSON, lo=None):
     return S.Request(hoplist=hl, kappa=kg, lo=0 if lo is None else lo, hi=m, kind=kind)
 
 
-def test_footprint_counts_resident_vectors_and_h_chunk():
+def test_resident_bytes_counts_vectors_values_and_status():
     r = req(2, 4)
     N, m, nk = r.N, r.m, r.n_k
-    fp = S.footprint_bytes(r, chunk_k=8)
-    assert fp == nk * (N * m * 16 + (m + 2) * 8 + 4) + 8 * N * N * 16
+    assert S.resident_bytes(r) == nk * (N * m * 16 + (m + 2) * 8 + 4)
+    ex = S.FakeExecutor(sleep=False, chunk_k=8)
+    assert ex.footprint(r) == S.resident_bytes(r) + 8 * N * N * 16
 
 
 def test_admission_respects_budget_and_all_complete():
-    ex = S.FakeExecutor(sleep=False)
+    ex = S.FakeExecutor(sleep=False, chunk_k=16)
     reqs = [req(2, 4) for _ in range(5)]
-    fp = S.footprint_bytes(reqs[0], 16)
-    eng = S.Engine(ex, hbm_budget=int(2.5 * fp), chunk_k=16)
+    fp = ex.footprint(reqs[0])
+    eng = S.Engine(ex, hbm_budget=int(2.5 * fp))
     for r in reqs:
         eng.submit(r)
     eng.run_until_idle()
@@ -34,8 +38,8 @@ def test_admission_respects_budget_and_all_complete():
 
 
 def test_continuous_batching_mixes_compatible_requests():
-    ex = S.FakeExecutor(sleep=False)
-    eng = S.Engine(ex, hbm_budget=1 << 40, chunk_k=10)
+    ex = S.FakeExecutor(sleep=False, chunk_k=10)
+    eng = S.Engine(ex, hbm_budget=1 << 40)
     a = eng.submit(req(2, 4))          # 16 k-points
     eng.step()                         # a alone: 10 k-points
     b = eng.submit(req(2, 4))          # arrives while a is in flight
@@ -48,8 +52,8 @@ def test_continuous_batching_mixes_compatible_requests():
 
 
 def test_incompatible_requests_never_share_a_launch():
-    ex = S.FakeExecutor(sleep=False)
-    eng = S.Engine(ex, hbm_budget=1 << 40, chunk_k=64)
+    ex = S.FakeExecutor(sleep=False, chunk_k=64)
+    eng = S.Engine(ex, hbm_budget=1 << 40)
     for L in (2, 3, 2, 1, 3):
         eng.submit(req(L, 4))
     eng.run_until_idle()   # FakeExecutor asserts one (N, bands, precision) per launch
@@ -63,11 +67,39 @@ def test_oversized_request_rejected():
 
 
 def test_poisson_stream_latencies():
-    ex = S.FakeExecutor(flops_per_s=5e10, sleep=True)
+    ex = S.FakeExecutor(flops_per_s=5e10, sleep=True, chunk_k=16)
     reqs = [req(L, 4) for L in (1, 2, 2, 1, 2, 1)]
-    eng = S.Engine(ex, hbm_budget=1 << 40, chunk_k=16)
+    eng = S.Engine(ex, hbm_budget=1 << 40)
     t = S.drive(eng, reqs, S.poisson_arrivals(200.0, len(reqs), [5, 0]))
     st = S.latency_stats(reqs)
     assert st["n"] == 6 and 0 < st["p50_ms"] <= st["p99_ms"]
     assert all(r.t_done >= r.t_admit >= r.t_submit for r in reqs)
     assert t > 0
+
+
+def test_two_lanes_overlap_different_sizes_never_one_key_twice():
+    """Two lanes: launches of different sizes run at the same time, one size
+    never on both lanes at once (the executor asserts it), and every request
+    completes with its k-points processed in order, once."""
+    ex = S.FakeExecutor(flops_per_s=2e9, sleep=True, n_lanes=2, chunk_k=4)
+    reqs = [req(L, 4) for L in (3, 1, 3, 2, 1, 3, 2, 1)]
+    eng = S.Engine(ex, hbm_budget=1 << 40)
+    S.drive(eng, reqs, np.zeros(len(reqs)))
+    assert all(r.done.is_set() and r.error is None for r in reqs)
+    assert ex.overlaps > 0
+    lanes = {c[3] for c in ex.calls if c[0] == "eig"}
+    assert lanes == {0, 1}
+    assert ex.live == 0 and eng.used == 0
+
+
+def test_executor_error_is_reported_on_the_request():
+    class Failing(S.FakeExecutor):
+        def run_eig(self, parts, lane):
+            raise RuntimeError("launch failed")
+
+    ex = Failing(sleep=False)
+    eng = S.Engine(ex, hbm_budget=1 << 40)
+    r = eng.submit(req(2, 4))
+    eng.run_until_idle()
+    assert r.done.is_set() and isinstance(r.error, RuntimeError) and r.result is None
+    assert ex.live == 0 and eng.used == 0
