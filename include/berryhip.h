@@ -171,14 +171,16 @@ int be_build_hk(be_ctx *ctx, const be_hk_plan *plan, int32_t sys_first, int32_t 
  * projector U U^H agrees with the FP64 path's to about 1e-12 where the
  * window is separated from the other bands by a gap well above 1e-6 ||H||;
  * single columns inside the window are eigenvectors to the FP32 path's
- * accuracy only, and the eigenvalues are within about 1e-9 ||H||
- * (eigenvalues lo-1 and hi: the FP32 path's). Workspace per matrix: about
+ * accuracy only; the eigenvalues are Rayleigh quotients of those columns,
+ * second order in their error (typically within 1e-12 ||H||, but a pair of
+ * nearly equal eigenvalues inside the window can keep the FP32 path's error,
+ * ~1e-7 ||H||; eigenvalues lo-1 and hi: the FP32 path's). Workspace per matrix: about
  * 40 N^2 + 32 N m + 32 (N - m) m bytes besides the mixed path's for m = N.
  * Steps: blocked Householder reduction to real tridiagonal form (panel
  * kernel whose matrix-vector products read the lower triangle once per
  * column + MFMA rank-2k trailing updates of the lower triangle), FP64 bisection for eigenvalues
  * [lo-1, hi], FP64 inverse iteration for bands [lo, hi) (Cholesky QR inside
- * clusters of eigenvalues equal within 64 eps ||T||), FP64 Newton-Schulz
+ * clusters of eigenvalues closer than 1e-12 ||T||), FP64 Newton-Schulz
  * orthonormalization of the tridiagonal eigenvectors, back-transformation
  * with compact-WY blocks on MFMA (FP32 on the mixed path).
  * Outputs:

@@ -625,7 +625,14 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
 }
 
 // Tolerances relative to ||T||: split < block window < cluster gap, so a
-// cluster's window never reaches the next cluster (clu_rel = 64 eps).
+// cluster's window never reaches the next cluster. Eigenvalues closer than
+// the cluster tolerance (clu_rel = 1e-12) form a cluster, whose vectors are
+// computed as one invariant subspace (any orthonormal basis of it): inverse
+// iteration separates two eigenvalues only to about eps ||T|| / gap, so
+// below that gap their vectors can come out nearly parallel (a cluster of
+// eigenvalues spread over 1e-12 ||T|| - e.g. the projected spin operator's
+// +-1 clusters computed from refined eigenvectors - would otherwise leave
+// an orthonormalization that cannot converge).
 __device__ __forceinline__ double tol_split(double tnorm) { return 16.0 * DBL_EPSILON * tnorm; }
 __device__ __forceinline__ double tol_window(double tnorm, double clu_rel) { return 0.5 * clu_rel * tnorm; }
 __device__ __forceinline__ double tol_cluster(double tnorm, double clu_rel) { return clu_rel * tnorm; }
@@ -1550,7 +1557,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     }
   }
   // ---- tridiagonal eigenpairs: bisection, inverse iteration, Gram-Schmidt of shared-block clusters
-  const double clu_rel = 64.0 * DBL_EPSILON;
+  const double clu_rel = 1e-12;
   {
     const size_t smb = (4 * size_t(N) + m + 4) * sizeof(double);
     if (smb > 65536)

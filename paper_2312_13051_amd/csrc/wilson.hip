@@ -462,12 +462,30 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
     for (int r = k + 1 + tid; r < m; r += NT) at(r, k) = r == k + 1 ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
     if (tau.x != 0.0 || tau.y != 0.0) {
       const double2 ctau = be::cconj(tau);
-      // left: rows k+1..m-1, threads over columns k+1..m-1
+      // left: rows k+1..m-1, threads over columns k+1..m-1. Loads are issued
+      // HB at a time ahead of their use (the stores of a column's update would
+      // otherwise keep each next load waiting: the compiler cannot tell the
+      // rows apart)
+      constexpr int HB = 8;
       for (int c = k + 1 + tid; c < m; c += NT) {
         double2 sacc = make_double2(0.0, 0.0);
-        for (int r = k + 1; r < m; ++r) sacc = be::cadd(sacc, be::cmulc(sv[r], at(r, c)));
+        for (int r0 = k + 1; r0 < m; r0 += HB) {
+          double2 a[HB];
+#pragma unroll
+          for (int u = 0; u < HB; ++u) a[u] = r0 + u < m ? at(r0 + u, c) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < HB; ++u)
+            if (r0 + u < m) sacc = be::cadd(sacc, be::cmulc(sv[r0 + u], a[u]));
+        }
         const double2 f = be::cmul(ctau, sacc);
-        for (int r = k + 1; r < m; ++r) at(r, c) = be::csub(at(r, c), be::cmul(sv[r], f));
+        for (int r0 = k + 1; r0 < m; r0 += HB) {
+          double2 a[HB];
+#pragma unroll
+          for (int u = 0; u < HB; ++u) a[u] = r0 + u < m ? at(r0 + u, c) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < HB; ++u)
+            if (r0 + u < m) at(r0 + u, c) = be::csub(a[u], be::cmul(sv[r0 + u], f));
+        }
       }
       __syncthreads();
       // right: every row, columns k+1..m-1: a wave per row, lanes over columns
@@ -483,7 +501,14 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
           si += __shfl_xor(si, o, 64);
         }
         const double2 f = be::cmul(tau, make_double2(sr, si));
-        for (int c = k + 1 + lane; c < m; c += 64) at(i, c) = be::csub(at(i, c), be::cmul(f, be::cconj(sv[c])));
+        for (int c0 = k + 1 + lane; c0 < m; c0 += 64 * 4) {
+          double2 a[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[u] = c0 + 64 * u < m ? at(i, c0 + 64 * u) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c0 + 64 * u < m) at(i, c0 + 64 * u) = be::csub(a[u], be::cmul(f, be::cconj(sv[c0 + 64 * u])));
+        }
       }
     }
     __syncthreads();
@@ -600,25 +625,43 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
         const int r = rb + e / nb, c = rb + e % nb;
         at(r, c) = B(r, c);
       }
-      // rows k0..ke right of the window: each thread a column, the rotations in order
+      // rows k0..ke right of the window: each thread a column, the rotations
+      // in order, the column's entries loaded RB at a time ahead of their use
+      constexpr int RB = 8;
       for (int c = k1 + 1 + tid; c <= ihi; c += NT) {
         double2 x = at(k0, c);
-        for (int k = k0; k < ke; ++k) {
-          const double cr = rot_c[k - k0];
-          const double2 sn = rot_s[k - k0], y = at(k + 1, c);
-          at(k, c) = be::cadd(be::cscale(x, cr), be::cmul(sn, y));
-          x = be::csub(be::cscale(y, cr), be::cmul(be::cconj(sn), x));
+        for (int kb = k0; kb < ke; kb += RB) {
+          double2 y[RB];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) y[u] = kb + u < ke ? at(kb + u + 1, c) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            if (kb + u < ke) {
+              const double cr = rot_c[kb + u - k0];
+              const double2 sn = rot_s[kb + u - k0];
+              at(kb + u, c) = be::cadd(be::cscale(x, cr), be::cmul(sn, y[u]));
+              x = be::csub(be::cscale(y[u], cr), be::cmul(be::cconj(sn), x));
+            }
+          }
         }
         at(ke, c) = x;
       }
       // columns k0..ke above the window: each thread a row
       for (int r = l + tid; r < rb; r += NT) {
         double2 x = at(r, k0);
-        for (int k = k0; k < ke; ++k) {
-          const double cr = rot_c[k - k0];
-          const double2 sn = rot_s[k - k0], y = at(r, k + 1);
-          at(r, k) = be::cadd(be::cscale(x, cr), be::cmul(be::cconj(sn), y));
-          x = be::csub(be::cscale(y, cr), be::cmul(sn, x));
+        for (int kb = k0; kb < ke; kb += RB) {
+          double2 y[RB];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) y[u] = kb + u < ke ? at(r, kb + u + 1) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            if (kb + u < ke) {
+              const double cr = rot_c[kb + u - k0];
+              const double2 sn = rot_s[kb + u - k0];
+              at(r, kb + u) = be::cadd(be::cscale(x, cr), be::cmul(be::cconj(sn), y[u]));
+              x = be::csub(be::cscale(y[u], cr), be::cmul(sn, x));
+            }
+          }
         }
         at(r, ke) = x;
       }
