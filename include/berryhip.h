@@ -345,6 +345,17 @@ int be_profile_names(be_ctx *ctx, char *buf, size_t len);
 int be_tune_set(be_ctx *ctx, const char *knob, int32_t value);
 int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value);
 
+/* Per-order settings of a knob, as an autotuner writes them: value applies to
+ * matrices of order N in [n_lo, n_hi] on the paths of `precision` (BE_FP64:
+ * the FP64 reduction; BE_MIXED_FP32 or BE_MIXED_FP32_REFINED: the FP32
+ * reduction; -1: both); settings made later take precedence over earlier
+ * ones, and be_tune_set's value applies where none matches. be_tune_clear
+ * drops a knob's per-order settings and restores its default.
+ * (The package's tune.py measures these settings on the device and stores
+ * them as JSON; Context.load_tuning applies a stored table.) */
+int be_tune_set_orders(be_ctx *ctx, const char *knob, int32_t n_lo, int32_t n_hi, int32_t precision, int32_t value);
+int be_tune_clear(be_ctx *ctx, const char *knob);
+
 /* Utility kernel exposed for tests: batched complex GEMM on MFMA,
  *   C_q = alpha op(A_q) op(B_q) + beta C_q,   op = 'N' (none) or 'C'
  * (conjugate transpose), c128, strided batches (element strides). */

@@ -30,6 +30,7 @@ EXPORTS = [
     "be_spin_resolved_wilson", "be_plaquette_flux", "be_plaquette_flux_noalloc", "be_spin_sectors",
     "be_zgemm_strided",
     "be_profile_enable", "be_profile_query", "be_profile_names", "be_tune_set", "be_tune_get",
+    "be_tune_set_orders", "be_tune_clear",
 ]
 
 
@@ -82,6 +83,8 @@ def load():
     lib.be_profile_names.argtypes = [vp, C.c_char_p, C.c_size_t]
     lib.be_tune_set.argtypes = [vp, C.c_char_p, i32]
     lib.be_tune_get.argtypes = [vp, C.c_char_p, C.POINTER(i32)]
+    lib.be_tune_set_orders.argtypes = [vp, C.c_char_p, i32, i32, i32, i32]
+    lib.be_tune_clear.argtypes = [vp, C.c_char_p]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
             "be_last_error", "be_workspace_bytes", "be_hk_plan_N") else C.c_int
@@ -218,6 +221,27 @@ class Context:
         v = C.c_int32()
         self._check(self.lib.be_tune_get(self.handle, knob.encode(), C.byref(v)))
         return v.value
+
+    def tune_set_orders(self, knob: str, n_lo: int, n_hi: int, precision: int, value: int):
+        self._check(self.lib.be_tune_set_orders(self.handle, knob.encode(), int(n_lo), int(n_hi), int(precision),
+                                                int(value)))
+
+    def tune_clear(self, knob: str):
+        self._check(self.lib.be_tune_clear(self.handle, knob.encode()))
+
+    def load_tuning(self, table):
+        """Apply a tuning table (a dict, or the path of its JSON file, as
+        tune.py writes it): {"knobs": {knob: [{"n_lo", "n_hi", "precision",
+        "value"}, ...]}}. Returns the table."""
+        if isinstance(table, (str, os.PathLike)):
+            import json
+            with open(table) as f:
+                table = json.load(f)
+        for knob, rows in table.get("knobs", {}).items():
+            self.tune_clear(knob)
+            for r in rows:
+                self.tune_set_orders(knob, r["n_lo"], r["n_hi"], r["precision"], r["value"])
+        return table
 
     def profile_enable(self, on=True):
         self._check(self.lib.be_profile_enable(self.handle, 1 if on else 0))

@@ -17,7 +17,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Workspace slots: each pipeline stage carves its scratch from its own slot,
 // so a stage may call another stage without their scratch overlapping.
-enum { WS_EIGH = 0, WS_WILSON = 1, WS_OUTER = 2, WS_MISC = 3, WS_SLOTS = 4 };
+enum { WS_EIGH = 0, WS_WILSON = 1, WS_OUTER = 2, WS_MISC = 3, WS_UNIT = 4, WS_SLOTS = 5 };
 
 // Per-name launch timer: hipEvent pairs recorded around launches while
 // profiling is on; resolved (synchronously) when queried.
@@ -32,17 +32,32 @@ struct be_ctx {
   bool prof_on = false;
   std::map<std::string, ProfEntry> prof;
   std::vector<hipEvent_t> event_pool;
-  void *ws[WS_SLOTS] = {nullptr, nullptr, nullptr, nullptr};  // device workspaces (grow on demand)
-  size_t ws_bytes[WS_SLOTS] = {0, 0, 0, 0};
+  void *ws[WS_SLOTS] = {};  // device workspaces (grow on demand)
+  size_t ws_bytes[WS_SLOTS] = {};
   void *pinned = nullptr;  // small pinned host buffer for scalar read-backs
   std::string err;
   int n_cu = 256;
-  // tuning knobs (be_tune_set)
+  // tuning knobs (be_tune_set, be_tune_set_orders)
   int tune_panel_threads = 512;   // threads per matrix of the Householder panel kernel
+  struct TuneRange {
+    int n_lo, n_hi;  // orders N in [n_lo, n_hi]
+    int elem;        // bytes per element of the reduction (8: mixed paths, 16: FP64), 0: both
+    int value;
+  };
+  std::vector<TuneRange> tune_panel_ranges;  // per-order panel thread counts (last match wins)
   std::string prof_scope;         // prefix of launch-timer names (nested calls)
 };
 
 namespace be {
+
+// Threads per matrix of the Householder panel kernel for order N and element
+// size elem (bytes): the last matching per-order setting, else the default.
+inline int panel_threads(const be_ctx *ctx, int N, size_t elem) {
+  int v = ctx->tune_panel_threads;
+  for (const auto &r : ctx->tune_panel_ranges)
+    if (N >= r.n_lo && N <= r.n_hi && (r.elem == 0 || size_t(r.elem) == elem)) v = r.value;
+  return v;
+}
 
 // ---------------------------------------------------------------- errors
 int set_err(be_ctx *ctx, int code, const std::string &msg);
@@ -274,7 +289,8 @@ int noalloc_scratch_init(be_ctx *ctx, int device);
 // or mixed (c64 input, FP32 reduction and back-transformation, FP64
 // tridiagonal solve and orthonormalization, c128 eigenvectors out).
 int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
-              double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
+              double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream,
+              double clu_rel = 1e-12);
 int eigh_mixed(be_ctx *ctx, float2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
                double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
 

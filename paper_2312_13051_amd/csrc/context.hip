@@ -165,6 +165,33 @@ int be_tune_set(be_ctx *ctx, const char *knob, int32_t value) {
   return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
 }
 
+int be_tune_set_orders(be_ctx *ctx, const char *knob, int32_t n_lo, int32_t n_hi, int32_t precision, int32_t value) {
+  if (!ctx || !knob) return BE_EINVAL;
+  const std::string k(knob);
+  if (k == "hetrd_panel_threads") {
+    BE_CHECK_ARG(ctx, value == 256 || value == 512 || value == 1024, "hetrd_panel_threads takes 256, 512 or 1024");
+    BE_CHECK_ARG(ctx, 1 <= n_lo && n_lo <= n_hi, "be_tune_set_orders: need 1 <= n_lo <= n_hi");
+    BE_CHECK_ARG(ctx, precision == -1 || precision == BE_FP64 || precision == BE_MIXED_FP32 ||
+                          precision == BE_MIXED_FP32_REFINED,
+                 "be_tune_set_orders: precision must be -1, BE_FP64, BE_MIXED_FP32 or BE_MIXED_FP32_REFINED");
+    const int elem = precision == -1 ? 0 : precision == BE_FP64 ? 16 : 8;
+    ctx->tune_panel_ranges.push_back({n_lo, n_hi, elem, value});
+    return BE_OK;
+  }
+  return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
+}
+
+int be_tune_clear(be_ctx *ctx, const char *knob) {
+  if (!ctx || !knob) return BE_EINVAL;
+  const std::string k(knob);
+  if (k == "hetrd_panel_threads") {
+    ctx->tune_panel_ranges.clear();
+    ctx->tune_panel_threads = 512;
+    return BE_OK;
+  }
+  return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
+}
+
 int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value) {
   if (!ctx || !knob || !value) return BE_EINVAL;
   const std::string k(knob);

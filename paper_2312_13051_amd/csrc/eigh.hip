@@ -626,13 +626,17 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
 
 // Tolerances relative to ||T||: split < block window < cluster gap, so a
 // cluster's window never reaches the next cluster. Eigenvalues closer than
-// the cluster tolerance (clu_rel = 1e-12) form a cluster, whose vectors are
+// the cluster tolerance (clu_rel, by default kCluRel = 1e-12) form a cluster, whose vectors are
 // computed as one invariant subspace (any orthonormal basis of it): inverse
 // iteration separates two eigenvalues only to about eps ||T|| / gap, so
 // below that gap their vectors can come out nearly parallel (a cluster of
 // eigenvalues spread over 1e-12 ||T|| - e.g. the projected spin operator's
-// +-1 clusters computed from refined eigenvectors - would otherwise leave
-// an orthonormalization that cannot converge).
+// +-1 clusters computed from refined eigenvectors, whose T splits into many
+// blocks - would otherwise have lanes pick blocks by windows narrower than
+// the cluster, and leave an orthonormalization that cannot converge). A
+// caller that needs the vectors of nearly equal eigenvalues resolved one by
+// one (and validates them) may pass a smaller tolerance.
+constexpr double kCluRel = 1e-12;
 __device__ __forceinline__ double tol_split(double tnorm) { return 16.0 * DBL_EPSILON * tnorm; }
 __device__ __forceinline__ double tol_window(double tnorm, double clu_rel) { return 0.5 * clu_rel * tnorm; }
 __device__ __forceinline__ double tol_cluster(double tnorm, double clu_rel) { return clu_rel * tnorm; }
@@ -1470,7 +1474,8 @@ struct GemmOf<float> {
 // Hin: nb_mat matrices of CT<T>::c; U: c128 output.
 template <typename T>
 static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ms, int64_t nb_mat, int lo, int hi,
-                      double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream) {
+                      double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream,
+                      double clu_rel = kCluRel) {
   typedef typename CT<T>::c C;
   typedef typename GemmOf<T>::type G;
   const int m = hi - lo;
@@ -1506,7 +1511,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   if (mixed) cv.add(&Uw, size_t(nb_mat) * N * std::max(m, 1));
   // panel kernel: 256, 512 or 1024 threads per matrix; partial vectors of its
   // matrix-vector product in LDS or in global scratch
-  const int pnt = ctx->tune_panel_threads;
+  const int pnt = panel_threads(ctx, N, sizeof(C));
   const bool pl = panel_part_lds(N, sizeof(C), pnt);
   const size_t psm = panel_lds(N, sizeof(C), pnt);
   const int64_t sPg = pl ? 0 : int64_t(panel_part_bytes(N - 1, 1));
@@ -1557,7 +1562,6 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     }
   }
   // ---- tridiagonal eigenpairs: bisection, inverse iteration, Gram-Schmidt of shared-block clusters
-  const double clu_rel = 1e-12;
   {
     const size_t smb = (4 * size_t(N) + m + 4) * sizeof(double);
     if (smb > 65536)
@@ -1756,7 +1760,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
 template <typename T>
 static int64_t panel_slots(be_ctx *ctx, int N) {
   typedef typename CT<T>::c C;
-  const int pnt = ctx->tune_panel_threads;
+  const int pnt = panel_threads(ctx, N, sizeof(C));
   const size_t psm = panel_lds(N, sizeof(C), pnt);
   PanelFn<T> panel = panel_kernel<T>(pnt, panel_part_lds(N, sizeof(C), pnt));
   int per_cu = 0;
@@ -1773,7 +1777,7 @@ static int64_t panel_slots(be_ctx *ctx, int N) {
 
 // The panel vectors and the tridiagonal solver's arrays live in LDS.
 static int check_eigh_lds(be_ctx *ctx, int N, int m, size_t cs) {
-  const size_t lds_need = std::max({panel_lds(N, cs, ctx->tune_panel_threads), (4 * size_t(N) + m + 4) * sizeof(double),
+  const size_t lds_need = std::max({panel_lds(N, cs, panel_threads(ctx, N, cs)), (4 * size_t(N) + m + 4) * sizeof(double),
                                     (3 * size_t(N) + m) * sizeof(double) + (size_t(N) + 1 + 2 * size_t(m)) * sizeof(int),
                                     gs_smem(m)});
   BE_CHECK_ARG(ctx, lds_need <= 160 * 1024, "be_eigh_batched: order too large for the LDS-resident kernels");
@@ -1788,7 +1792,7 @@ static size_t eigh_chunk_bytes(be_ctx *ctx, int N, int m) {
   const size_t cs = sizeof(typename CT<T>::c);
   return cs * (size_t(N) * 3 * NB + size_t(P) * NB * NB + 4 * size_t(NB) * std::max(m, 1) + 6 * size_t(NB) * NB +
                size_t(N) * std::max(m, 1)) +
-         (panel_part_lds(N, cs, ctx->tune_panel_threads) ? 0 : panel_part_bytes(N - 1, cs)) +
+         (panel_part_lds(N, cs, panel_threads(ctx, N, cs)) ? 0 : panel_part_bytes(N - 1, cs)) +
          sizeof(double) * (3 * size_t(N) + 4 * size_t(N) * mp + size_t(std::max(m, 1)) * std::max(m, 1) + size_t(m) +
                            1) +
          sizeof(int) * size_t(std::max(m, 1)) + 16 * 256;
@@ -1824,7 +1828,7 @@ static int64_t eigh_sub_batch(be_ctx *ctx, int N, size_t per, size_t reusable, i
 template <typename T>
 static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo,
                     int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
-                    hipStream_t stream) {
+                    hipStream_t stream, double clu_rel = kCluRel) {
   const int m = band_hi - band_lo;
   BE_RET_IF(check_eigh_lds(ctx, N, m, sizeof(typename CT<T>::c)));
   if (n_mat == 0) return BE_OK;
@@ -1833,7 +1837,7 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
     BE_RET_IF(eigh_chunk<T>(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo, band_hi, evals + b0 * (m + 2),
-                            U + b0 * u_stride, ldu, u_stride, status + b0, stream));
+                            U + b0 * u_stride, ldu, u_stride, status + b0, stream, clu_rel));
   }
   return BE_OK;
 }
@@ -2018,8 +2022,9 @@ static int eigh_refined(be_ctx *ctx, const double2 *H, int N, int ld, int64_t ms
 }
 
 int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
-              double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream) {
-  return eigh_run<double>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream);
+              double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream,
+              double clu_rel) {
+  return eigh_run<double>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream, clu_rel);
 }
 
 int eigh_mixed(be_ctx *ctx, float2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,

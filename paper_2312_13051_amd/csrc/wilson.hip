@@ -181,11 +181,11 @@ __global__ void k_carry_last(const double2 *src, int n_src, double2 *dst, int n_
 template <bool INLDS>
 __global__ __launch_bounds__(64) void k_unitary_eig(const double2 *W, int m, int64_t n_mat, double2 *Hs,
                                                     double2 *Zs, double *theta_sorted, int ldt, double *theta_raw,
-                                                    uint32_t *flags, int flag_div) {
+                                                    uint32_t *flags, int flag_div, const int *act) {
   extern __shared__ double2 sv[];  // Householder vector (m), eigenvalues (m), [INLDS: the matrix (m x m)]
   double2 *slam = sv + m;
   const int64_t q = blockIdx.x;
-  if (q >= n_mat) return;
+  if (q >= n_mat || (act && act[q] == 0)) return;
   const int lane = threadIdx.x;
   const double2 *Wq = W + q * int64_t(m) * m;
   double2 *H = INLDS ? slam + m : Hs + q * int64_t(m) * m;
@@ -400,7 +400,7 @@ constexpr int kUnitaryWgLds = QW * QLD;  // double2 entries of the window
 template <int NT>
 __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, int64_t n_mat, double2 *Hs,
                                                        double *theta_sorted, int ldt, double *theta_raw,
-                                                       uint32_t *flags, int flag_div) {
+                                                       uint32_t *flags, int flag_div, const int *act) {
   // Householder vector (m) during the reduction, the QR window (QW x QLD)
   // afterwards; then the eigenvalues (m)
   extern __shared__ double2 sv[];
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
   __shared__ double red[NT / 64];
   __shared__ int redi[NT / 64];
   const int64_t q = blockIdx.x;
-  if (q >= n_mat) return;
+  if (q >= n_mat || (act && act[q] == 0)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NT / 64;
   const double2 *Wq = W + q * int64_t(m) * m;
   double2 *H = Hs + q * int64_t(m) * m;  // row-major: H[r * m + c]
@@ -692,6 +692,114 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
   if (failed && tid == 0) atomicOr(&flags[q / flag_div], BE_ST_NONCONVERGED);
 }
 
+// ---- eigenphases of large unitary matrices through a Hermitian eigenproblem.
+// A = (e^{-i phi} W + e^{i phi} W^H) / 2 is Hermitian, has W's eigenvectors and
+// the eigenvalues cos(theta - phi); for an eigenvector v, sin(theta - phi) =
+// Im(e^{-i phi} v^H W v). The shift phi keeps pairs theta, -theta (frequent in
+// Wilson loops of symmetric models) apart in A's spectrum. Eigenvalues of W
+// that still share a cosine (theta_a + theta_b = 2 phi) leave eigenvectors of
+// A that are not W's; they show in the residual |W v - e^{i theta} v|, and
+// such matrices are handed to the QR kernels.
+constexpr double kHermShift = 0.6180339887498949;
+
+// Lower triangle and diagonal of A from W (both column-major m x m), by
+// 32 x 32 tile pairs: tile (bj, bi) of W is staged in LDS so that W(c, r) is
+// read coalesced for the lower tile (bi, bj).
+__global__ __launch_bounds__(256) void k_herm_of_unitary(const double2 *W, int m, int64_t n_mat, double2 *A) {
+  __shared__ double2 t[32][33];  // t[col - 32 bi][row - 32 bj] = W(row, col) of tile (bj, bi)
+  const int nt = (m + 31) / 32;
+  int p = blockIdx.x, bj = 0;
+  while (p >= nt - bj) {
+    p -= nt - bj;
+    ++bj;
+  }
+  const int bi = bj + p;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double cs = cos(kHermShift), sn = sin(kHermShift);
+  const int64_t mm = int64_t(m) * m;
+  for (int64_t q = blockIdx.y; q < n_mat; q += gridDim.y) {
+    const double2 *Wq = W + q * mm;
+    double2 *Aq = A + q * mm;
+    __syncthreads();
+    for (int c = ty; c < 32; c += 8) {
+      const int row = bj * 32 + tx, col = bi * 32 + c;
+      t[c][tx] = (row < m && col < m) ? Wq[row + int64_t(col) * m] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int c = ty; c < 32; c += 8) {
+      const int r = bi * 32 + tx, cc = bj * 32 + c;
+      if (r >= m || cc >= m || r < cc) continue;
+      const double2 a = Wq[r + int64_t(cc) * m], b = t[tx][c];  // W(r, cc), W(cc, r)
+      // (e^{-i phi} a + e^{i phi} conj(b)) / 2
+      double2 v = make_double2(0.5 * (cs * a.x + sn * a.y + cs * b.x + sn * b.y),
+                               0.5 * (cs * a.y - sn * a.x - cs * b.y + sn * b.x));
+      if (r == cc) v.y = 0.0;
+      Aq[r + int64_t(cc) * m] = v;
+    }
+  }
+}
+
+// Phases from the eigenpairs of A: theta_n = phi + atan2(s_n, c_n), c_n the
+// eigenvalue, s_n = Im(e^{-i phi} v_n^H (W v_n)); residual check; ascending
+// sort; optional raw phases and eigenvectors. One workgroup per matrix, a
+// wave per column. fb[q] = 1 where the QR kernel must take over.
+__global__ __launch_bounds__(256) void k_herm_phases(const double *ev, const uint32_t *est, const double2 *V,
+                                                     const double2 *WV, int m, int64_t n_mat, double *theta_sorted,
+                                                     int ldt, double *theta_raw, double2 *Zout, int *fb) {
+  extern __shared__ double sth[];  // m phases
+  __shared__ int s_bad;
+  const int64_t q = blockIdx.x;
+  if (q >= n_mat) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t mm = int64_t(m) * m;
+  const double2 *Vq = V + q * mm, *Gq = WV + q * mm;
+  const double cs = cos(kHermShift), sn = sin(kHermShift);
+  if (tid == 0) s_bad = (est[q] != 0) ? 1 : 0;
+  __syncthreads();
+  for (int n = wave; n < m; n += 4) {
+    const double2 *v = Vq + int64_t(n) * m, *g = Gq + int64_t(n) * m;
+    double pr = 0.0, pi = 0.0;
+    for (int r = lane; r < m; r += 64) {
+      const double2 a = v[r], b = g[r];
+      pr += a.x * b.x + a.y * b.y;
+      pi += a.x * b.y - a.y * b.x;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      pr += __shfl_xor(pr, o, 64);
+      pi += __shfl_xor(pi, o, 64);
+    }
+    const double s = cs * pi - sn * pr;  // Im(e^{-i phi} p)
+    double th = kHermShift + atan2(s, ev[q * (m + 2) + 1 + n]);
+    if (th > M_PI) th -= 2.0 * M_PI;
+    const double er = cos(th), ei = sin(th);
+    double res = 0.0;
+    for (int r = lane; r < m; r += 64) {
+      const double2 a = v[r], b = g[r];
+      const double dx = b.x - (er * a.x - ei * a.y), dy = b.y - (er * a.y + ei * a.x);
+      res += dx * dx + dy * dy;
+    }
+    for (int o = 32; o > 0; o >>= 1) res += __shfl_xor(res, o, 64);
+    if (lane == 0) {
+      sth[n] = th;
+      if (!(res <= 1e-20)) s_bad = 1;  // |W v - e^{i theta} v| > 1e-10, or NaN
+    }
+  }
+  __syncthreads();
+  for (int n = tid; n < m; n += 256) {
+    const double th = sth[n];
+    if (theta_raw) theta_raw[q * m + n] = th;
+    int rank = 0;
+    for (int k = 0; k < m; ++k) {
+      const double tk = sth[k];
+      rank += (tk < th) || (tk == th && k < n);
+    }
+    theta_sorted[q * int64_t(ldt) + rank] = th;
+  }
+  if (Zout)
+    for (int64_t k = tid; k < mm; k += 256) Zout[q * mm + k] = Vq[k];
+  if (tid == 0) fb[q] = s_bad;
+}
+
 // Chern winding of each system from theta [line][ldt] (first m valid).
 __global__ void k_winding(const double *theta, int ldt, int m, int n_sys, int n_perp, double *phi, int32_t *winding,
                           uint32_t *status) {
@@ -911,29 +1019,92 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
 // n_lines m x m matrices (unused when the matrices fit LDS).
 static int unitary_phases(be_ctx *ctx, const double2 *cur, int m, int64_t n_lines, double2 *Hs, double2 *Zout,
                           double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream) {
-  // ---- eigenphases
+  ProfScope prof(ctx, "unitary_eig", stream);
   const size_t esm_lds = (size_t(m) * m + 2 * size_t(m)) * sizeof(double2);
   const bool inlds = Zout == nullptr && esm_lds <= 160 * 1024;
-  if (Zout == nullptr && !inlds) {  // large order: a workgroup per matrix, row-major scratch
-    const size_t esm = (size_t(std::max(m, kUnitaryWgLds)) + size_t(m)) * sizeof(double2);
-    BE_CHECK_ARG(ctx, esm <= 150 * 1024, "Wilson loop: order of the Wilson matrices too large for the eigenphase kernel");
+  if (inlds || m <= 32) {  // orders up to 100 (up to 32 with eigenvectors): one wave per matrix, QR
+    const size_t esm = inlds ? esm_lds : 2 * size_t(m) * sizeof(double2);
+    auto kern = inlds ? &k_unitary_eig<true> : &k_unitary_eig<false>;
     if (esm > 65536)
-      BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig_wg<256>),
+      BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
-    ProfScope prof(ctx, "unitary_eig", stream);
-    hipLaunchKernelGGL(k_unitary_eig_wg<256>, dim3(static_cast<uint32_t>(n_lines)), dim3(256), esm, stream, cur, m,
-                       n_lines, Hs, theta_sorted, ldt, theta_raw, line_status, 1);
+    hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs, Zout,
+                       theta_sorted, ldt, theta_raw, line_status, 1, nullptr);
     return check_launch(ctx, "unitary_eig");
   }
-  const size_t esm = inlds ? esm_lds : 2 * size_t(m) * sizeof(double2);
-  auto kern = inlds ? &k_unitary_eig<true> : &k_unitary_eig<false>;
-  if (esm > 65536)
-    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(esm)));
-  ProfScope prof(ctx, "unitary_eig", stream);
-  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs, Zout,
-                     theta_sorted, ldt, theta_raw, line_status, 1);
-  return check_launch(ctx, "unitary_eig");
+  // larger orders: the Hermitian eigenproblem of (e^{-i phi} W + e^{i phi} W^H) / 2
+  // (batched FP64 eigensolver, all bands), in chunks of lines within ~4 GiB;
+  // matrices it cannot resolve go to the QR kernels (a workgroup per matrix,
+  // or one wave with Schur vectors when eigenvectors are wanted)
+  const int64_t mm = int64_t(m) * m;
+  const int64_t per = 3 * mm * int64_t(sizeof(double2)) + (m + 2) * 8 + 4096;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(n_lines, (int64_t(4) << 30) / per));
+  double2 *A = nullptr, *V = nullptr, *WV = nullptr;
+  double *ev = nullptr;
+  uint32_t *est = nullptr;
+  int *fb = nullptr;
+  Carve cv;
+  cv.add(&A, size_t(cap * mm));
+  cv.add(&V, size_t(cap * mm));
+  cv.add(&WV, size_t(cap * mm));
+  cv.add(&ev, size_t(cap * (m + 2)));
+  cv.add(&est, size_t(cap));
+  cv.add(&fb, size_t(cap));
+  BE_RET_IF(cv.commit(ctx, stream, WS_UNIT));
+  const size_t esm_wg = (size_t(std::max(m, kUnitaryWgLds)) + size_t(m)) * sizeof(double2);
+  BE_CHECK_ARG(ctx, esm_wg <= 150 * 1024, "Wilson loop: order of the Wilson matrices too large for the eigenphase kernel");
+  if (esm_wg > 65536)
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig_wg<256>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(esm_wg)));
+  const size_t esm_1w = 2 * size_t(m) * sizeof(double2);
+  if (esm_1w > 65536)
+    BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&k_unitary_eig<false>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(esm_1w)));
+  const int nt = (m + 31) / 32;
+  for (int64_t l0 = 0; l0 < n_lines; l0 += cap) {
+    const int64_t nl = std::min<int64_t>(cap, n_lines - l0);
+    const double2 *Wc = cur + l0 * mm;
+    hipLaunchKernelGGL(k_herm_of_unitary, dim3(static_cast<uint32_t>(nt * (nt + 1) / 2),
+                                               static_cast<uint32_t>(std::min<int64_t>(nl, 65535))),
+                       dim3(256), 0, stream, Wc, m, nl, A);
+    BE_RET_IF(check_launch(ctx, "herm_of_unitary"));
+    const std::string scope = ctx->prof_scope;
+    ctx->prof_scope = scope + "unitary_";  // launch-timer names of the inner eigensolver
+    // clusters only at 64 eps: W's nearly equal phases (often hundreds within
+    // 1e-9 of each other) are then resolved one by one, each vector checked below
+    const int erc = eigh_fp64(ctx, A, m, m, mm, nl, 0, m, ev, V, m, mm, est, stream, 64.0 * DBL_EPSILON);
+    ctx->prof_scope = scope;
+    BE_RET_IF(erc);
+    ZGemm g;  // W V
+    g.M = m;
+    g.N = m;
+    g.K = m;
+    g.A = Wc;
+    g.lda = m;
+    g.bA = ZBatch::strided(mm);
+    g.B = V;
+    g.ldb = m;
+    g.bB = ZBatch::strided(mm);
+    g.C = WV;
+    g.ldc = m;
+    g.bC = ZBatch::strided(mm);
+    g.batch = nl;
+    g.tag = "unitary_wv";
+    BE_RET_IF(zgemm(ctx, g, stream));
+    double *ths = theta_sorted + l0 * ldt, *thr = theta_raw ? theta_raw + l0 * m : nullptr;
+    double2 *Zc = Zout ? Zout + l0 * mm : nullptr;
+    hipLaunchKernelGGL(k_herm_phases, dim3(static_cast<uint32_t>(nl)), dim3(256), size_t(m) * sizeof(double), stream, ev,
+                       est, V, WV, m, nl, ths, ldt, thr, Zc, fb);
+    BE_RET_IF(check_launch(ctx, "herm_phases"));
+    if (Zout)
+      hipLaunchKernelGGL(k_unitary_eig<false>, dim3(static_cast<uint32_t>(nl)), dim3(64), esm_1w, stream, Wc, m, nl,
+                         Hs + l0 * mm, Zc, ths, ldt, thr, line_status + l0, 1, fb);
+    else
+      hipLaunchKernelGGL(k_unitary_eig_wg<256>, dim3(static_cast<uint32_t>(nl)), dim3(256), esm_wg, stream, Wc, m, nl,
+                         Hs + l0 * mm, ths, ldt, thr, line_status + l0, 1, fb);
+    BE_RET_IF(check_launch(ctx, "unitary_eig"));
+  }
+  return BE_OK;
 }
 
 }  // namespace be

@@ -310,8 +310,11 @@ class GpuExecutor:
         # the eigensolver works in sub-batches of at most 48 GiB of workspace
         eig_ws = min(48 << 30, min(c, req.n_k) * (req.N * 96 * self._hb(req) + 4 * req.N * mp * 8 + req.N * m * 8
                                                   + m * m * 8))
-        loop_ws = min(6 << 30, req.n_k * 3 * m * m * 16) + req.n_k * req.N * m * 16 * (
-            1 if req.kind in (KIND_SPIN, KIND_SPIN_FLUX) else 0)
+        n_lines = req.n_k // max(1, req.kappa.shape[1]) if req.kappa.ndim == 3 else req.n_k
+        # overlap/polar/product buffers (passes of at most 4 GiB), the Wilson
+        # matrices' eigenproblems (at most 4 GiB, plus the eigensolver's own)
+        loop_ws = (min(6 << 30, req.n_k * 3 * m * m * 16) + min(6 << 30, n_lines * 5 * m * m * 16)
+                   + req.n_k * req.N * m * 16 * (1 if req.kind in (KIND_SPIN, KIND_SPIN_FLUX) else 0))
         return int(resident_bytes(req) + c * req.N * req.N * self._hb(req) + eig_ws + loop_ws)
 
     def _hbuf(self, req, stream):

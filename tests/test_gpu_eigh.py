@@ -363,3 +363,29 @@ def test_eigh_fuzzy_clusters(spread):
             P = Uq[:, :100] @ Uq[:, :100].conj().T
             Pref = Q[q][:, :100] @ Q[q][:, :100].conj().T
             assert np.max(np.abs(P - Pref)) < 1e-10
+
+
+def test_eigh_per_order_tuning():
+    """Per-order panel thread counts (as the autotuner stores them) select the
+    kernel variant by order and precision; results stay correct."""
+    gu.need_gpu()
+    c = gu.ctx()
+    try:
+        c.load_tuning({"knobs": {"hetrd_panel_threads": [
+            {"n_lo": 1, "n_hi": 100, "precision": -1, "value": 256},
+            {"n_lo": 101, "n_hi": 1000, "precision": 0, "value": 1024},
+            {"n_lo": 101, "n_hi": 1000, "precision": 1, "value": 256}]}})
+        for N, lo, hi in ((70, 10, 45), (129, 64, 129)):
+            rng = np.random.default_rng(N + 7)
+            A = rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))
+            Hs = A + np.conj(np.swapaxes(A, 1, 2))
+            ev, U, st = run_eigh(c, Hs, lo, hi)
+            check(Hs, lo, hi, ev, U, st)
+        hl = syn.bhz_disordered(6, 2.0, [3, 2, 9])
+        Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in syn.kplane(2, 1).reshape(-1, 3)])
+        ev, U, st = run_eigh_mixed(c, Hs, 0, hl.N // 2)
+        w, V = np.linalg.eigh(Hs[0])
+        P = U[0] @ U[0].conj().T
+        assert np.max(np.abs(P - V[:, :hl.N // 2] @ V[:, :hl.N // 2].conj().T)) < 1e-4
+    finally:
+        c.tune_clear("hetrd_panel_threads")

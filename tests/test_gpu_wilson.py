@@ -232,3 +232,39 @@ def test_wilson_large_order_random_bases(N, m, n_par):
     for i in range(2):
         assert phase_set_error(th[i].cpu().numpy(), ref_th[i]) < 1e-10
     assert (int(st[0]) & orc.OVERLAP_SINGULAR) == (ref_st & orc.OVERLAP_SINGULAR)
+
+
+def test_wilson_large_order_raw_mode_falls_back_to_qr():
+    """Raw overlaps (eq. 2 without polar factors) make W non-unitary: the
+    Hermitian route for large orders cannot represent it, sees the residual,
+    and hands every line to the QR kernel; phases against the oracle's."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    hl = syn.bhz_disordered(8, 2.0, [3, 8, 1])
+    kg = syn.kplane(16, 2)
+    m = hl.N // 2
+    out = P.wsurf(c, [hl], kg, 0, m, mode=1)
+    for i in range(2):
+        ev, U, st = orc.eigh_grid(hl, kg[i], 0, m)
+        W, _ = orc.wilson_matrix(U, "raw")
+        assert phase_set_error(out["theta"][0, i].cpu().numpy(), orc.eigphases(W)) < 1e-9
+
+
+def test_nested_large_sector_eigenvectors():
+    """Nested Wilson loop of a clean BBH 6x6 supercell (m = 72: the Wilson
+    matrices' eigenvectors come from the Hermitian route), against the
+    oracle."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    hl = syn.supercell(syn.bbh(0.5, 1.0), 6)
+    kg = syn.kplane(10, 8)
+    m = hl.N // 2
+    # the supercell's Wannier centres crowd at 0; the window takes the six
+    # bands between 0.07 and 0.25 (far from its edges on every line)
+    out = P.wnwl(c, [hl], kg, 0, m, window=(0.03, 0.3))
+    ref = orc.nested_wilson(hl, kg, 0, m, window=(0.03, 0.3))
+    assert ref["status"] == 0 and int(out["status"][0]) == 0
+    assert out["s"] == [ref["s"]]
+    assert phase_set_error(out["theta"][0, :, :ref["s"]].cpu().numpy(), ref["theta"]) < TOL
