@@ -247,6 +247,8 @@ def main():
                     help="served: arrival rate as a multiple of the one-request-at-a-time capacity")
     ap.add_argument("--lanes", type=int, default=2, help="served: GPU lanes (host threads with a stream each)")
     ap.add_argument("--hbm-gib", type=int, default=150, help="served: HBM budget of admitted requests (GiB)")
+    ap.add_argument("--graph-lanes", type=int, default=1,
+                    help="uneven: lanes (context + stream) of the captured graph's size groups")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: berryhip has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -312,9 +314,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = L.Context(0)
-    tuning = {}
+    tuning = {"table": ctx.tuning}
     for kv in args.tune:
         k, v = kv.split("=")
+        ctx.tune_clear(k)  # one value for every order
         ctx.tune_set(k, int(v))
         tuning[k] = int(v)
     plan = ctx.hk_plan(hls)
@@ -986,6 +989,91 @@ def main_uneven(args):
         ctx.profile_enable(False)
         note(f"{pname}: {timing[pname]:.2f} s per step")
     total_k = len(hls) * n_k
+
+    # ---- the mixed step as one HIP graph: the size groups on two lanes (a
+    # library context and a stream each; groups dealt largest work first to
+    # the less loaded lane), every buffer allocated beforehand; captured after
+    # an eager run of the same body has sized the workspaces, then replayed.
+    # The graph runs the Newton-Schulz loops' full schedules (converged
+    # matrices skip the steps), so its phases equal the eager run's bit for bit.
+    gprec, gdc, gcdt = L.BE_MIXED_FP32, L.BE_C64, torch.complex64
+    kap = torch.from_numpy(np.ascontiguousarray(kg.reshape(-1, 3), dtype=np.float64)).cuda()
+    nl = max(1, args.graph_lanes)
+    lanes = [ctx] + [L.Context(0) for _ in range(nl - 1)]
+    streams = [torch.cuda.Stream() for _ in range(nl)]
+    work = {N: len(groups[N]) * N ** 3 for N in sizes}
+    order = sorted(sizes, key=lambda n: -work[n])
+    load, assign = [0] * nl, {}
+    for N in order:
+        k = int(np.argmin(load))
+        assign[N] = k
+        load[k] += work[N]
+    lplans = {N: lanes[assign[N]].hk_plan([hls[s] for s in groups[N]]) for N in sizes}
+    chunk_k = {N: max(n_k, min(len(groups[N]) * n_k, (4 << 30) // (N * N * 8) // n_k * n_k)) for N in sizes}
+    gbuf = []
+    for k in range(nl):
+        Ns = [N for N in sizes if assign[N] == k]
+        gbuf.append({"U": torch.empty(max(len(groups[N]) * n_k * (N // 2) * N for N in Ns), dtype=torch.complex128,
+                                      device="cuda"),
+                     "H": torch.empty(max(chunk_k[N] * N * N for N in Ns), dtype=gcdt, device="cuda"),
+                     "ev": torch.empty(max(len(groups[N]) * n_k * (N // 2 + 2) for N in Ns), dtype=torch.float64,
+                                       device="cuda"),
+                     "st": torch.empty(max(len(groups[N]) * n_k for N in Ns), dtype=torch.int32, device="cuda")})
+    gout = {N: {"theta": torch.empty((len(groups[N]), UNEVEN_GRID, N // 2), dtype=torch.float64, device="cuda"),
+                "phi": torch.empty((len(groups[N]), UNEVEN_GRID), dtype=torch.float64, device="cuda"),
+                "wind": torch.empty(len(groups[N]), dtype=torch.int32, device="cuda"),
+                "st": torch.empty(len(groups[N]), dtype=torch.int32, device="cuda")} for N in sizes}
+
+    def run_group(N):
+        c, b = lanes[assign[N]], gbuf[assign[N]]
+        ns, m = len(groups[N]), N // 2
+        nmat = ns * n_k
+        U = b["U"][:nmat * m * N].view(nmat, m, N)
+        ev = b["ev"][:nmat * (m + 2)].view(nmat, m + 2)
+        per = chunk_k[N] // n_k
+        for s0 in range(0, ns, per):
+            nsc = min(per, ns - s0)
+            H = b["H"][:nsc * n_k * N * N].view(nsc * n_k, N, N)
+            c.build_hk(lplans[N], s0, nsc, kap, H, N * N, N, gdc)
+            q0 = s0 * n_k
+            c.eigh_batched(H, gdc, N, N, N * N, nsc * n_k, 0, m, gprec, ev[q0:], U[q0:], N, U.stride(0),
+                           b["st"][q0:])
+        o = gout[N]
+        c.wilson_loop(U, N, m, N, U.stride(0), ns, UNEVEN_GRID, UNEVEN_GRID, L.BE_OVL_POLAR, o["theta"], o["phi"],
+                      o["wind"], o["st"])
+
+    def body():
+        cur = torch.cuda.current_stream()
+        for s_ in streams:
+            s_.wait_stream(cur)
+        for N in order:
+            with torch.cuda.stream(streams[assign[N]]):
+                run_group(N)
+        for s_ in streams:
+            cur.wait_stream(s_)
+
+    body()
+    torch.cuda.synchronize()
+    eager = {N: gout[N]["theta"].clone() for N in sizes}
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(graph, stream=cap):
+        body()
+    torch.cuda.synchronize()
+    note("uneven step captured as one graph")
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_equal = all(torch.equal(gout[N]["theta"], eager[N]) for N in sizes)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    timing["graph"] = (time.perf_counter() - t0) / args.steps
+    note(f"graph: {timing['graph']:.2f} s per step (phases equal to the eager run's: {graph_equal})")
+    # the line's value: the faster of the eager loop and the graph (when the
+    # graph's phases equal the eager run's)
+    tbest = min(timing["graph"], timing["mixed"]) if graph_equal else timing["mixed"]
     # gate: mixed against FP64 on every line; FP64 against the oracle's lines
     from tests.phase_metrics import phase_set_error
     err_mixed = 0.0
@@ -1011,14 +1099,20 @@ def main_uneven(args):
                      "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": round(byts / launches, 1)})
     st = np.concatenate([res["mixed"][N][1]["status"].cpu().numpy() for N in sizes])
     out = {
-        "metric": METRIC, "value": round(total_k / timing["mixed"], 1), "unit": "k-point solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(timing["mixed"] * 1e3, 2),
+        "metric": METRIC, "value": round(total_k / tbest, 1), "unit": "k-point solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tbest * 1e3, 2),
+        "eager_value": round(total_k / timing["mixed"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "uneven batch: 64 BHZ L x L supercells, L drawn from {6, 8, 12, 16, 20}, 2 % vacancies "
                                "(N = 140, 252, 564, 1004, 1568), 16x16 k-grids, half filling, Wilson loop on all "
                                "occupied bands; mixed path (FP32 reduction and back-transformation) and FP64 path",
                    "systems": len(hls), "sizes": {str(N): len(groups[N]) for N in sizes}, "k_points": total_k},
         "fp64_value": round(total_k / timing["fp64"], 1), "mixed_over_fp64": round(timing["fp64"] / timing["mixed"], 3),
+        "graph": {"value": round(total_k / timing["graph"], 1), "ms_per_step": round(timing["graph"] * 1e3, 2),
+                  "lanes": nl, "groups_by_lane": {str(N): assign[N] for N in sizes},
+                  "phases_equal_eager_bitwise": bool(graph_equal),
+                  "note": "the mixed step captured once as one HIP graph (size groups dealt to the lanes, "
+                          "largest work first) and replayed"},
         "roofline": roof, "cpu_baseline": cpu,
         "phase_err_mixed_vs_fp64_rad": err_mixed, "phase_err_fp64_vs_oracle_rad": err_fp64 if oracle_res else None,
         "phase_gate_1e-6_ok": bool(err_mixed <= 1e-6),

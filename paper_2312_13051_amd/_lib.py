@@ -132,15 +132,28 @@ class HkPlan:
             pass
 
 
-class Context:
-    """One be_ctx on a HIP device."""
+# Per-order settings measured on an MI355X by tune.py (applied by default)
+DEFAULT_TUNING = os.path.join(_HERE, "tuning_mi355x.json")
 
-    def __init__(self, device: int = 0):
+
+class Context:
+    """One be_ctx on a HIP device. tuning: "default" applies DEFAULT_TUNING
+    (when present), None leaves the library's defaults, or a table / path."""
+
+    def __init__(self, device: int = 0, tuning="default"):
         self.lib = load()
         self.handle = C.c_void_p()
         rc = self.lib.be_create(C.byref(self.handle), int(device))
         if rc != BE_OK:
             raise BerryError(f"be_create failed ({rc})")
+        self.tuning = None
+        if tuning == "default":
+            if os.path.exists(DEFAULT_TUNING):
+                self.load_tuning(DEFAULT_TUNING)
+                self.tuning = os.path.basename(DEFAULT_TUNING)
+        elif tuning is not None:
+            self.load_tuning(tuning)
+            self.tuning = tuning if isinstance(tuning, str) else "table"
 
     def _check(self, rc):
         if rc != BE_OK:

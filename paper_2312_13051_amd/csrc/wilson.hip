@@ -739,10 +739,19 @@ __global__ __launch_bounds__(256) void k_herm_of_unitary(const double2 *W, int m
   }
 }
 
-// Phases from the eigenpairs of A: theta_n = phi + atan2(s_n, c_n), c_n the
-// eigenvalue, s_n = Im(e^{-i phi} v_n^H (W v_n)); residual check; ascending
-// sort; optional raw phases and eigenvectors. One workgroup per matrix, a
-// wave per column. fb[q] = 1 where the QR kernel must take over.
+// Phases from the eigenpairs of A. c_n (the eigenvalue, from bisection:
+// complete and accurate whatever the vectors) fixes |theta_n - phi| =
+// acos(c_n); s_n = Im(e^{-i phi} v_n^H (W v_n)) gives the sign. A vector
+// inside a cluster of nearly equal phases may be any mix of the cluster's
+// eigenvectors (W matrices of disordered supercells hold hundreds of phases
+// within 1e-9 of 0): its s_n keeps the common sign and |s_n| stays at
+// sqrt(1 - c_n^2), which is checked (a mix of a pair theta, 2 phi - theta
+// would break it). Within 0.05 of the branch points (sin ~ 0), and whenever
+// eigenvectors are returned, theta_n = phi + atan2(s_n, c_n) from a vector
+// whose residual |W v - e^{i theta} v| must be below 1e-10 (and the
+// eigensolver's status clear). Ascending sort; optional raw phases and
+// eigenvectors. One workgroup per matrix, a wave per column. fb[q] = 1 where
+// the QR kernel must take over.
 __global__ __launch_bounds__(256) void k_herm_phases(const double *ev, const uint32_t *est, const double2 *V,
                                                      const double2 *WV, int m, int64_t n_mat, double *theta_sorted,
                                                      int ldt, double *theta_raw, double2 *Zout, int *fb) {
@@ -754,34 +763,48 @@ __global__ __launch_bounds__(256) void k_herm_phases(const double *ev, const uin
   const int64_t mm = int64_t(m) * m;
   const double2 *Vq = V + q * mm, *Gq = WV + q * mm;
   const double cs = cos(kHermShift), sn = sin(kHermShift);
-  if (tid == 0) s_bad = (est[q] != 0) ? 1 : 0;
+  const bool vectors = Zout != nullptr;
+  if (tid == 0) s_bad = (est[q] & (vectors ? ~0u : uint32_t(BE_ST_NAN_INF))) ? 1 : 0;
   __syncthreads();
   for (int n = wave; n < m; n += 4) {
     const double2 *v = Vq + int64_t(n) * m, *g = Gq + int64_t(n) * m;
-    double pr = 0.0, pi = 0.0;
+    double pr = 0.0, pi = 0.0, vv = 0.0;
     for (int r = lane; r < m; r += 64) {
       const double2 a = v[r], b = g[r];
       pr += a.x * b.x + a.y * b.y;
       pi += a.x * b.y - a.y * b.x;
+      vv += a.x * a.x + a.y * a.y;
     }
     for (int o = 32; o > 0; o >>= 1) {
       pr += __shfl_xor(pr, o, 64);
       pi += __shfl_xor(pi, o, 64);
+      vv += __shfl_xor(vv, o, 64);
     }
-    const double s = cs * pi - sn * pr;  // Im(e^{-i phi} p)
-    double th = kHermShift + atan2(s, ev[q * (m + 2) + 1 + n]);
+    // Im(e^{-i phi} v^H W v) / v^H v (the vectors of a crowd of nearly equal
+    // phases need not come out normalized)
+    const double s = (cs * pi - sn * pr) / vv;
+    const double c = fmin(1.0, fmax(-1.0, ev[q * (m + 2) + 1 + n]));
+    const double sabs = sqrt(fmax(0.0, 1.0 - c * c));
+    const bool by_cos = !vectors && sabs >= 0.05;
+    double th = kHermShift + (by_cos ? copysign(acos(c), s) : atan2(s, c));
     if (th > M_PI) th -= 2.0 * M_PI;
-    const double er = cos(th), ei = sin(th);
-    double res = 0.0;
-    for (int r = lane; r < m; r += 64) {
-      const double2 a = v[r], b = g[r];
-      const double dx = b.x - (er * a.x - ei * a.y), dy = b.y - (er * a.y + ei * a.x);
-      res += dx * dx + dy * dy;
+    bool bad = !(th == th);
+    if (by_cos) {
+      bad = bad || !(fabs(fabs(s) - sabs) <= 1e-3);
+    } else {
+      const double er = cos(th), ei = sin(th);
+      double res = 0.0;
+      for (int r = lane; r < m; r += 64) {
+        const double2 a = v[r], b = g[r];
+        const double dx = b.x - (er * a.x - ei * a.y), dy = b.y - (er * a.y + ei * a.x);
+        res += dx * dx + dy * dy;
+      }
+      for (int o = 32; o > 0; o >>= 1) res += __shfl_xor(res, o, 64);
+      bad = bad || !(res <= 1e-20);  // |W v - e^{i theta} v| > 1e-10, or NaN
     }
-    for (int o = 32; o > 0; o >>= 1) res += __shfl_xor(res, o, 64);
     if (lane == 0) {
       sth[n] = th;
-      if (!(res <= 1e-20)) s_bad = 1;  // |W v - e^{i theta} v| > 1e-10, or NaN
+      if (bad) s_bad = 1;
     }
   }
   __syncthreads();
@@ -847,7 +870,7 @@ __global__ void k_or_lines(const uint32_t *line_st, int64_t n_lines, int per_sys
 namespace be {
 
 static int unitary_phases(be_ctx *ctx, const double2 *cur, int m, int64_t n_lines, double2 *Hs, double2 *Zout,
-                          double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream);
+                          double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream, bool unitary = true);
 
 // Wilson loops of n_lines closed lines of a grid of N x m matrices.
 // theta_sorted: [line][ldt]; Zout/theta_raw: optional eigenvectors of each W
@@ -1011,14 +1034,15 @@ static int wilson_core(be_ctx *ctx, Grid U, int N, int m, int64_t n_lines, int n
                        stream, cur, mm, Wout, mm, mm, n_lines);
     return check_launch(ctx, "copy_w");
   }
-  return unitary_phases(ctx, cur, m, n_lines, Hs, Zout, theta_sorted, ldt, theta_raw, line_status, stream);
+  return unitary_phases(ctx, cur, m, n_lines, Hs, Zout, theta_sorted, ldt, theta_raw, line_status, stream,
+                        mode == BE_OVL_POLAR);
 }
 
 // Eigenphases of n_lines unitary m x m matrices W (ascending into
 // theta_sorted [line][ldt]); Zout/theta_raw as for wilson_core; Hs: scratch of
 // n_lines m x m matrices (unused when the matrices fit LDS).
 static int unitary_phases(be_ctx *ctx, const double2 *cur, int m, int64_t n_lines, double2 *Hs, double2 *Zout,
-                          double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream) {
+                          double *theta_sorted, int ldt, double *theta_raw, uint32_t *line_status, hipStream_t stream, bool unitary) {
   ProfScope prof(ctx, "unitary_eig", stream);
   const size_t esm_lds = (size_t(m) * m + 2 * size_t(m)) * sizeof(double2);
   const bool inlds = Zout == nullptr && esm_lds <= 160 * 1024;
@@ -1030,6 +1054,21 @@ static int unitary_phases(be_ctx *ctx, const double2 *cur, int m, int64_t n_line
                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
     hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m, n_lines, Hs, Zout,
                        theta_sorted, ldt, theta_raw, line_status, 1, nullptr);
+    return check_launch(ctx, "unitary_eig");
+  }
+  if (!unitary) {  // raw overlaps: W is not unitary, the QR kernels take every matrix
+    const size_t esm = Zout ? 2 * size_t(m) * sizeof(double2)
+                            : (size_t(std::max(m, kUnitaryWgLds)) + size_t(m)) * sizeof(double2);
+    BE_CHECK_ARG(ctx, esm <= 150 * 1024, "Wilson loop: order of the Wilson matrices too large for the eigenphase kernel");
+    const void *kp = Zout ? reinterpret_cast<const void *>(&k_unitary_eig<false>)
+                          : reinterpret_cast<const void *>(&k_unitary_eig_wg<256>);
+    if (esm > 65536) BE_HIP_TRY(ctx, hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, int(esm)));
+    if (Zout)
+      hipLaunchKernelGGL(k_unitary_eig<false>, dim3(static_cast<uint32_t>(n_lines)), dim3(64), esm, stream, cur, m,
+                         n_lines, Hs, Zout, theta_sorted, ldt, theta_raw, line_status, 1, nullptr);
+    else
+      hipLaunchKernelGGL(k_unitary_eig_wg<256>, dim3(static_cast<uint32_t>(n_lines)), dim3(256), esm, stream, cur, m,
+                         n_lines, Hs, theta_sorted, ldt, theta_raw, line_status, 1, nullptr);
     return check_launch(ctx, "unitary_eig");
   }
   // larger orders: the Hermitian eigenproblem of (e^{-i phi} W + e^{i phi} W^H) / 2
@@ -1165,7 +1204,8 @@ extern "C" int be_wilson_loop(be_ctx *ctx, const void *U, int32_t N, int32_t m, 
       BE_RET_IF(wilson_core(ctx, g, N, m, nl, n_par, mode, theta + l0 * m, m, nullptr, nullptr, line_st + l0, nullptr,
                             stream, Wall + l0 * mm));
     }
-    BE_RET_IF(unitary_phases(ctx, Wall, m, n_lines, Hs, nullptr, theta, m, nullptr, line_st, stream));
+    BE_RET_IF(unitary_phases(ctx, Wall, m, n_lines, Hs, nullptr, theta, m, nullptr, line_st, stream,
+                             mode == BE_OVL_POLAR));
   }
   hipLaunchKernelGGL(k_or_lines, dim3(static_cast<uint32_t>((n_lines + 255) / 256)), dim3(256), 0, stream, line_st,
                      n_lines, n_perp, status);

@@ -234,10 +234,10 @@ def test_wilson_large_order_random_bases(N, m, n_par):
     assert (int(st[0]) & orc.OVERLAP_SINGULAR) == (ref_st & orc.OVERLAP_SINGULAR)
 
 
-def test_wilson_large_order_raw_mode_falls_back_to_qr():
-    """Raw overlaps (eq. 2 without polar factors) make W non-unitary: the
-    Hermitian route for large orders cannot represent it, sees the residual,
-    and hands every line to the QR kernel; phases against the oracle's."""
+def test_wilson_large_order_raw_mode():
+    """Raw overlaps (eq. 2 without polar factors) make W non-unitary, which
+    the Hermitian route for large orders cannot represent: such matrices go to
+    the QR kernel (order 128); phases against the oracle's."""
     gu.need_gpu()
     P = pipe()
     c = gu.ctx()
@@ -268,3 +268,24 @@ def test_nested_large_sector_eigenvectors():
     assert ref["status"] == 0 and int(out["status"][0]) == 0
     assert out["s"] == [ref["s"]]
     assert phase_set_error(out["theta"][0, :, :ref["s"]].cpu().numpy(), ref["theta"]) < TOL
+
+
+def test_wilson_clustered_phases_served_supercell():
+    """A served BHZ L = 12 supercell (m = 288): most of its Wilson phases
+    crowd within ~1e-9 of 0, which the eigenphase path must resolve (the
+    eigenvalues of the Hermitian matrix fix the phases, the vectors only their
+    signs); two lines against the oracle, FP64 path."""
+    gu.need_gpu()
+    P = pipe()
+    c = gu.ctx()
+    hl = syn.served_model("bhz12", 3)
+    kg = syn.kplane(32, 2)
+    m = hl.N // 2
+    out = P.wsurf(c, [hl], kg, 0, m)
+    assert int(out["status"][0]) & ~orc.WINDING_UNRESOLVED == 0
+    for i in range(2):
+        ev, U, st = orc.eigh_grid(hl, kg[i], 0, m)
+        W, _ = orc.wilson_matrix(U)
+        ref = orc.eigphases(W)
+        assert np.sum(np.abs(ref) < 1e-6) > m // 3  # the crowded cluster is there
+        assert phase_set_error(out["theta"][0, i].cpu().numpy(), ref) < 1e-10
