@@ -234,9 +234,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed", "refined"], default=None,
                     help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere; "
                          "refined: the mixed path for all bands, then an FP64 correction of the occupied "
-                         "subspace; phases are checked against the FP64 oracle at 1e-6 rad). Default: mixed, "
-                         "except refined for bbh_disorder (N = 1764, m = 882: the c64 Hamiltonian alone puts the "
-                         "summed phases of 882 bands near 1e-6 rad on the mixed path)")
+                         "subspace; phases are checked against the FP64 oracle at 1e-6 rad in every run). "
+                         "Default: mixed")
     ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
     ap.add_argument("--tune", action="append", default=[], metavar="KNOB=VALUE",
                     help="set a library tuning knob (be_tune_set) before timing")
@@ -254,7 +253,7 @@ def main():
         print("bench.py runs on one GPU only: berryhip has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.precision is None:
-        args.precision = "refined" if args.workload == "bbh_disorder" else "mixed"
+        args.precision = "mixed"
     if args.workload in ("bbh_disorder", "choti_nested"):
         return main_study(args)
     if args.workload == "served":
