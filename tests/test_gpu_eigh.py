@@ -389,3 +389,26 @@ def test_eigh_per_order_tuning():
         assert np.max(np.abs(P - V[:, :hl.N // 2] @ V[:, :hl.N // 2].conj().T)) < 1e-4
     finally:
         c.tune_clear("hetrd_panel_threads")
+
+
+@pytest.mark.parametrize("N,lo,hi", [(1, 0, 1), (5, 2, 2), (40, 0, 40), (70, 0, 1), (70, 69, 70)])
+def test_eigh_refined_edges(N, lo, hi):
+    """Refined path at its edges: one matrix element, an empty window, the
+    whole spectrum (no complement), a single band at either end."""
+    gu.need_gpu()
+    rng = np.random.default_rng([N, lo, hi])
+    A = rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))
+    Hs = A + np.conj(np.swapaxes(A, 1, 2))
+    c = gu.ctx()
+    m = hi - lo
+    ev, U, st = run_eigh_refined(c, Hs, lo, hi)
+    for q in range(3):
+        w, V = np.linalg.eigh(Hs[q])
+        nrm = max(1.0, np.max(np.abs(w)))
+        assert np.max(np.abs(ev[q, 1:m + 1] - w[lo:hi]), initial=0.0) <= 1e-9 * nrm
+        if m:
+            Uq = U[q]
+            assert np.max(np.abs(Uq.conj().T @ Uq - np.eye(m))) < 5e-12
+            P = Uq @ Uq.conj().T
+            assert np.max(np.abs(P - V[:, lo:hi] @ V[:, lo:hi].conj().T)) < 1e-9
+        assert (ev[q, 0] == ev[q, 0]) == (lo > 0) and (ev[q, m + 1] == ev[q, m + 1]) == (hi < N)

@@ -98,7 +98,9 @@ def test_largest_uneven_supercell_line():
 
 
 def test_largest_served_request_line():
-    """BHZ 24x24 with disorder (N = 2304), one 32-point Wilson line."""
+    """BHZ 24x24 with disorder (N = 2304), one 32-point Wilson line: eigenpairs
+    of one k-point against LAPACK, polar against raw overlaps, mixed against
+    FP64, and the Wilson stage against the oracle's on the GPU eigenvectors."""
     gu.need_gpu()
     P = pipe()
     c = gu.ctx()
@@ -124,3 +126,8 @@ def test_largest_served_request_line():
     th = out["theta"][0, 0].cpu().numpy()
     mixed = P.wsurf(c, [hl], kg, 0, m, precision=1)
     assert phase_set_error(th, mixed["theta"][0, 0].cpu().numpy()) < 1e-6
+    # the Wilson stage at order 1152 (overlaps, polar factors, product, eigenphases
+    # through the Hermitian route) against the oracle's on the same eigenvectors
+    Ul = gu.to_np(g.U, hl.N)[:, :, :m]
+    W, _ = orc.wilson_matrix(Ul)
+    assert phase_set_error(th, orc.eigphases(W)) < 1e-10
