@@ -13,10 +13,10 @@ torch = gu.torch
 pytestmark = pytest.mark.gpu
 
 
-def _setup(prec):
+def _setup(prec, L_cell=3):
     from paper_2312_13051_amd import _lib as L
     c = gu.ctx()
-    hls = [syn.bhz_disordered(3, 1.0 + r, [13, r]) for r in range(2)]
+    hls = [syn.bhz_disordered(L_cell, 1.0 + r, [13, r]) for r in range(2)]
     plan = c.hk_plan(hls)
     kg = syn.kplane(8, 6)
     n_k = kg.shape[0] * kg.shape[1]
@@ -51,10 +51,13 @@ def _setup(prec):
     return c, run, bufs
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_captured_hot_path_replays_bitwise(prec):
+@pytest.mark.parametrize("prec,L_cell", [(0, 3), (1, 3), (2, 3), (0, 8), (1, 8)])
+def test_captured_hot_path_replays_bitwise(prec, L_cell):
+    """L_cell = 8: Wilson matrices of order 128, whose eigenphases take the
+    Hermitian route (an eigensolver call and the checked QR fallback inside
+    the graph); prec 2: the refined eigensolver."""
     gu.need_gpu()
-    c, run, bufs = _setup(prec)
+    c, run, bufs = _setup(prec, L_cell)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         run()           # sizes the workspace outside capture
