@@ -142,6 +142,11 @@ class Context:
 
     def __init__(self, device: int = 0, tuning="default"):
         self.lib = load()
+        try:  # torch provides the streams and device memory: let it initialize the device first
+            import torch
+            torch.cuda.init()
+        except Exception:  # noqa: BLE001 - be_create reports a missing device itself
+            pass
         self.handle = C.c_void_p()
         rc = self.lib.be_create(C.byref(self.handle), int(device))
         if rc != BE_OK:
