@@ -206,6 +206,14 @@ int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, int32_t ld, 
                     int32_t n_mat, int32_t band_lo, int32_t band_hi, int32_t precision, double *evals,
                     void *U, int32_t ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
 
+/* Matrices of order N that the eigensolver's panel kernel keeps resident on
+ * the device at once for `precision` (one workgroup per matrix; depends on
+ * the panel thread count chosen for N). be_eigh_batched processes a batch in
+ * equal sub-batches of whole such rounds where its workspace cap allows, so a
+ * batch of a multiple of *round matrices fills every round. Host-only query
+ * (an occupancy calculation), no device work. */
+int be_eigh_round(be_ctx *ctx, int32_t N, int32_t precision, int64_t *round);
+
 /* Rows (a6)-(a8) -- Wilson loop over a U-grid (eq. 2 with the path ordering
  * of eq. 1, hybrid centres of eq. 3, Chern winding of eq. 6).
  *   F_j = U(kappa_{j+1})^H U(kappa_j), j < n_par (closing to j = 0);

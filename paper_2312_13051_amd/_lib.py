@@ -30,7 +30,7 @@ EXPORTS = [
     "be_spin_resolved_wilson", "be_plaquette_flux", "be_plaquette_flux_noalloc", "be_spin_sectors",
     "be_zgemm_strided",
     "be_profile_enable", "be_profile_query", "be_profile_names", "be_tune_set", "be_tune_get",
-    "be_tune_set_orders", "be_tune_clear",
+    "be_tune_set_orders", "be_tune_clear", "be_eigh_round",
 ]
 
 
@@ -85,6 +85,7 @@ def load():
     lib.be_tune_get.argtypes = [vp, C.c_char_p, C.POINTER(i32)]
     lib.be_tune_set_orders.argtypes = [vp, C.c_char_p, i32, i32, i32, i32]
     lib.be_tune_clear.argtypes = [vp, C.c_char_p]
+    lib.be_eigh_round.argtypes = [vp, i32, i32, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
             "be_last_error", "be_workspace_bytes", "be_hk_plan_N") else C.c_int
@@ -243,6 +244,12 @@ class Context:
     def tune_set_orders(self, knob: str, n_lo: int, n_hi: int, precision: int, value: int):
         self._check(self.lib.be_tune_set_orders(self.handle, knob.encode(), int(n_lo), int(n_hi), int(precision),
                                                 int(value)))
+
+    def eigh_round(self, N: int, precision: int) -> int:
+        """Matrices of order N the eigensolver runs at once on the device."""
+        r = C.c_int64()
+        self._check(self.lib.be_eigh_round(self.handle, int(N), int(precision), C.byref(r)))
+        return int(r.value)
 
     def tune_clear(self, knob: str):
         self._check(self.lib.be_tune_clear(self.handle, knob.encode()))

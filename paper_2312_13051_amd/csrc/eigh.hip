@@ -2061,3 +2061,17 @@ extern "C" int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, i
   }
   return set_err(ctx, BE_EINVAL, "be_eigh_batched: unknown precision");
 }
+
+extern "C" int be_eigh_round(be_ctx *ctx, int32_t N, int32_t precision, int64_t *round) {
+  using namespace be;
+  BE_CHECK_ARG(ctx, ctx && round, "be_eigh_round: null argument");
+  BE_CHECK_ARG(ctx, N >= 1, "be_eigh_round: N < 1");
+  if (precision == BE_FP64) {
+    *round = panel_slots<double>(ctx, N);
+  } else if (precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED) {
+    *round = panel_slots<float>(ctx, N);
+  } else {
+    return set_err(ctx, BE_EINVAL, "be_eigh_round: unknown precision");
+  }
+  return BE_OK;
+}

@@ -286,6 +286,7 @@ class GpuExecutor:
         for _ in range(self.n_lanes):
             self.lanes.append((L.Context(device), torch.cuda.Stream(device=device)))
         self._H = {}          # key -> [H buffer, event after its last use]
+        self._chunk = {}      # (N, precision) -> Hamiltonians per launch
         self._key_users = collections.Counter()
         self._lock = threading.Lock()
 
@@ -295,9 +296,17 @@ class GpuExecutor:
 
     def chunk_for(self, req: Request) -> int:
         """Hamiltonians per eigensolver launch for the request's key: the same
-        for every request of a key, since the key's buffer holds that many."""
-        per = req.N * req.N * self._hb(req)
-        return int(max(1, min(self.chunk_cap, self.h_bytes // per)))
+        for every request of a key, since the key's buffer holds that many;
+        a whole number of the eigensolver's device rounds where it holds at
+        least one (a launch of 404 order-2304 matrices would run as two
+        rounds of 202 on 256 compute units; 256 fill one)."""
+        key = (req.N, req.precision)
+        if key not in self._chunk:
+            per = req.N * req.N * self._hb(req)
+            c = int(max(1, min(self.chunk_cap, self.h_bytes // per)))
+            r = self.lanes[0][0].eigh_round(req.N, req.precision)
+            self._chunk[key] = c // r * r if c >= r else c
+        return self._chunk[key]
 
     def footprint(self, req: Request) -> int:
         """Resident eigenvectors, one chunk of Hamiltonians (one buffer per
