@@ -349,7 +349,14 @@ int be_profile_names(be_ctx *ctx, char *buf, size_t len);
  *   "hetrd_panel_threads" threads per matrix of the panel kernel: 256, 512
  *                       or 1024 (default 512: two matrices per compute
  *                       unit overlap one's serial reflector steps with the
- *                       other's matrix-vector product). */
+ *                       other's matrix-vector product).
+ *   "hetrd_panel_loads"  loads in flight per lane in the matrix-vector
+ *                       product of the 512-thread FP32 panel kernel (the
+ *                       mixed paths): 4 (six waves resident per SIMD) or 8
+ *                       (four waves); 0 (default) takes 8 from order 960 on.
+ *                       The other panel kernels have one form each (FP64
+ *                       and 256 threads: 4; 1024-thread FP32: 8), which
+ *                       this knob leaves unchanged. */
 int be_tune_set(be_ctx *ctx, const char *knob, int32_t value);
 int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value);
 

@@ -39,12 +39,14 @@ struct be_ctx {
   int n_cu = 256;
   // tuning knobs (be_tune_set, be_tune_set_orders)
   int tune_panel_threads = 512;   // threads per matrix of the Householder panel kernel
+  int tune_panel_loads = 0;       // loads in flight per lane of the 512-thread FP32 panel (0: by order)
   struct TuneRange {
     int n_lo, n_hi;  // orders N in [n_lo, n_hi]
     int elem;        // bytes per element of the reduction (8: mixed paths, 16: FP64), 0: both
     int value;
   };
   std::vector<TuneRange> tune_panel_ranges;  // per-order panel thread counts (last match wins)
+  std::vector<TuneRange> tune_loads_ranges;  // per-order loads in flight (last match wins)
   std::string prof_scope;         // prefix of launch-timer names (nested calls)
 };
 
@@ -52,11 +54,29 @@ namespace be {
 
 // Threads per matrix of the Householder panel kernel for order N and element
 // size elem (bytes): the last matching per-order setting, else the default.
-inline int panel_threads(const be_ctx *ctx, int N, size_t elem) {
-  int v = ctx->tune_panel_threads;
-  for (const auto &r : ctx->tune_panel_ranges)
+inline int tune_value(const std::vector<be_ctx::TuneRange> &ranges, int v, int N, size_t elem) {
+  for (const auto &r : ranges)
     if (N >= r.n_lo && N <= r.n_hi && (r.elem == 0 || size_t(r.elem) == elem)) v = r.value;
   return v;
+}
+inline int panel_threads(const be_ctx *ctx, int N, size_t elem) {
+  return tune_value(ctx->tune_panel_ranges, ctx->tune_panel_threads, N, elem);
+}
+
+// Loads in flight per lane of the panel kernel's matrix-vector product (the
+// columns of one transposed column sum): 4 for the FP64 reduction and the
+// 256-thread FP32 one, 8 for the 1024-thread FP32 one. The 512-thread FP32
+// kernel comes in both forms (4 loads at six waves per SIMD, 8 loads at four,
+// the register budget of each): the knob's value for the order, else 8 from
+// order kPanelLoads8From on (measured on MI355X: 4 loads faster up to order
+// 800, 8 loads from 1024 on, where the larger matrices leave fewer resident
+// workgroups to hide the load latency).
+constexpr int kPanelLoads8From = 960;
+inline int panel_loads(const be_ctx *ctx, int N, size_t elem, int nt) {
+  if (elem != 8 || nt == 256) return 4;
+  if (nt == 1024) return 8;
+  const int v = tune_value(ctx->tune_loads_ranges, ctx->tune_panel_loads, N, elem);
+  return v ? v : (N >= kPanelLoads8From ? 8 : 4);
 }
 
 // ---------------------------------------------------------------- errors

@@ -154,52 +154,68 @@ int be_profile_query(be_ctx *ctx, const char *name, double *total_ms, int64_t *l
   return BE_OK;
 }
 
+namespace {
+// The tunable knobs: default value, per-order settings, accepted values.
+struct Knob {
+  int *value;
+  std::vector<be_ctx::TuneRange> *ranges;
+  int reset;
+  bool (*ok)(int);
+  const char *allowed;
+};
+bool find_knob(be_ctx *ctx, const std::string &k, Knob *kn) {
+  if (k == "hetrd_panel_threads") {
+    *kn = {&ctx->tune_panel_threads, &ctx->tune_panel_ranges, 512,
+           [](int v) { return v == 256 || v == 512 || v == 1024; }, "hetrd_panel_threads takes 256, 512 or 1024"};
+    return true;
+  }
+  if (k == "hetrd_panel_loads") {
+    *kn = {&ctx->tune_panel_loads, &ctx->tune_loads_ranges, 0, [](int v) { return v == 0 || v == 4 || v == 8; },
+           "hetrd_panel_loads takes 0 (by order), 4 or 8"};
+    return true;
+  }
+  return false;
+}
+}  // namespace
+
 int be_tune_set(be_ctx *ctx, const char *knob, int32_t value) {
   if (!ctx || !knob) return BE_EINVAL;
-  const std::string k(knob);
-  if (k == "hetrd_panel_threads") {
-    BE_CHECK_ARG(ctx, value == 256 || value == 512 || value == 1024, "hetrd_panel_threads takes 256, 512 or 1024");
-    ctx->tune_panel_threads = value;
-    return BE_OK;
-  }
-  return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
+  Knob kn;
+  if (!find_knob(ctx, knob, &kn)) return be::set_err(ctx, BE_EINVAL, std::string("unknown tuning knob: ") + knob);
+  BE_CHECK_ARG(ctx, kn.ok(value), kn.allowed);
+  *kn.value = value;
+  return BE_OK;
 }
 
 int be_tune_set_orders(be_ctx *ctx, const char *knob, int32_t n_lo, int32_t n_hi, int32_t precision, int32_t value) {
   if (!ctx || !knob) return BE_EINVAL;
-  const std::string k(knob);
-  if (k == "hetrd_panel_threads") {
-    BE_CHECK_ARG(ctx, value == 256 || value == 512 || value == 1024, "hetrd_panel_threads takes 256, 512 or 1024");
-    BE_CHECK_ARG(ctx, 1 <= n_lo && n_lo <= n_hi, "be_tune_set_orders: need 1 <= n_lo <= n_hi");
-    BE_CHECK_ARG(ctx, precision == -1 || precision == BE_FP64 || precision == BE_MIXED_FP32 ||
-                          precision == BE_MIXED_FP32_REFINED,
-                 "be_tune_set_orders: precision must be -1, BE_FP64, BE_MIXED_FP32 or BE_MIXED_FP32_REFINED");
-    const int elem = precision == -1 ? 0 : precision == BE_FP64 ? 16 : 8;
-    ctx->tune_panel_ranges.push_back({n_lo, n_hi, elem, value});
-    return BE_OK;
-  }
-  return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
+  Knob kn;
+  if (!find_knob(ctx, knob, &kn)) return be::set_err(ctx, BE_EINVAL, std::string("unknown tuning knob: ") + knob);
+  BE_CHECK_ARG(ctx, kn.ok(value), kn.allowed);
+  BE_CHECK_ARG(ctx, 1 <= n_lo && n_lo <= n_hi, "be_tune_set_orders: need 1 <= n_lo <= n_hi");
+  BE_CHECK_ARG(ctx, precision == -1 || precision == BE_FP64 || precision == BE_MIXED_FP32 ||
+                        precision == BE_MIXED_FP32_REFINED,
+               "be_tune_set_orders: precision must be -1, BE_FP64, BE_MIXED_FP32 or BE_MIXED_FP32_REFINED");
+  const int elem = precision == -1 ? 0 : precision == BE_FP64 ? 16 : 8;
+  kn.ranges->push_back({n_lo, n_hi, elem, value});
+  return BE_OK;
 }
 
 int be_tune_clear(be_ctx *ctx, const char *knob) {
   if (!ctx || !knob) return BE_EINVAL;
-  const std::string k(knob);
-  if (k == "hetrd_panel_threads") {
-    ctx->tune_panel_ranges.clear();
-    ctx->tune_panel_threads = 512;
-    return BE_OK;
-  }
-  return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
+  Knob kn;
+  if (!find_knob(ctx, knob, &kn)) return be::set_err(ctx, BE_EINVAL, std::string("unknown tuning knob: ") + knob);
+  kn.ranges->clear();
+  *kn.value = kn.reset;
+  return BE_OK;
 }
 
 int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value) {
   if (!ctx || !knob || !value) return BE_EINVAL;
-  const std::string k(knob);
-  if (k == "hetrd_panel_threads") {
-    *value = ctx->tune_panel_threads;
-    return BE_OK;
-  }
-  return be::set_err(ctx, BE_EINVAL, "unknown tuning knob: " + k);
+  Knob kn;
+  if (!find_knob(ctx, knob, &kn)) return be::set_err(ctx, BE_EINVAL, std::string("unknown tuning knob: ") + knob);
+  *value = *kn.value;
+  return BE_OK;
 }
 
 int be_profile_names(be_ctx *ctx, char *buf, size_t len) {

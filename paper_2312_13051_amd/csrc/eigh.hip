@@ -101,8 +101,8 @@ __device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
   __syncthreads();
 }
 
-// Column sums over the 64 lanes of a wave for CW columns at once (CW = 8 or
-// 16): lane L holds the products of its row with the CW columns in
+// Column sums over the 64 lanes of a wave for CW columns at once (CW = 4, 8
+// or 16): lane L holds the products of its row with the CW columns in
 // (pr[c], pi[c]). Butterfly transpose: at offset o (32, 16, ...) each lane
 // keeps the half of its columns selected by bit o of L, adds the partner's
 // copy of that half and passes on the other half, so every exchange halves
@@ -142,16 +142,18 @@ __device__ __forceinline__ C xpose_colsum(C (&p)[CW], int lane) {
 // per-matrix NB x NB compact-WY factor of each panel, d/e: FP64 tridiagonal
 // output. Partial vectors of the matrix-vector product: in LDS after the
 // panel's other arrays (PL), else at Pg + q*sPg (global scratch of
-// (nrb+1)*nrb*64 elements, nrb = ceil((N-1)/64)).
-template <typename T, int NT, bool PL>
-__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT <= 512) ? 6 : 1) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
+// (nrb+1)*nrb*64 elements, nrb = ceil((N-1)/64)). CW: loads in flight per
+// lane in the matrix-vector product (columns per transposed column sum, 4 or
+// 8); the FP32 kernels of up to 512 threads with 4 loads keep six waves per
+// SIMD resident, with 8 loads four (the registers the loads take).
+template <typename T, int NT, bool PL, int CW>
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? (NT == 1024 ? 1 : CW == 4 ? 6 : 4) : 1) void hetrd_panel(typename CT<T>::c *A, int64_t sA, int lda, int N, int p0, int nbp,
                                                   typename CT<T>::c *VW, int64_t sVW, typename CT<T>::c *Tm,
                                                   int64_t sTm, double *d, double *e, int64_t sDE,
                                                   typename CT<T>::c *Pg, int64_t sPg, uint32_t *status) {
   typedef typename CT<T>::c C;
-  // columns per transposed column sum = loads in flight per lane (64 bytes)
-  constexpr int CW = 4;
-  constexpr int CSH = 4;  // lane -> column shift of xpose_colsum<CW>
+  static_assert(CW == 4 || CW == 8, "4 or 8 loads in flight");
+  constexpr int CSH = CW == 8 ? 3 : 4;  // lane -> column shift of xpose_colsum<CW>
   extern __shared__ unsigned char smem_raw[];
   C *sv = reinterpret_cast<C *>(smem_raw);  // v, length N
   C *sy = sv + N;                           // y / w, length N
@@ -1273,10 +1275,19 @@ using PanelFn = void (*)(typename CT<T>::c *, int64_t, int, int, int, int, typen
                          typename CT<T>::c *, int64_t, double *, double *, int64_t, typename CT<T>::c *, int64_t,
                          uint32_t *);
 
+// The panel kernel for nt threads, partial vectors in LDS (pl) or not, and
+// cw loads in flight (as panel_loads gives it: only the 512-thread FP32
+// kernel has both forms; FP64 has 4 everywhere).
+template <typename T, bool PL>
+PanelFn<T> panel_kernel_pl(int nt, int cw) {
+  constexpr bool f32 = sizeof(T) == 4;
+  if (nt == 256) return &hetrd_panel<T, 256, PL, 4>;
+  if (nt == 512) return (f32 && cw == 8) ? &hetrd_panel<T, 512, PL, f32 ? 8 : 4> : &hetrd_panel<T, 512, PL, 4>;
+  return &hetrd_panel<T, 1024, PL, f32 ? 8 : 4>;
+}
 template <typename T>
-PanelFn<T> panel_kernel(int nt, bool pl) {
-  if (pl) return nt == 256 ? &hetrd_panel<T, 256, true> : nt == 512 ? &hetrd_panel<T, 512, true> : &hetrd_panel<T, 1024, true>;
-  return nt == 256 ? &hetrd_panel<T, 256, false> : nt == 512 ? &hetrd_panel<T, 512, false> : &hetrd_panel<T, 1024, false>;
+PanelFn<T> panel_kernel(int nt, int cw, bool pl) {
+  return pl ? panel_kernel_pl<T, true>(nt, cw) : panel_kernel_pl<T, false>(nt, cw);
 }
 
 
@@ -1522,7 +1533,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
   BE_RET_IF(check_launch(ctx, "zero_u32"));
   const int64_t sVW = int64_t(N) * 3 * NB;
   const int64_t sT = int64_t(P) * NB * NB;
-  PanelFn<T> panel = panel_kernel<T>(pnt, pl);
+  PanelFn<T> panel = panel_kernel<T>(pnt, panel_loads(ctx, N, sizeof(C), pnt), pl);
   if (psm > 65536)
     BE_HIP_TRY(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)));
@@ -1762,7 +1773,7 @@ static int64_t panel_slots(be_ctx *ctx, int N) {
   typedef typename CT<T>::c C;
   const int pnt = panel_threads(ctx, N, sizeof(C));
   const size_t psm = panel_lds(N, sizeof(C), pnt);
-  PanelFn<T> panel = panel_kernel<T>(pnt, panel_part_lds(N, sizeof(C), pnt));
+  PanelFn<T> panel = panel_kernel<T>(pnt, panel_loads(ctx, N, sizeof(C), pnt), panel_part_lds(N, sizeof(C), pnt));
   int per_cu = 0;
   if (psm > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(panel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(psm)) != hipSuccess)

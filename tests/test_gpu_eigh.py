@@ -158,27 +158,54 @@ def test_eigh_mixed_precision_bounds(name):
         assert st[q] == 0
 
 
-@pytest.mark.parametrize("threads", [1024, 512, 256])
+@pytest.mark.parametrize("threads,loads", [(1024, 0), (512, 4), (512, 8), (256, 0)])
 @pytest.mark.parametrize("N,lo,hi", [(257, 0, 128), (400, 7, 203), (463, 100, 300)])
-def test_eigh_panel_variants(N, lo, hi, threads):
-    """The panel kernel with 256 to 1024 threads per matrix."""
+def test_eigh_panel_variants(N, lo, hi, threads, loads):
+    """The panel kernel with 256 to 1024 threads per matrix, and the FP32
+    512-thread kernel in both loads-in-flight forms (the FP64 reduction has
+    one form per thread count: the loads knob leaves it unchanged)."""
     gu.need_gpu()
     rng = np.random.default_rng([N, 7])
     A = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
     Hs = A + np.conj(np.swapaxes(A, 1, 2))
     c = gu.ctx()
+    for knob in ("hetrd_panel_threads", "hetrd_panel_loads"):
+        c.tune_clear(knob)  # no per-order table: one setting for every order
     c.tune_set("hetrd_panel_threads", threads)
-    assert c.tune_get("hetrd_panel_threads") == threads
-    ev, U, st = run_eigh(c, Hs, lo, hi, ld_pad=1)
-    check(Hs, lo, hi, ev, U, st)
-    hl = syn.bhz_disordered(10, 2.0, [3, 2, 4])
-    Hm = np.stack([orc.bloch_hamiltonian(hl, k) for k in syn.kplane(2, 1).reshape(-1, 3)])
-    ev, U, st = run_eigh_mixed(c, Hm, 0, 200)
-    for q in range(Hm.shape[0]):
-        w = np.linalg.eigvalsh(Hm[q])
-        assert np.max(np.abs(ev[q, 1:201] - w[:200])) <= 2e-5 * max(1.0, np.abs(w).max())
-        assert np.max(np.abs(U[q].conj().T @ U[q] - np.eye(200))) < 1e-5
-        assert st[q] == 0
+    c.tune_set("hetrd_panel_loads", loads)
+    assert c.tune_get("hetrd_panel_threads") == threads and c.tune_get("hetrd_panel_loads") == loads
+    try:
+        ev, U, st = run_eigh(c, Hs, lo, hi, ld_pad=1)
+        check(Hs, lo, hi, ev, U, st)
+        hl = syn.bhz_disordered(10, 2.0, [3, 2, 4])
+        Hm = np.stack([orc.bloch_hamiltonian(hl, k) for k in syn.kplane(2, 1).reshape(-1, 3)])
+        # mixed path on the BHZ supercell and on the random matrices (at
+        # N = 257 the panel splits each 64-row tile into column groups)
+        for H, m in ((Hm, 200), (Hs, hi)):
+            ev, U, st = run_eigh_mixed(c, H, 0, m)
+            for q in range(H.shape[0]):
+                w = np.linalg.eigvalsh(H[q])
+                assert np.max(np.abs(ev[q, 1:m + 1] - w[:m])) <= 2e-5 * max(1.0, np.abs(w).max())
+                assert np.max(np.abs(U[q].conj().T @ U[q] - np.eye(m))) < 1e-5
+                assert st[q] == 0
+    finally:
+        c.close()
+
+
+def test_tune_loads_knob_checks_values():
+    """hetrd_panel_loads takes 0, 4 or 8; tune_clear restores 0 (by order)."""
+    gu.need_gpu()
+    c = gu.ctx()
+    try:
+        with pytest.raises(Exception):
+            c.tune_set("hetrd_panel_loads", 6)
+        with pytest.raises(Exception):
+            c.tune_set_orders("hetrd_panel_loads", 1, 100, 1, 16)
+        c.tune_set("hetrd_panel_loads", 8)
+        c.tune_clear("hetrd_panel_loads")
+        assert c.tune_get("hetrd_panel_loads") == 0
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("N,n_minus", [(200, 100), (96, 40)])
@@ -387,8 +414,16 @@ def test_eigh_per_order_tuning():
         w, V = np.linalg.eigh(Hs[0])
         P = U[0] @ U[0].conj().T
         assert np.max(np.abs(P - V[:, :hl.N // 2] @ V[:, :hl.N // 2].conj().T)) < 1e-4
+        # per-order loads in flight of the 512-thread FP32 kernel
+        c.load_tuning({"knobs": {"hetrd_panel_threads": [{"n_lo": 1, "n_hi": 10000, "precision": -1, "value": 512}],
+                                 "hetrd_panel_loads": [{"n_lo": 1, "n_hi": 200, "precision": 1, "value": 8},
+                                                       {"n_lo": 201, "n_hi": 10000, "precision": 1, "value": 4}]}})
+        ev2, U2, st2 = run_eigh_mixed(c, Hs, 0, hl.N // 2)
+        P2 = U2[0] @ U2[0].conj().T
+        assert np.max(np.abs(P2 - V[:, :hl.N // 2] @ V[:, :hl.N // 2].conj().T)) < 1e-4
+        assert np.all(st2 == 0)
     finally:
-        c.tune_clear("hetrd_panel_threads")
+        c.close()
 
 
 @pytest.mark.parametrize("N,lo,hi", [(1, 0, 1), (5, 2, 2), (40, 0, 40), (70, 0, 1), (70, 69, 70)])
