@@ -102,6 +102,31 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _span(n, stride, rows, cols, ld):
+    """Elements from the start of the first to the end of the last of n
+    column-major rows x cols matrices (matrix q at q*stride, leading
+    dimension ld); 0 when nothing is accessed."""
+    if n <= 0 or rows <= 0 or cols <= 0:
+        return 0
+    return (int(n) - 1) * int(stride) + (int(cols) - 1) * int(ld) + int(rows)
+
+
+def _require(t, name, nbytes, device=None):
+    """The library accesses nbytes bytes through t's pointer: t's storage
+    must hold that many from t's first element on (whatever t's own shape and
+    strides), and, with device given, t must live on that HIP device. Checked
+    on the host before the call, so a too-small buffer is an error here, not
+    a device memory fault. A missing tensor is left to the library (its
+    BE_EINVAL for a null pointer)."""
+    if t is None or nbytes <= 0:
+        return
+    if device is not None and (not t.is_cuda or t.device.index != device):
+        raise BerryError(f"{name}: must be a tensor on cuda:{device}, got one on {t.device}")
+    avail = t.untyped_storage().nbytes() - t.storage_offset() * t.element_size()
+    if avail < nbytes:
+        raise BerryError(f"{name}: the call accesses {nbytes} bytes from its first element, its storage holds {avail}")
+
+
 class HkPlan:
     """Device copy of packed hopping lists (be_hk_plan)."""
 
@@ -149,7 +174,8 @@ class Context:
         except Exception:  # noqa: BLE001 - be_create reports a missing device itself
             pass
         self.handle = C.c_void_p()
-        rc = self.lib.be_create(C.byref(self.handle), int(device))
+        self.device = int(device)
+        rc = self.lib.be_create(C.byref(self.handle), self.device)
         if rc != BE_OK:
             raise BerryError(f"be_create failed ({rc})")
         self.tuning = None
@@ -184,21 +210,46 @@ class Context:
     def hk_plan(self, hoplists) -> HkPlan:
         return HkPlan(self, hoplists)
 
+    def _req(self, t, name, n_elems, elem_bytes):
+        _require(t, name, int(n_elems) * elem_bytes, self.device)
+
+    def _ugrid(self, U, N, m, ldu, u_stride, n_mats, name="U"):
+        self._req(U, name, _span(n_mats, u_stride, N, m, ldu), 16)
+
     def build_hk(self, plan: HkPlan, sys_first: int, n_sys: int, kappa, H, mat_stride: int, ld: int, dtype: int):
+        n_kap = kappa.shape[0]
+        N = int(self.lib.be_hk_plan_N(plan.handle, int(sys_first)))
+        self._req(kappa, "kappa", n_kap * 3, 8)
+        self._req(H, "H", _span(n_sys * n_kap, mat_stride, N, N, ld), 16 if dtype == BE_C128 else 8)
         self._check(self.lib.be_build_hk(self.handle, plan.handle, sys_first, n_sys, _ptr(kappa), kappa.shape[0],
                                          _ptr(H), mat_stride, ld, dtype, _stream()))
 
     def eigh_batched(self, H, dtype, N, ld, mat_stride, n_mat, lo, hi, precision, evals, U, ldu, u_stride, status):
+        m = hi - lo
+        self._req(H, "H", _span(n_mat, mat_stride, N, N, ld), 16 if dtype == BE_C128 else 8)
+        self._req(evals, "evals", n_mat * (m + 2), 8)
+        self._ugrid(U, N, m, ldu, u_stride, n_mat)
+        self._req(status, "status", n_mat, 4)
         self._check(self.lib.be_eigh_batched(self.handle, _ptr(H), dtype, N, ld, mat_stride, n_mat, lo, hi,
                                              precision, _ptr(evals), _ptr(U), ldu, u_stride, _ptr(status),
                                              _stream()))
 
     def wilson_loop(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, theta, phi, winding, status):
+        self._ugrid(U, N, m, ldu, u_stride, n_sys * n_perp * n_par)
+        self._req(theta, "theta", n_sys * n_perp * m, 8)
+        self._req(phi, "phi", n_sys * n_perp, 8)
+        self._req(winding, "winding", n_sys, 4)
+        self._req(status, "status", n_sys, 4)
         self._check(self.lib.be_wilson_loop(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp, mode,
                                             _ptr(theta), _ptr(phi), _ptr(winding), _ptr(status), _stream()))
 
     def nested_wilson(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, mode, win_lo, win_hi, nested_theta, p,
                       p_mean, status):
+        self._ugrid(U, N, m, ldu, u_stride, n_sys * n_perp * n_par)
+        self._req(nested_theta, "nested_theta", n_sys * n_par * m, 8)
+        self._req(p, "p", n_sys * n_par, 8)
+        self._req(p_mean, "p_mean", n_sys, 8)
+        self._req(status, "status", n_sys, 4)
         s_out = (C.c_int32 * n_sys)()
         self._check(self.lib.be_nested_wilson(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp, mode,
                                               win_lo, win_hi, _ptr(nested_theta), _ptr(p), _ptr(p_mean), s_out,
@@ -209,6 +260,14 @@ class Context:
                              theta_dn, theta_up, C_dn, C_up, C_s, status, precision=BE_FP64, m_dn_in=None):
         """m_dn_in: sector sizes to pass in (required while the stream is
         being captured into a graph)."""
+        self._ugrid(U, N, m, ldu, u_stride, n_sys * n_perp * n_par)
+        self._req(spin_diag, "spin_diag", n_sys * N, 8)
+        self._req(pso_evals, "pso_evals", n_sys * n_perp * n_par * m, 8)
+        for t, name in ((theta_dn, "theta_dn"), (theta_up, "theta_up")):
+            self._req(t, name, n_sys * n_perp * m, 8)
+        for t, name in ((C_dn, "C_dn"), (C_up, "C_up"), (status, "status")):
+            self._req(t, name, n_sys, 4)
+        self._req(C_s, "C_s", n_sys, 8)
         m_dn = (C.c_int32 * n_sys)(*(m_dn_in or []))
         self._check(self.lib.be_spin_resolved_wilson(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
                                                      mode, precision, _ptr(spin_diag), _ptr(pso_evals), _ptr(theta_dn),
@@ -216,17 +275,31 @@ class Context:
                                                      _ptr(status), _stream()))
         return [int(x) for x in m_dn]
 
+    def _flux_args(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status):
+        self._ugrid(U, N, m, ldu, u_stride, n_sys * n_perp * n_par)
+        self._req(flux, "flux", n_sys * n_perp * n_par, 8)
+        self._req(chern, "chern", n_sys, 4)
+        self._req(total, "total", n_sys, 8)
+        self._req(status, "status", n_sys, 4)
+
     def plaquette_flux(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status):
+        self._flux_args(U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status)
         self._check(self.lib.be_plaquette_flux(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par, n_perp,
                                                _ptr(flux), _ptr(chern), _ptr(total), _ptr(status), _stream()))
 
     def plaquette_flux_noalloc(self, U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status):
+        self._flux_args(U, N, m, ldu, u_stride, n_sys, n_par, n_perp, flux, chern, total, status)
         self._check(self.lib.be_plaquette_flux_noalloc(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_par,
                                                        n_perp, _ptr(flux), _ptr(chern), _ptr(total), _ptr(status),
                                                        _stream()))
 
     def spin_sectors(self, U, N, m, ldu, u_stride, n_sys, n_k_sys, spin_diag, pso_evals, V, ldv, v_stride, status,
                      precision=BE_FP64):
+        self._ugrid(U, N, m, ldu, u_stride, n_sys * n_k_sys)
+        self._req(spin_diag, "spin_diag", n_sys * N, 8)
+        self._req(pso_evals, "pso_evals", n_sys * n_k_sys * m, 8)
+        self._ugrid(V, N, m, ldv, v_stride, n_sys * n_k_sys, "V")
+        self._req(status, "status", n_sys, 4)
         m_dn = (C.c_int32 * n_sys)()
         self._check(self.lib.be_spin_sectors(self.handle, _ptr(U), N, m, ldu, u_stride, n_sys, n_k_sys, precision,
                                              _ptr(spin_diag), _ptr(pso_evals), _ptr(V), ldv, v_stride, m_dn,
@@ -285,5 +358,10 @@ class Context:
     def zgemm_strided(self, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cm, ldc, sC, batch):
         a = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
         b = (C.c_double * 2)(complex(beta).real, complex(beta).imag)
+        ra, ca = (M, K) if opA == "N" else (K, M)
+        rb, cb = (K, N) if opB == "N" else (N, K)
+        self._req(A, "A", _span(batch, sA, ra, ca, lda), 16)
+        self._req(B, "B", _span(batch, sB, rb, cb, ldb), 16)
+        self._req(Cm, "C", _span(batch, sC, M, N, ldc), 16)
         self._check(self.lib.be_zgemm_strided(self.handle, opA.encode(), opB.encode(), M, N, K, a, _ptr(A), lda, sA,
                                               _ptr(B), ldb, sB, b, _ptr(Cm), ldc, sC, batch, _stream()))

@@ -367,6 +367,9 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             hent = self._hbuf(r0, stream)
             H = hent[0]
+            total = sum(k1 - k0 for _, k0, k1 in parts)
+            if total > H.shape[0]:  # the kernels would write past the key's buffer
+                raise ValueError(f"launch of {total} k-points exceeds the key's buffer of {H.shape[0]}")
             n = 0
             for st, k0, k1 in parts:
                 if st["event"] is not None:
