@@ -34,9 +34,13 @@ def variant_name(nt: int, loads: int) -> str:
     return f"{nt}" if loads == 0 else f"{nt}x{loads}"
 
 
-def batch_for(N: int) -> int:
-    """Matrices per timed call: about 6 GiB of c128 input, 32 .. 1536."""
-    return int(max(32, min(1536, (6 << 30) // (16 * N * N))))
+def batch_for(N: int, n_cu: int = 256) -> int:
+    """Matrices per timed call: about 6 GiB of c128 input, at most 1536, and
+    at least one matrix per compute unit up to order 4096 (the eigensolver
+    runs one workgroup per matrix: fewer matrices would time a partly idle
+    device, where the thread counts rank differently), else 32."""
+    floor = n_cu if N <= 4096 else 32
+    return int(max(floor, min(1536, (6 << 30) // (16 * N * N))))
 
 
 def time_eigh(ctx, N: int, precision: int, n_mat: int, reps: int = 2, seed: int = 0) -> float:

@@ -77,5 +77,7 @@ def test_load_tuning_applies_rows_in_order(tmp_path):
 
 def test_batch_sizes_bounded():
     assert tune.batch_for(16) == 1536
-    assert 32 <= tune.batch_for(2304) <= 1536
+    assert tune.batch_for(1024) == 384
+    assert tune.batch_for(2304) == 256          # one matrix per compute unit
+    assert tune.batch_for(2304, n_cu=80) == 80
     assert tune.batch_for(8000) == 32
