@@ -246,6 +246,8 @@ def main():
                     help="served: arrival rate as a multiple of the one-request-at-a-time capacity")
     ap.add_argument("--lanes", type=int, default=2, help="served: GPU lanes (host threads with a stream each)")
     ap.add_argument("--hbm-gib", type=int, default=150, help="served: HBM budget of admitted requests (GiB)")
+    ap.add_argument("--request-log", default=None, metavar="PATH",
+                    help="served: append one JSON line per completed request of the stream to PATH")
     ap.add_argument("--graph-lanes", type=int, default=1,
                     help="uneven: lanes (context + stream) of the captured graph's size groups")
     args = ap.parse_args()
@@ -819,7 +821,7 @@ def main_served(args):
     arrivals = S.poisson_arrivals(rate, n_req, [5, 0])
     for lane_ctx, _ in ex.lanes:
         lane_ctx.profile_enable(True)
-    eng = S.Engine(ex, hbm_budget=budget, on_event=progress)
+    eng = S.Engine(ex, hbm_budget=budget, on_event=progress, log_path=args.request_log)
     note(f"stream: {n_req} requests at {rate:.3f}/s ({args.load} x the one-at-a-time capacity)")
     wall = S.drive(eng, reqs, arrivals)
     torch.cuda.synchronize()

@@ -20,7 +20,15 @@ time. The engine
   diagonalized on one lane at a time;
 * runs a request's loop stage as soon as all its k-points are diagonalized
   (on whichever lane is free: it waits on the eigensolver's stream event),
-  frees its memory and records its latency.
+  frees its memory and records its latency;
+* stops a request that is cancelled (``Engine.cancel``) or outlives its
+  ``timeout`` (seconds from submission): a waiting one is never admitted, an
+  admitted one gets no further eigensolver launches and no loop stage, and
+  its memory is freed once its launch in flight (if any) has ended; either
+  way the request completes with ``RequestCancelled`` / ``RequestTimeout`` as
+  its error and the other requests are unaffected;
+* writes one JSON line per completed request (``log_path``): its sizes,
+  precision, kind, outcome, queueing time, latency and status flags.
 
 The engine holds no arithmetic of the method: the executor runs the library
 calls (``GpuExecutor``), or simulates their duration (``FakeExecutor``, used to
@@ -30,6 +38,7 @@ from __future__ import annotations
 
 import collections
 import itertools
+import json
 import threading
 import time
 from dataclasses import dataclass, field
@@ -43,6 +52,14 @@ KIND_WILSON, KIND_SPIN, KIND_NESTED = "wilson", "spin", "nested"
 KIND_FLUX, KIND_SPIN_FLUX = "flux", "spin_flux"
 
 
+class RequestCancelled(Exception):
+    """The request was cancelled before its result was computed."""
+
+
+class RequestTimeout(RequestCancelled):
+    """The request outlived its timeout before its result was computed."""
+
+
 @dataclass
 class Request:
     hoplist: object
@@ -54,9 +71,10 @@ class Request:
     precision: int = L.BE_FP64
     window: tuple = (0.0, 0.5)
     tag: str = ""
+    timeout: Optional[float] = None  # seconds from submission; None: no limit
     rid: int = -1
     t_submit: float = 0.0
-    t_admit: float = 0.0
+    t_admit: Optional[float] = None
     t_done: float = 0.0
     result: Optional[dict] = None
     error: Optional[BaseException] = None
@@ -92,9 +110,11 @@ class Engine:
     """Admission, batching and scheduling over the executor's lanes."""
 
     def __init__(self, executor, hbm_budget: int, clock: Callable[[], float] = time.perf_counter,
-                 on_event: Optional[Callable[[dict], None]] = None):
+                 on_event: Optional[Callable[[dict], None]] = None, log_path: Optional[str] = None):
         self.ex = executor
         self.on_event = on_event  # called after every task (progress reporting)
+        self.log_path = log_path  # JSON lines, one per completed request
+        self._log_lock = threading.Lock()
         self.budget = int(hbm_budget)
         self.clock = clock
         self._cv = threading.Condition()
@@ -106,6 +126,7 @@ class Engine:
         self.peak_used = 0
         self.completed: List[Request] = []
         self.step_log: List[dict] = []
+        self._to_log: List[Request] = []  # stopped before admission, logged outside the lock
         self._stop = False
         self._threads: List[threading.Thread] = []
 
@@ -124,15 +145,83 @@ class Engine:
         with self._cv:
             return len(self._queue) + len(self._active)
 
+    def cancel(self, req: Request) -> bool:
+        """Stop a request that has not started its loop stage. Returns False
+        when it is already finishing or done."""
+        with self._cv:
+            ok = self._stop_request(req, RequestCancelled(f"request {req.rid} cancelled"))
+            self._cv.notify_all()
+        if ok and req.done.is_set():
+            self._log(req)
+        return ok
+
+    # ------------------------------------------------------------ stopping
+    def _stop_request(self, req: Request, exc: RequestCancelled) -> bool:
+        """(Lock held.) A waiting request completes at once; an admitted one
+        takes no further k-points and skips its loop stage, and completes when
+        its launch in flight (if any) has ended."""
+        if req in self._queue:
+            self._queue.remove(req)
+            req.error = exc
+            req.t_done = self.clock()
+            self.completed.append(req)
+            req.done.set()
+            return True
+        a = self._active.get(req.rid)
+        if a is None or a["finishing"] or a["req"] is not req:
+            return False
+        if req.error is None:
+            req.error = exc
+        a["next_k"] = req.n_k
+        return True
+
+    def _expire(self):
+        """(Lock held.) Stop the requests that outlived their timeout."""
+        now = self.clock()
+        late = [r for r in list(self._queue) + [a["req"] for a in self._active.values()]
+                if r.timeout is not None and now - r.t_submit > r.timeout and r.error is None]
+        for r in late:
+            queued = r in self._queue
+            if self._stop_request(r, RequestTimeout(f"request {r.rid} exceeded its timeout of {r.timeout} s")) \
+                    and queued:
+                self._to_log.append(r)
+
+    def log_record(self, req: Request) -> dict:
+        """The request's JSON-lines record."""
+        out = req.result or {}
+        st = out.get("status")
+        status = int(np.bitwise_or.reduce(np.asarray(st, dtype=np.int64).ravel())) if st is not None else None
+        outcome = ("ok" if req.error is None else "timeout" if isinstance(req.error, RequestTimeout)
+                   else "cancelled" if isinstance(req.error, RequestCancelled) else "error")
+        return {"rid": req.rid, "tag": req.tag, "kind": req.kind, "N": req.N, "m": req.m, "k_points": req.n_k,
+                "precision": int(req.precision), "outcome": outcome,
+                "error": None if req.error is None else f"{type(req.error).__name__}: {req.error}",
+                "t_submit": req.t_submit, "queue_s": (req.t_admit - req.t_submit) if req.t_admit is not None else None,
+                "latency_s": req.latency, "status": status, "eig_status": out.get("eig_status")}
+
+    def _log(self, req: Request):
+        if not self.log_path:
+            return
+        line = json.dumps(self.log_record(req))
+        with self._log_lock, open(self.log_path, "a") as f:
+            f.write(line + "\n")
+
     def step(self, lane: int = 0) -> bool:
         """Take and run one task on `lane` in the calling thread (admission
         included). Returns False when there was nothing to do."""
         with self._cv:
             task = self._take_task()
+        self._flush_log()
         if task is None:
             return False
         self._run_task(task, lane)
         return True
+
+    def _flush_log(self):
+        with self._cv:
+            reqs, self._to_log = self._to_log, []
+        for r in reqs:
+            self._log(r)
 
     def run_until_idle(self, lane: int = 0):
         while self.step(lane) or self.pending():
@@ -162,8 +251,9 @@ class Engine:
                 while task is None and not self._stop:
                     self._cv.wait(0.05)
                     task = self._take_task()
-                if task is None:
-                    return
+            self._flush_log()
+            if task is None:
+                return
             self._run_task(task, lane)
 
     def _admit(self):
@@ -183,6 +273,7 @@ class Engine:
         k-points are all diagonalized, else an eigensolver launch of the
         oldest request whose key is not running on another lane, packed with
         the other admitted requests of that key."""
+        self._expire()
         self._admit()
         act = list(self._active.values())
         for a in act:
@@ -254,6 +345,7 @@ class Engine:
                 req.t_done = self.clock()
                 self.completed.append(req)
                 self._cv.notify_all()
+            self._log(req)
             req.done.set()
             if self.on_event:
                 self.on_event({"kind": "done", "lane": lane, "N": req.N, "request": req.rid, "tag": req.tag,

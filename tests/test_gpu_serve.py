@@ -130,3 +130,39 @@ def test_served_stream_at_full_request_sizes():
             ev, U, st = orc.eigh_grid(r.hoplist, kg[0], 0, r.m)
             W, _ = orc.wilson_matrix(U)
             assert phase_set_error(b["theta"][0, 0], orc.eigphases(W)) < 1e-6, r.tag
+
+
+def test_cancelled_request_frees_its_buffers_and_leaves_others_unchanged(tmp_path):
+    """Cancelling an admitted request on the GPU executor: no further launches
+    for it, its eigenvector grid and its key's Hamiltonian buffer are
+    released, and the other request's result is bitwise the one it has alone."""
+    gu.need_gpu()
+    import json
+    from paper_2312_13051_amd import serve as S
+    kg = syn.kplane(8, 6)
+
+    def pair():
+        h1 = syn.bhz_disordered(3, 2.0, [5, 1, 9])
+        h2 = syn.bhz_disordered(4, 2.0, [5, 1, 4])
+        return (S.Request(hoplist=h1, kappa=kg, lo=0, hi=h1.N // 2, kind=S.KIND_WILSON),
+                S.Request(hoplist=h2, kappa=kg, lo=0, hi=h2.N // 2, kind=S.KIND_WILSON))
+
+    ex = S.GpuExecutor(n_lanes=1, chunk_cap=16)
+    log = tmp_path / "req.jsonl"
+    eng = S.Engine(ex, hbm_budget=8 << 30, log_path=str(log))
+    keep, gone = pair()
+    eng.submit(gone)
+    eng.submit(keep)
+    eng.step()                        # gone's first chunk (16 of its 48 k-points)
+    assert gone.key in ex._H
+    assert eng.cancel(gone)
+    eng.run_until_idle()
+    torch.cuda.synchronize()
+    assert isinstance(gone.error, S.RequestCancelled) and gone.result is None
+    assert [s["k_points"] for s in eng.step_log if gone.rid in s["requests"]] == [16]
+    assert gone.key not in ex._H and gone.key not in ex._key_users
+    assert keep.error is None and eng.used == 0
+    (ref,) = alone(S, [pair()[0]])
+    assert np.array_equal(ref["theta"], keep.result["theta"])
+    outcomes = {r["rid"]: r["outcome"] for r in map(json.loads, log.read_text().splitlines())}
+    assert outcomes == {keep.rid: "ok", gone.rid: "cancelled"}

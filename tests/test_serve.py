@@ -103,3 +103,71 @@ def test_executor_error_is_reported_on_the_request():
     eng.run_until_idle()
     assert r.done.is_set() and isinstance(r.error, RuntimeError) and r.result is None
     assert ex.live == 0 and eng.used == 0
+
+
+def test_cancel_waiting_request_never_runs():
+    ex = S.FakeExecutor(sleep=False, chunk_k=8)
+    a, b = req(2, 4), req(2, 4)
+    eng = S.Engine(ex, hbm_budget=ex.footprint(a))      # room for one request at a time
+    eng.submit(a)
+    eng.submit(b)
+    eng.step()                                          # a admitted, its first chunk runs; b waits
+    assert eng.cancel(b) and b.done.is_set() and isinstance(b.error, S.RequestCancelled)
+    eng.run_until_idle()
+    assert a.error is None and a.result["n_k"] == a.n_k
+    assert all(b.rid not in (c[1] if c[0] == "eig" else [c[1]]) for c in ex.calls)
+    assert eng.used == 0 and ex.live == 0 and not eng.cancel(b)
+
+
+def test_cancel_admitted_request_stops_its_launches_and_frees_memory():
+    ex = S.FakeExecutor(sleep=False, chunk_k=4)
+    a, c = req(2, 4), req(3, 4)                          # 16 k-points each, different keys
+    eng = S.Engine(ex, hbm_budget=1 << 40)
+    eng.submit(a)
+    eng.submit(c)
+    eng.step()                                          # a's first 4 k-points
+    assert eng.cancel(a)
+    eng.run_until_idle()
+    assert isinstance(a.error, S.RequestCancelled) and a.result is None and a.done.is_set()
+    assert [k for k in ex.calls if k[0] == "eig" and a.rid in k[1]] == [("eig", [a.rid], 4, 0)]
+    assert ("loop", a.rid, 0) not in ex.calls           # no loop stage for a
+    assert c.error is None and c.result["n_k"] == c.n_k  # the other request is unaffected
+    assert eng.used == 0 and ex.live == 0
+
+
+def test_timeouts_stop_waiting_and_admitted_requests():
+    now = [0.0]
+    ex = S.FakeExecutor(sleep=False, chunk_k=4)
+    a, b = req(2, 4), req(2, 4)
+    a.timeout, b.timeout = 5.0, 1.0
+    eng = S.Engine(ex, hbm_budget=ex.footprint(a), clock=lambda: now[0])
+    eng.submit(a)
+    eng.submit(b)
+    eng.step()                                          # a: first chunk; b waits for memory
+    now[0] = 2.0                                        # b is past its timeout, a is not
+    eng.step()
+    assert isinstance(b.error, S.RequestTimeout) and b.done.is_set() and b.t_admit is None
+    now[0] = 10.0                                       # now a is too, mid-way through its k-points
+    eng.run_until_idle()
+    assert isinstance(a.error, S.RequestTimeout) and a.result is None
+    assert eng.used == 0 and ex.live == 0
+
+
+def test_request_log_has_one_line_per_request(tmp_path):
+    import json
+    log = tmp_path / "requests.jsonl"
+    ex = S.FakeExecutor(sleep=False, chunk_k=8)
+    a, b, c = req(2, 4), req(2, 4), req(1, 4)
+    eng = S.Engine(ex, hbm_budget=ex.footprint(a), log_path=str(log))
+    for r in (a, b, c):
+        eng.submit(r)
+    eng.step()
+    eng.cancel(b)
+    eng.run_until_idle()
+    recs = {r["rid"]: r for r in map(json.loads, log.read_text().splitlines())}
+    assert set(recs) == {a.rid, b.rid, c.rid}
+    assert recs[a.rid]["outcome"] == "ok" and recs[c.rid]["outcome"] == "ok"
+    assert recs[b.rid]["outcome"] == "cancelled" and recs[b.rid]["queue_s"] is None
+    ra = recs[a.rid]
+    assert (ra["N"], ra["m"], ra["k_points"], ra["kind"]) == (a.N, a.m, a.n_k, "wilson")
+    assert ra["latency_s"] >= ra["queue_s"] >= 0.0
