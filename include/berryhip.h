@@ -356,7 +356,13 @@ int be_profile_names(be_ctx *ctx, char *buf, size_t len);
  *                       (four waves); 0 (default) takes 8 from order 960 on.
  *                       The other panel kernels have one form each (FP64
  *                       and 256 threads: 4; 1024-thread FP32: 8), which
- *                       this knob leaves unchanged. */
+ *                       this knob leaves unchanged.
+ *   "tri_bisect_max_iter" a debug cap: bisection steps per eigenvalue after
+ *                       the multisection, 1 .. 128 (default 128, which never
+ *                       binds). A cap that stops an eigenvalue short of its
+ *                       tolerance sets BE_ST_NONCONVERGED on its matrix (a
+ *                       way to exercise that flag from the host); no
+ *                       per-order settings (be_tune_set_orders: BE_EINVAL). */
 int be_tune_set(be_ctx *ctx, const char *knob, int32_t value);
 int be_tune_get(be_ctx *ctx, const char *knob, int32_t *value);
 

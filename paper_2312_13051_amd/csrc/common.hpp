@@ -40,6 +40,7 @@ struct be_ctx {
   // tuning knobs (be_tune_set, be_tune_set_orders)
   int tune_panel_threads = 512;   // threads per matrix of the Householder panel kernel
   int tune_panel_loads = 0;       // loads in flight per lane of the 512-thread FP32 panel (0: by order)
+  int dbg_bisect_max_iter = 128;  // bisection steps per eigenvalue after the multisection (a debug cap)
   struct TuneRange {
     int n_lo, n_hi;  // orders N in [n_lo, n_hi]
     int elem;        // bytes per element of the reduction (8: mixed paths, 16: FP64), 0: both

@@ -174,6 +174,11 @@ bool find_knob(be_ctx *ctx, const std::string &k, Knob *kn) {
            "hetrd_panel_loads takes 0 (by order), 4 or 8"};
     return true;
   }
+  if (k == "tri_bisect_max_iter") {  // a debug cap (forces BE_ST_NONCONVERGED), no per-order settings
+    *kn = {&ctx->dbg_bisect_max_iter, nullptr, 128, [](int v) { return v >= 1 && v <= 128; },
+           "tri_bisect_max_iter takes 1 .. 128"};
+    return true;
+  }
   return false;
 }
 }  // namespace
@@ -191,6 +196,7 @@ int be_tune_set_orders(be_ctx *ctx, const char *knob, int32_t n_lo, int32_t n_hi
   if (!ctx || !knob) return BE_EINVAL;
   Knob kn;
   if (!find_knob(ctx, knob, &kn)) return be::set_err(ctx, BE_EINVAL, std::string("unknown tuning knob: ") + knob);
+  BE_CHECK_ARG(ctx, kn.ranges != nullptr, std::string("be_tune_set_orders: ") + knob + " has no per-order settings");
   BE_CHECK_ARG(ctx, kn.ok(value), kn.allowed);
   BE_CHECK_ARG(ctx, 1 <= n_lo && n_lo <= n_hi, "be_tune_set_orders: need 1 <= n_lo <= n_hi");
   BE_CHECK_ARG(ctx, precision == -1 || precision == BE_FP64 || precision == BE_MIXED_FP32 ||
@@ -205,7 +211,7 @@ int be_tune_clear(be_ctx *ctx, const char *knob) {
   if (!ctx || !knob) return BE_EINVAL;
   Knob kn;
   if (!find_knob(ctx, knob, &kn)) return be::set_err(ctx, BE_EINVAL, std::string("unknown tuning knob: ") + knob);
-  kn.ranges->clear();
+  if (kn.ranges) kn.ranges->clear();
   *kn.value = kn.reset;
   return BE_OK;
 }

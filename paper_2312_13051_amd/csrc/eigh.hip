@@ -524,10 +524,13 @@ __device__ bool load_tridiag(const double *d, const double *e, int64_t q, int64_
 
 // (a4) eigenvalues by bisection with Sturm counts, one lane per wanted index:
 // the selected [lo, hi), their neighbours lo-1 and hi (for the gap test) and
-// the extremes 0 and N-1 (for the scale).
+// the extremes 0 and N-1 (for the scale). At most max_it bisection steps per
+// eigenvalue after the multisection (128 does not bind: see tol_abs); an
+// eigenvalue left wider than its tolerance flags the matrix
+// BE_ST_NONCONVERGED.
 __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *e, int64_t sDE, int N, int lo, int hi,
-                                                 double bis_rel, double *evals, double *lamg, double2 *U, int ldu,
-                                                 int64_t sU, uint32_t *status) {
+                                                 double bis_rel, int max_it, double *evals, double *lamg, double2 *U,
+                                                 int ldu, int64_t sU, uint32_t *status) {
   extern __shared__ double2 tsm2[];
   double2 *sde = tsm2;                                // N: (d_i, e_{i-1}^2)
   double *sd = reinterpret_cast<double *>(sde + N);  // N
@@ -581,7 +584,11 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
   const double eps = DBL_EPSILON;
   gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm + 2.0 * pivmin;
-  const double tol_abs = bis_rel * tnorm;
+  // absolute floor eps^2 ||T||: far below any attainable accuracy, it only
+  // ends the halving at an eigenvalue (near) zero, where eps |lambda| alone
+  // would ask for ~1000 steps; from an interval of 1/257 of the Gershgorin
+  // width it takes at most ~97 steps
+  const double tol_abs = fmax(bis_rel, DBL_EPSILON * DBL_EPSILON) * tnorm;
   // multisection: Sturm counts at PT points spread over the Gershgorin
   // interval (one per thread) bracket every eigenvalue to one of PT + 1
   // subintervals, which replaces the first ~8 bisection steps of every lane
@@ -603,12 +610,15 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
       int u = 0;
       while (u < PT && s_cnt[u] <= k) ++u;
       double a = u == 0 ? gl : gl + double(u) * hstep, b = u == PT ? gu : gl + double(u + 1) * hstep;
-      for (int it = 0; it < 128; ++it) {
+      bool conv = false;
+      for (int it = 0; it <= max_it; ++it) {
         const double mid = 0.5 * (a + b);
-        if (b - a <= fmax(2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin, tol_abs) || mid <= a || mid >= b) break;
+        conv = b - a <= fmax(2.0 * eps * fmax(fabs(a), fabs(b)) + pivmin, tol_abs) || mid <= a || mid >= b;
+        if (conv || it == max_it) break;
         if (sturm_count_i(sde, N, mid, pivmin) > k) b = mid;
         else a = mid;
       }
+      if (!conv) atomicOr(&status[q], BE_ST_NONCONVERGED);
       val = 0.5 * (a + b);
     }
     slam[t] = val;
@@ -622,7 +632,7 @@ __global__ __launch_bounds__(PT) void tri_bisect(const double *d, const double *
     double g = INFINITY;
     if (lo > 0 && m > 0) g = fmin(g, lam[0] - slam[2]);
     if (hi < N && m > 0) g = fmin(g, slam[3] - lam[m - 1]);
-    if (g < 1e-9 * scale) status[q] |= BE_ST_GAP_CLOSED;
+    if (g < 1e-9 * scale) atomicOr(&status[q], BE_ST_GAP_CLOSED);
   }
 }
 
@@ -1414,7 +1424,7 @@ __global__ __launch_bounds__(PT) void refine_evals(const double2 *GU, int N, int
     double g = INFINITY;
     if (lo > 0 && m > 0) g = fmin(g, lam[lo] - lam[lo - 1]);
     if (hi < N && m > 0) g = fmin(g, lam[hi] - lam[hi - 1]);
-    if (g < 1e-9 * scale) status[q] |= BE_ST_GAP_CLOSED;
+    if (g < 1e-9 * scale) atomicOr(&status[q], BE_ST_GAP_CLOSED);
   }
 }
 
@@ -1582,8 +1592,8 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     // eigenvalues to eps |lambda|: inverse iteration must separate the
     // closely spaced ones (bis_rel > 0 would stop at bis_rel ||T||)
     const double bis_rel = 0.0;
-    hipLaunchKernelGGL(tri_bisect, dim3(nb_mat), dim3(PT), smb, stream, dd, ee, int64_t(N), N, lo, hi, bis_rel, evals,
-                       lamg, U, ldu, us, status);
+    hipLaunchKernelGGL(tri_bisect, dim3(nb_mat), dim3(PT), smb, stream, dd, ee, int64_t(N), N, lo, hi, bis_rel,
+                       ctx->dbg_bisect_max_iter, evals, lamg, U, ldu, us, status);
   }
   BE_RET_IF(check_launch(ctx, "tri_bisect"));
   if (m == 0) return BE_OK;

@@ -447,3 +447,34 @@ def test_eigh_refined_edges(N, lo, hi):
             P = Uq @ Uq.conj().T
             assert np.max(np.abs(P - V[:, lo:hi] @ V[:, lo:hi].conj().T)) < 1e-9
         assert (ev[q, 0] == ev[q, 0]) == (lo > 0) and (ev[q, m + 1] == ev[q, m + 1]) == (hi < N)
+
+
+def test_bisection_cap_flags_nonconverged():
+    """A bisection cap set from the host leaves eigenvalues short of their
+    tolerance: every matrix is flagged NONCONVERGED (the kernels still end
+    normally), and the default cap gives the uncapped results again."""
+    gu.need_gpu()
+    from paper_2312_13051_amd import BerryError
+    N, lo, hi = 40, 5, 25
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))
+    Hs = A + np.conj(np.swapaxes(A, 1, 2))
+    c = gu.ctx()
+    try:
+        ev0, U0, st0 = run_eigh(c, Hs, lo, hi)
+        assert np.all(st0 == 0)
+        c.tune_set("tri_bisect_max_iter", 1)
+        ev1, U1, st1 = run_eigh(c, Hs, lo, hi)
+        assert np.all(st1 & 32), st1                       # BE_ST_NONCONVERGED
+        assert np.all(np.isfinite(ev1[:, 1:hi - lo + 1]))
+        assert np.max(np.abs(ev1[:, 1:hi - lo + 1] - ev0[:, 1:hi - lo + 1])) > 1e-6
+        with pytest.raises(BerryError):
+            c.tune_set_orders("tri_bisect_max_iter", 1, 100, -1, 4)
+        with pytest.raises(BerryError):
+            c.tune_set("tri_bisect_max_iter", 0)
+        c.tune_clear("tri_bisect_max_iter")
+        assert c.tune_get("tri_bisect_max_iter") == 128
+        ev2, U2, st2 = run_eigh(c, Hs, lo, hi)
+        assert np.all(st2 == 0) and np.array_equal(ev2, ev0) and np.array_equal(U2, U0)
+    finally:
+        c.close()
