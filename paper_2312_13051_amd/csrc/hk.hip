@@ -11,10 +11,13 @@
 // order, so the result is deterministic.
 #include <algorithm>
 #include <cmath>
-#include <map>
-#include <tuple>
 
 #include "common.hpp"
+#include "hk_pack.hpp"
+
+static_assert(sizeof(be::hkpack::PairRC) == sizeof(int2) && sizeof(be::hkpack::EntR) == sizeof(int4) &&
+                  sizeof(be::hkpack::EntT) == sizeof(double2),
+              "packed host arrays are uploaded as int2 / int4 / double2");
 
 struct be_hk_plan {
   int device = 0;
@@ -36,19 +39,6 @@ struct be_hk_plan {
 };
 
 namespace {
-
-struct Ent {
-  int32_t i, j, R[3];
-  double tr, ti;
-};
-
-bool key_less(const Ent &a, const Ent &b) {
-  // column-major grouping: by j, then i, then R
-  return std::tie(a.j, a.i, a.R[0], a.R[1], a.R[2]) < std::tie(b.j, b.i, b.R[0], b.R[1], b.R[2]);
-}
-bool key_eq(const Ent &a, const Ent &b) {
-  return a.i == b.i && a.j == b.j && a.R[0] == b.R[0] && a.R[1] == b.R[1] && a.R[2] == b.R[2];
-}
 
 __global__ void hk_zero_c128(double2 *H, int64_t stride, int32_t ld, int32_t N, int64_t n_k) {
   int64_t per = int64_t(N) * N;
@@ -140,95 +130,23 @@ int be_hk_plan_create(be_ctx *ctx, const be_hoplist *sys_h, int32_t n_sys, be_hk
   auto *P = new be_hk_plan();
   P->device = ctx->device;
   P->n_sys = n_sys;
-  std::vector<int2> rc_all;
-  std::vector<int32_t> start_all;
-  std::vector<int4> R_all;
-  std::vector<double2> t_all;
+  be::hkpack::Packed pk;
   for (int s = 0; s < n_sys; ++s) {
     const be_hoplist &h = sys_h[s];
-    if (h.N <= 0 || h.dim < 1 || h.dim > 3 || h.nnz < 0 || (h.nnz > 0 && (!h.i || !h.j || !h.R || !h.t))) {
+    int32_t np = 0;
+    const std::string why = be::hkpack::pack_system(h.N, h.dim, h.nnz, h.i, h.j, h.R, h.t, pk, &np);
+    if (!why.empty()) {
       delete P;
-      return set_err(ctx, BE_EINVAL, "be_hk_plan_create: system " + std::to_string(s) + " has bad N/dim/nnz or null arrays");
-    }
-    std::vector<Ent> ents(static_cast<size_t>(h.nnz));
-    double tmax = 0.0;
-    for (int64_t e = 0; e < h.nnz; ++e) {
-      Ent x;
-      x.i = h.i[e];
-      x.j = h.j[e];
-      if (x.i < 0 || x.i >= h.N || x.j < 0 || x.j >= h.N) {
-        delete P;
-        return set_err(ctx, BE_EINVAL, "be_hk_plan_create: system " + std::to_string(s) + " orbital index out of range");
-      }
-      for (int d = 0; d < 3; ++d) x.R[d] = d < h.dim ? h.R[e * h.dim + d] : 0;
-      x.tr = h.t[2 * e];
-      x.ti = h.t[2 * e + 1];
-      if (!std::isfinite(x.tr) || !std::isfinite(x.ti)) {
-        delete P;
-        return set_err(ctx, BE_EINVAL, "be_hk_plan_create: system " + std::to_string(s) + " has a non-finite amplitude");
-      }
-      tmax = std::max(tmax, std::hypot(x.tr, x.ti));
-      ents[e] = x;
-    }
-    std::sort(ents.begin(), ents.end(), key_less);
-    std::vector<Ent> merged;
-    for (const Ent &x : ents) {
-      if (!merged.empty() && key_eq(merged.back(), x)) {
-        merged.back().tr += x.tr;
-        merged.back().ti += x.ti;
-      } else {
-        merged.push_back(x);
-      }
-    }
-    // Hermiticity: (i, j, R, t) needs (j, i, -R, conj t).
-    double tol = 1e-12 * std::max(tmax, 1e-300);
-    for (const Ent &x : merged) {
-      Ent key = x;
-      key.i = x.j;
-      key.j = x.i;
-      for (int d = 0; d < 3; ++d) key.R[d] = -x.R[d];
-      auto it = std::lower_bound(merged.begin(), merged.end(), key, key_less);
-      double pr = 0.0, pi = 0.0;
-      if (it != merged.end() && key_eq(*it, key)) {
-        pr = it->tr;
-        pi = it->ti;
-      }
-      if (std::hypot(pr - x.tr, pi + x.ti) > tol) {
-        delete P;
-        return set_err(ctx, BE_EINVAL, "be_hk_plan_create: system " + std::to_string(s) + " is not Hermitian (entry (" +
-                                           std::to_string(x.i) + "," + std::to_string(x.j) + ") lacks its partner)");
-      }
+      return set_err(ctx, BE_EINVAL, "be_hk_plan_create: system " + std::to_string(s) + ": " + why);
     }
     P->N.push_back(h.N);
     P->dim.push_back(h.dim);
-    P->pair_off.push_back(static_cast<int64_t>(rc_all.size()));
-    int32_t np = 0;
-    for (size_t a = 0; a < merged.size();) {
-      const Ent &x = merged[a];
-      if (x.i > x.j) {
-        ++a;
-        continue;
-      }
-      size_t b = a;
-      rc_all.push_back(make_int2(x.i, x.j));
-      start_all.push_back(static_cast<int32_t>(R_all.size()));
-      while (b < merged.size() && merged[b].i == x.i && merged[b].j == x.j) {
-        R_all.push_back(make_int4(merged[b].R[0], merged[b].R[1], merged[b].R[2], 0));
-        t_all.push_back(make_double2(merged[b].tr, merged[b].ti));
-        ++b;
-      }
-      ++np;
-      a = b;
-    }
+    P->pair_off.push_back(static_cast<int64_t>(pk.rc.size()) - np);
     P->n_pairs.push_back(np);
   }
-  start_all.push_back(static_cast<int32_t>(R_all.size()));
-  if (R_all.size() > size_t(INT32_MAX)) {
-    delete P;
-    return set_err(ctx, BE_EINVAL, "be_hk_plan_create: too many entries");
-  }
-  P->total_pairs = static_cast<int64_t>(rc_all.size());
-  P->total_ents = static_cast<int64_t>(R_all.size());
+  pk.start.push_back(static_cast<int32_t>(pk.R.size()));
+  P->total_pairs = static_cast<int64_t>(pk.rc.size());
+  P->total_ents = static_cast<int64_t>(pk.R.size());
   auto up = [&](void **dst, const void *src, size_t bytes) -> int {
     size_t b = std::max<size_t>(bytes, 16);
     if (hipMalloc(dst, b) != hipSuccess) return BE_ENOMEM;
@@ -236,10 +154,10 @@ int be_hk_plan_create(be_ctx *ctx, const be_hoplist *sys_h, int32_t n_sys, be_hk
     return BE_OK;
   };
   int rc = 0;
-  rc |= up(reinterpret_cast<void **>(&P->d_pair_rc), rc_all.data(), rc_all.size() * sizeof(int2));
-  rc |= up(reinterpret_cast<void **>(&P->d_pair_start), start_all.data(), start_all.size() * sizeof(int32_t));
-  rc |= up(reinterpret_cast<void **>(&P->d_ent_R), R_all.data(), R_all.size() * sizeof(int4));
-  rc |= up(reinterpret_cast<void **>(&P->d_ent_t), t_all.data(), t_all.size() * sizeof(double2));
+  rc |= up(reinterpret_cast<void **>(&P->d_pair_rc), pk.rc.data(), pk.rc.size() * sizeof(int2));
+  rc |= up(reinterpret_cast<void **>(&P->d_pair_start), pk.start.data(), pk.start.size() * sizeof(int32_t));
+  rc |= up(reinterpret_cast<void **>(&P->d_ent_R), pk.R.data(), pk.R.size() * sizeof(int4));
+  rc |= up(reinterpret_cast<void **>(&P->d_ent_t), pk.t.data(), pk.t.size() * sizeof(double2));
   rc |= up(reinterpret_cast<void **>(&P->d_sys_dim), P->dim.data(), P->dim.size() * sizeof(int32_t));
   rc |= up(reinterpret_cast<void **>(&P->d_sys_pair_off), P->pair_off.data(), P->pair_off.size() * sizeof(int64_t));
   rc |= up(reinterpret_cast<void **>(&P->d_sys_npairs), P->n_pairs.data(), P->n_pairs.size() * sizeof(int32_t));
