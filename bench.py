@@ -246,6 +246,8 @@ def main():
                     help="served: arrival rate as a multiple of the one-request-at-a-time capacity")
     ap.add_argument("--lanes", type=int, default=2, help="served: GPU lanes (host threads with a stream each)")
     ap.add_argument("--hbm-gib", type=int, default=150, help="served: HBM budget of admitted requests (GiB)")
+    ap.add_argument("--types", default=None, metavar="T1,T2",
+                    help="served: only these request types (of bhz8, bhz12, bhz16, bhz24, w96), in the stream's order")
     ap.add_argument("--request-log", default=None, metavar="PATH",
                     help="served: append one JSON line per completed request of the stream to PATH")
     ap.add_argument("--graph-lanes", type=int, default=1,
@@ -307,13 +309,7 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda", 0)
-    if args.copy_calibration_mb:
-        nb = args.copy_calibration_mb << 20
-        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args.copy_calibration_mb)
     ctx = L.Context(0)
     tuning = {"table": ctx.tuning}
     for kv in args.tune:
@@ -726,13 +722,34 @@ def _oracle_served_segment(args):
     return (kind, req, n_pts, time.perf_counter() - t0, th)
 
 
+def copy_calibration(mb: int):
+    """One plain device copy of mb MiB (its FETCH_SIZE and WRITE_SIZE calibrate
+    the byte counters of a rocprofv3 counter run); nothing when mb is 0."""
+    if not mb:
+        return
+    import torch
+    nb = mb << 20
+    src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main_served(args):
     """Served stream: Poisson arrivals of Wilson-loop requests (BHZ supercells
     L in {8, 12, 16, 24} with W ~ U[0, 4], and the 96-orbital model), 32 x 32
     k-grids, continuous batching with HBM admission on two GPU lanes."""
     from collections import Counter
     n_req = args.requests
-    kinds = syn.served_types(n_req, [5, 0])
+    if args.types:
+        want = args.types.split(",")
+        bad = [t for t in want if t not in syn.SERVED_TYPES]
+        if bad:
+            raise SystemExit(f"unknown served types {bad}; known: {', '.join(syn.SERVED_TYPES)}")
+        kinds = [k for k in syn.served_types(n_req * len(syn.SERVED_TYPES), [5, 0]) if k in want][:n_req]
+    else:
+        kinds = syn.served_types(n_req, [5, 0])
     first = {}
     for q, k in enumerate(kinds):
         first.setdefault(k, q)
@@ -744,7 +761,7 @@ def main_served(args):
     seg = {"w96": SERVED_GRID, "bhz8": SERVED_GRID, "bhz12": 6, "bhz16": 2}
     sample = [(k, first[k], 0, seg[k]) for k in seg if k in first]
     cpu, oracle_lines = None, {}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and sample:
         res, cdt = cpu_baseline(sample, min(workers, len(sample)), _oracle_served_segment, warm_with_sample=False)
         per_k = {}
         for kind, req, n_pts, secs, th in res:
@@ -778,6 +795,7 @@ def main_served(args):
         sys.exit(1)
     mixed = args.precision in ("mixed", "refined")
     kg = syn.kplane(SERVED_GRID, SERVED_GRID)
+    copy_calibration(args.copy_calibration_mb)
 
     def make(q):
         hl = _served_request_model(kinds[q], q)
@@ -872,7 +890,17 @@ def main_served(args):
         ach = byts / (ms_tot * 1e-3) / 1e9
         roof.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": round(byts / launches, 1),
-                     "note": "durations of launches that may overlap with the other lane's work"})
+                     "note": "durations of launches that may overlap with the other lane's work; the stream's "
+                             "launches span several orders, so traffic per launch is given for the dominant "
+                             "order's launches (counters of order-2304 requests) rather than for the mix"})
+        prof24 = os.path.join(ROOT, "profiles", "hetrd_panel_served_bhz24_mixed.md")
+        t24 = traffic_from_profile(prof24, os.path.join(ROOT, "paper_2312_13051_amd", "csrc", "eigh.hip"),
+                                   "mixed") if mixed else None
+        if t24 is not None:
+            a24 = hetrd_panel_bytes(2304, 256, 8) / ((2304 + NB - 1) // NB)  # one panel of 256 matrices
+            roof["order_2304_counters"] = {"profile": os.path.relpath(prof24, ROOT), "traffic_bytes_per_launch": t24,
+                                           "algorithmic_bytes_per_launch": round(a24, 1),
+                                           "traffic_over_algorithmic": round(t24 / a24, 3)}
     kernels = {k: {"ms": round(v[0], 1), "launches": v[1]} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "k-point solves/s", "n_gpus": 1,

@@ -54,9 +54,10 @@ def test_traffic_lookup_follows_digest_and_precision(tmp_path):
     assert bench.traffic_from_profile(str(tmp_path / "missing.md"), src, "mixed") is None
 
 
-def test_committed_profile_matches_the_panel_source():
+@pytest.mark.parametrize("name", ["hetrd_panel_bhz400_mixed.md", "hetrd_panel_served_bhz24_mixed.md"])
+def test_committed_profile_matches_the_panel_source(name):
     src = os.path.join(ROOT, "paper_2312_13051_amd", "csrc", "eigh.hip")
-    prof = os.path.join(ROOT, "profiles", "hetrd_panel_bhz400_mixed.md")
+    prof = os.path.join(ROOT, "profiles", name)
     assert bench.traffic_from_profile(prof, src, "mixed") is not None
 
 
