@@ -65,3 +65,21 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_served_gemm_flops_and_phase_summary():
+    import numpy as np
+    from types import SimpleNamespace as NS
+    REF = 2
+    a = NS(N=64, m=32, n_k=12, kappa=np.zeros((3, 4, 3)), precision=1)
+    b = NS(N=96, m=48, n_k=12, kappa=np.zeros((3, 4, 3)), precision=REF)   # refined: all bands in the eigensolver
+    fl = bench.served_gemm_flops([a, b], REF)
+    assert fl["her2k"] == bench.eigh_gemm_flops("her2k", 64, 32, 12) + bench.eigh_gemm_flops("her2k", 96, 96, 12)
+    assert fl["unmtr"] == bench.eigh_gemm_flops("unmtr", 64, 32, 12) + bench.eigh_gemm_flops("unmtr", 96, 96, 12)
+    assert fl["overlap"] == 8.0 * (64 * 32 * 32 + 96 * 48 * 48) * 12
+    assert fl["chain"] == 8.0 * (32 ** 3 + 48 ** 3) * 3 * 3           # (n_par - 1) products per line, 3 lines
+    # the summary: rates against the peak of each tag's type, time-weighted fraction
+    s = bench.gemm_phase_summary({"her2k": 157.3e12, "overlap": 78.6e12 / 2, "absent": 1.0},
+                                 {"her2k": 2000.0, "overlap": 1000.0}, ("her2k",), scale=2.0)
+    assert s["per_tag"]["her2k"]["frac"] == 1.0 and s["per_tag"]["overlap"]["frac"] == 1.0
+    assert "absent" not in s["per_tag"] and s["frac_of_mfma_peak"] == 1.0
