@@ -292,6 +292,9 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: berryhip has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven" and args.precision not in (None, "mixed"):
+        print("[bench] the uneven workload times the mixed and the FP64 path on the same batch (value and "
+              "fp64_value); --precision is not used", file=sys.stderr, flush=True)
     if args.precision is None:
         args.precision = "mixed"
     if args.workload in ("bbh_disorder", "choti_nested"):
