@@ -282,6 +282,9 @@ def main():
                     help="served: arrival rate as a multiple of the one-request-at-a-time capacity")
     ap.add_argument("--lanes", type=int, default=2, help="served: GPU lanes (host threads with a stream each)")
     ap.add_argument("--hbm-gib", type=int, default=150, help="served: HBM budget of admitted requests (GiB)")
+    ap.add_argument("--policy", choices=["fifo", "srpt"], default="srpt",
+                    help="served: which admitted request's k-points go first (oldest, or least remaining work: "
+                         "the default, measured to halve p50 latency at the same throughput)")
     ap.add_argument("--types", default=None, metavar="T1,T2",
                     help="served: only these request types (of bhz8, bhz12, bhz16, bhz24, w96), in the stream's order")
     ap.add_argument("--request-log", default=None, metavar="PATH",
@@ -866,7 +869,7 @@ def main_served(args):
     arrivals = S.poisson_arrivals(rate, n_req, [5, 0])
     for lane_ctx, _ in ex.lanes:
         lane_ctx.profile_enable(True)
-    eng = S.Engine(ex, hbm_budget=budget, on_event=progress, log_path=args.request_log)
+    eng = S.Engine(ex, hbm_budget=budget, on_event=progress, log_path=args.request_log, policy=args.policy)
     note(f"stream: {n_req} requests at {rate:.3f}/s ({args.load} x the one-at-a-time capacity)")
     wall = S.drive(eng, reqs, arrivals)
     torch.cuda.synchronize()
@@ -944,7 +947,7 @@ def main_served(args):
                                (PRECISION_TEXT["mixed"] + " (refined mixed path for the 96-orbital model)"
                                 if args.precision == "mixed" else PRECISION_TEXT[args.precision]),
                    "requests": n_req, "k_points": total_k, "types": dict(Counter(kinds)),
-                   "arrival_rate_per_s": round(rate, 4), "load": args.load, "lanes": args.lanes,
+                   "arrival_rate_per_s": round(rate, 4), "load": args.load, "lanes": args.lanes, "policy": args.policy,
                    "hbm_budget_gib": args.hbm_gib},
         "roofline": roof,
         "gemm_phases": gemm_phases,

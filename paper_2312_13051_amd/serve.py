@@ -110,7 +110,11 @@ class Engine:
     """Admission, batching and scheduling over the executor's lanes."""
 
     def __init__(self, executor, hbm_budget: int, clock: Callable[[], float] = time.perf_counter,
-                 on_event: Optional[Callable[[dict], None]] = None, log_path: Optional[str] = None):
+                 on_event: Optional[Callable[[dict], None]] = None, log_path: Optional[str] = None,
+                 policy: str = "fifo"):
+        if policy not in ("fifo", "srpt"):
+            raise ValueError("policy must be 'fifo' (oldest request first) or 'srpt' (least remaining work first)")
+        self.policy = policy
         self.ex = executor
         self.on_event = on_event  # called after every task (progress reporting)
         self.log_path = log_path  # JSON lines, one per completed request
@@ -270,9 +274,11 @@ class Engine:
 
     def _take_task(self):
         """Next task (caller holds the lock): a loop stage of a request whose
-        k-points are all diagonalized, else an eigensolver launch of the
-        oldest request whose key is not running on another lane, packed with
-        the other admitted requests of that key."""
+        k-points are all diagonalized, else an eigensolver launch of a request
+        whose key is not running on another lane (the oldest one, or with
+        policy "srpt" the one with the least remaining eigensolver work,
+        pending k-points times N^3), packed with the other admitted requests of
+        that key."""
         self._expire()
         self._admit()
         act = list(self._active.values())
@@ -280,7 +286,10 @@ class Engine:
             if not a["finishing"] and a["inflight"] == 0 and a["next_k"] >= a["req"].n_k:
                 a["finishing"] = True
                 return ("loop", a)
-        for a in act:
+        order = act
+        if self.policy == "srpt":
+            order = sorted(act, key=lambda a: (a["req"].n_k - a["next_k"]) * float(a["req"].N) ** 3)
+        for a in order:
             r = a["req"]
             if a["next_k"] >= r.n_k or r.key in self._busy_keys:
                 continue

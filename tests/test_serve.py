@@ -171,3 +171,22 @@ def test_request_log_has_one_line_per_request(tmp_path):
     ra = recs[a.rid]
     assert (ra["N"], ra["m"], ra["k_points"], ra["kind"]) == (a.N, a.m, a.n_k, "wilson")
     assert ra["latency_s"] >= ra["queue_s"] >= 0.0
+
+
+def test_srpt_policy_serves_the_smallest_remaining_work_first():
+    ex = S.FakeExecutor(sleep=False, chunk_k=8)
+    big, small = req(3, 4), req(1, 4)              # same k-points, N = 36 against N = 4
+    with pytest.raises(ValueError):
+        S.Engine(ex, hbm_budget=1 << 40, policy="lifo")
+    eng = S.Engine(ex, hbm_budget=1 << 40, policy="srpt")
+    eng.submit(big)
+    eng.submit(small)
+    eng.run_until_idle()
+    eigs = [c[1] for c in ex.calls if c[0] == "eig"]
+    assert eigs[0] == [small.rid] and eigs[1] == [small.rid]   # the small request's two chunks go first
+    assert small.t_done <= big.t_done and all(r.error is None for r in (big, small))
+    ex2 = S.FakeExecutor(sleep=False, chunk_k=8)
+    eng2 = S.Engine(ex2, hbm_budget=1 << 40)       # fifo: the older request first
+    b2, s2 = eng2.submit(req(3, 4)), eng2.submit(req(1, 4))
+    eng2.run_until_idle()
+    assert [c[1] for c in ex2.calls if c[0] == "eig"][0] == [b2.rid]
