@@ -1,0 +1,94 @@
+"""Seeded sweep of small random cases against the oracle (FP64 path): random
+models (two-band, BHZ supercells with disorder, many-orbital random ones),
+band windows away from half filling, k-planes with offsets, integer but
+oblique loop directions and degenerate grid shapes (one loop point, one
+transverse line). Every case whose windows are gapped on the whole grid is
+compared: Wilson phases and windings, plaquette fluxes and Chern numbers,
+and (on larger grids) the nested loop's phases."""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import berry as orc
+from paper_2312_13051_amd import _lib as L, pipeline as PL
+from tests import gpu_util as gu
+from tests.phase_metrics import circ_dist, phase_set_error
+
+pytestmark = pytest.mark.gpu
+
+
+def case(seed):
+    rng = np.random.default_rng([77, seed])
+    kind = seed % 4
+    if kind == 0:
+        hl = syn.qwz(float(rng.uniform(-2.5, 2.5)))
+    elif kind == 1:
+        hl = syn.bhz_disordered(int(rng.integers(2, 4)), float(rng.uniform(0.0, 3.0)), [77, seed, 1])
+    elif kind == 2:
+        hl = syn.wannier_like(int(rng.choice([6, 10, 14])), [77, seed, 2], r_max=2.0)
+    else:  # BBH: gapped Wannier bands, so the nested loop has a fixed sector
+        hl = syn.bbh(float(rng.uniform(0.1, 0.8)), 1.0)
+    N = hl.N
+    if kind == 1:  # the supercell's gap at half filling; the window may start above the bottom
+        lo, hi = int(rng.choice([0, 2])), N // 2
+    elif kind == 3:
+        lo, hi = 0, 2
+    else:
+        lo = int(rng.integers(0, N // 2))
+        hi = int(rng.integers(lo + 1, N))
+    if seed % 6 == 5:  # degenerate grid shapes: one loop point, or one transverse line
+        n_par, n_perp = [(1, 4), (6, 1), (2, 3)][(seed // 6) % 3]
+    else:
+        n_par, n_perp = int(rng.choice([5, 8, 12])), int(rng.choice([4, 6]))
+    e_par, e_perp = [((1, 0, 0), (0, 1, 0)), ((1, 1, 0), (0, 1, 0)), ((0, 1, 0), (1, 0, 0)),
+                     ((1, -1, 0), (1, 0, 0))][seed % 4]
+    k0 = tuple(rng.uniform(-0.5, 0.5, size=3) * np.array([1, 1, 0]))
+    kg = syn.kplane(n_par, n_perp, e_par=e_par, e_perp=e_perp, k0=k0)
+    return hl, lo, hi, kg
+
+
+def gapped(hl, lo, hi, kg, tol=2e-2):
+    """The window [lo, hi) is separated from the other bands by tol on every k-point."""
+    ev = np.stack([np.linalg.eigvalsh(orc.bloch_hamiltonian(hl, k)) for k in kg.reshape(-1, 3)])
+    g = np.inf
+    if lo > 0:
+        g = min(g, float(np.min(ev[:, lo] - ev[:, lo - 1])))
+    if hi < hl.N:
+        g = min(g, float(np.min(ev[:, hi] - ev[:, hi - 1])))
+    return g > tol
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_cases_match_the_oracle(seed):
+    gu.need_gpu()
+    hl, lo, hi, kg = case(seed)
+    if not gapped(hl, lo, hi, kg):
+        pytest.skip("window not gapped on this grid (phases undetermined)")
+    c = gu.ctx()
+    try:
+        g = PL.eig_grid(c, c.hk_plan([hl]), 0, 1, kg, lo, hi, L.BE_FP64)
+        w = PL.wilson(c, g)
+        ref = orc.wilson_surface(hl, kg, lo, hi)
+        st = int(w["status"].cpu().numpy()[0])
+        assert bool(st & L.ST_OVERLAP_SINGULAR) == bool(ref["status"] & orc.OVERLAP_SINGULAR)
+        assert phase_set_error(w["theta"].cpu().numpy()[0], ref["theta"]) < 1e-9
+        if not (ref["status"] & orc.WINDING_UNRESOLVED):
+            assert int(w["winding"].cpu().numpy()[0]) == ref["winding"]
+        n_perp, n_par = kg.shape[:2]
+        if n_par >= 2 and n_perp >= 3:
+            f = PL.flux(c, g)
+            rf = orc.plaquette_flux(hl, kg, lo, hi)
+            if not (rf["status"] & orc.OVERLAP_SINGULAR):
+                assert float(np.max(circ_dist(f["flux"].cpu().numpy()[0], rf["flux"]))) < 1e-9
+                if not rf["status"] & orc.WINDING_UNRESOLVED:
+                    assert int(f["chern"].cpu().numpy()[0]) == rf["chern"]
+        if n_par >= 5 and n_perp >= 3 and hi - lo >= 2:
+            nw = PL.nested(c, g)
+            rn = orc.nested_from_grid(ref["U"])
+            if not rn["status"] & orc.WANNIER_GAP:
+                assert nw["s"][0] == rn["s"]
+                s = rn["s"]
+                assert phase_set_error(nw["theta"].cpu().numpy()[0, :, :s], rn["theta"]) < 1e-8
+                assert float(circ_dist(2 * np.pi * nw["p_mean"].cpu().numpy()[0], 2 * np.pi * rn["p_mean"])) < 1e-8
+    finally:
+        c.close()
