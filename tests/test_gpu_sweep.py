@@ -92,3 +92,36 @@ def test_random_cases_match_the_oracle(seed):
                 assert float(circ_dist(2 * np.pi * nw["p_mean"].cpu().numpy()[0], 2 * np.pi * rn["p_mean"])) < 1e-8
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_spin_resolved_cases_match_the_oracle(seed):
+    """Spin-resolved loops of disordered BHZ supercells on offset, oblique
+    k-planes: sector sizes, sector phases and C_dn, C_up, C_s."""
+    gu.need_gpu()
+    rng = np.random.default_rng([78, seed])
+    hl = syn.bhz_disordered(int(rng.integers(2, 4)), float(rng.uniform(0.0, 3.0)), [78, seed])
+    lo, hi = 0, hl.N // 2
+    e_par, e_perp = [((1, 0, 0), (0, 1, 0)), ((1, 1, 0), (0, 1, 0))][seed % 2]
+    kg = syn.kplane(int(rng.choice([6, 10])), int(rng.choice([4, 6])), e_par=e_par, e_perp=e_perp,
+                    k0=tuple(rng.uniform(-0.5, 0.5, size=3) * np.array([1, 1, 0])))
+    if not gapped(hl, lo, hi, kg):
+        pytest.skip("window not gapped on this grid (phases undetermined)")
+    sd = syn.bhz_spin_diag(hl)
+    ref = orc.spin_resolved_wilson(hl, sd, kg, lo, hi)
+    if ref["status"] & orc.PSO_GAP:
+        pytest.skip("projected spin spectrum not gapped")
+    c = gu.ctx()
+    try:
+        g = PL.eig_grid(c, c.hk_plan([hl]), 0, 1, kg, lo, hi, L.BE_FP64)
+        out = PL.spin(c, g, sd[None])
+        md = ref["m_minus"]
+        assert out["m_dn"] == [md]
+        assert phase_set_error(out["theta_dn"].cpu().numpy()[0, :, :md], ref["theta_dn"]) < 1e-9
+        assert phase_set_error(out["theta_up"].cpu().numpy()[0, :, :hi - lo - md], ref["theta_up"]) < 1e-9
+        if not ref["status"] & orc.WINDING_UNRESOLVED:
+            assert int(out["C_dn"].cpu().numpy()[0]) == ref["C_dn"]
+            assert int(out["C_up"].cpu().numpy()[0]) == ref["C_up"]
+            assert float(out["C_s"].cpu().numpy()[0]) == ref["C_s"]
+    finally:
+        c.close()
