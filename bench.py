@@ -40,12 +40,16 @@ PRECISION_TEXT = {
     "mixed": "mixed path: FP32 Householder reduction and back-transformation on MFMA, FP64 elsewhere",
     "refined": "refined mixed path: FP32 Householder reduction and back-transformation on MFMA for all bands, "
                "FP64 first-order correction of the occupied subspace from the other bands on MFMA, FP64 elsewhere",
+    "bf16x": "split-bf16 mixed path: FP32 Householder panels, trailing updates and back-transformation as "
+             "split-bf16 products on the bf16 matrix cores (three per real product, FP32 accumulation), FP64 "
+             "elsewhere",
 }
 L_SC, N_PAR, N_PERP = 10, 24, 24
 W_VALUES = (0.0, 1.0, 2.0, 3.0)
 REALIZATIONS = 16
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 MFMA
 FP32_PEAK_TFLOPS = 157.3
 NB = 32  # panel width of the Householder reduction
 
@@ -168,7 +172,7 @@ def served_gemm_flops(reqs, refined_code):
     return out
 
 
-def gemm_phase_summary(flops, prof_ms, fp32_tags, scale=1.0):
+def gemm_phase_summary(flops, prof_ms, fp32_tags, scale=1.0, bf16_tags=()):
     """Per tag: algorithmic flops over the timed milliseconds (prof_ms[tag],
     divided by scale), against the MFMA peak of the tag's arithmetic type; and
     the time-weighted fraction over all tags."""
@@ -178,7 +182,7 @@ def gemm_phase_summary(flops, prof_ms, fp32_tags, scale=1.0):
         if tag not in prof_ms or fl <= 0:
             continue
         t = prof_ms[tag] / scale * 1e-3
-        pk = FP32_PEAK_TFLOPS if tag in fp32_tags else FP64_PEAK_TFLOPS
+        pk = BF16_PEAK_TFLOPS if tag in bf16_tags else FP32_PEAK_TFLOPS if tag in fp32_tags else FP64_PEAK_TFLOPS
         gemm[tag] = {"tflops": round(fl / t / 1e12, 2), "peak": pk, "frac": round(fl / t / 1e12 / pk, 4)}
         w_sum += fl / (pk * 1e12)
         t_sum += t
@@ -267,11 +271,12 @@ def main():
     ap.add_argument("--chunk-systems", type=int, default=8)
     ap.add_argument("--cpu-lines", type=int, default=32, help="oracle sample size (transverse lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "mixed", "refined"], default=None,
+    ap.add_argument("--precision", choices=["fp64", "mixed", "refined", "bf16x"], default=None,
                     help="eigensolver precision (mixed: FP32 reduction/back-transformation, FP64 elsewhere; "
                          "refined: the mixed path for all bands, then an FP64 correction of the occupied "
-                         "subspace; phases are checked against the FP64 oracle at 1e-6 rad in every run). "
-                         "Default: mixed")
+                         "subspace; bf16x: the mixed path with split-bf16 products in the trailing updates and "
+                         "the back-transformation, spin_wilson only; phases are checked against the FP64 oracle "
+                         "at 1e-6 rad in every run). Default: mixed")
     ap.add_argument("--systems", type=int, default=0, help="profile a subset: first N systems only (0 = all 64)")
     ap.add_argument("--tune", action="append", default=[], metavar="KNOB=VALUE",
                     help="set a library tuning knob (be_tune_set) before timing")
@@ -295,6 +300,8 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: berryhip has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.precision == "bf16x" and args.workload not in ("spin_wilson", "spin_flux"):
+        raise SystemExit("--precision bf16x is measured on the spin_wilson and spin_flux workloads only")
     if args.workload == "uneven" and args.precision not in (None, "mixed"):
         print("[bench] the uneven workload times the mixed and the FP64 path on the same batch (value and "
               "fp64_value); --precision is not used", file=sys.stderr, flush=True)
@@ -366,9 +373,10 @@ def main():
     nmat = cs * n_k
     # mixed: FP32 reduction and back-transformation; refined: the same for all
     # bands of an FP32 copy of the FP64 H, then the FP64 subspace correction
-    mixed = args.precision in ("mixed", "refined")
-    hdt, hcode = (torch.complex64, L.BE_C64) if args.precision == "mixed" else (torch.complex128, L.BE_C128)
-    prec = {"fp64": L.BE_FP64, "mixed": L.BE_MIXED_FP32, "refined": L.BE_MIXED_FP32_REFINED}[args.precision]
+    mixed = args.precision in ("mixed", "refined", "bf16x")
+    prec = {"fp64": L.BE_FP64, "mixed": L.BE_MIXED_FP32, "refined": L.BE_MIXED_FP32_REFINED,
+            "bf16x": L.BE_MIXED_BF16X}[args.precision]
+    hdt, hcode = (torch.complex64, L.BE_C64) if L.c64_input(prec) else (torch.complex128, L.BE_C128)
     H = torch.empty((nmat, N, N), dtype=hdt, device=dev)
     U = torch.empty((nmat, m, N), dtype=torch.complex128, device=dev)
     ev = torch.empty((nmat, m + 2), dtype=torch.float64, device=dev)
@@ -476,7 +484,12 @@ def main():
     kernels = {k: {"ms_per_step": round(v[0] / steps, 2), "launches_per_step": v[1] // steps} for k, v in
                sorted(prof.items(), key=lambda kv: -kv[1][0])}
     # GEMM phases against the MFMA peak of their arithmetic type
-    gemm_phases = gemm_phase_summary(flops, {k: v[0] for k, v in prof.items()}, fp32_tags, scale=steps)
+    bf16_tags = ("her2k", "unmtr", "pso_her2k", "pso_unmtr") if args.precision == "bf16x" else ()
+    gemm_phases = gemm_phase_summary(flops, {k: v[0] for k, v in prof.items()}, fp32_tags, scale=steps,
+                                     bf16_tags=bf16_tags)
+    if bf16_tags:
+        gemm_phases["note"] += ("; bf16x tags: FP32-equivalent flops against the dense bf16 peak (the split "
+                                "takes three bf16 products per real product)")
 
     # ---- phase error of the sampled lines against the FP64 oracle
     max_err = None
@@ -526,7 +539,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
+        "dtype": ("bf16x3+f32+f64" if args.precision == "bf16x" else "f32+f64") if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "BHZ 10x10 supercell (N=400) with Anderson disorder W in {0,1,2,3} x 16 seeded "
                                "realizations, 24x24 supercell k-grid, half filling, " +

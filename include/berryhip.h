@@ -78,6 +78,15 @@ extern "C" {
                            in the FP32 error, so that error enters squared),
                            FP64 Rayleigh-quotient eigenvalues and FP64
                            orthonormalization; H (BE_C128) is not modified   */
+#define BE_MIXED_BF16X 3 /* BE_MIXED_FP32 with the trailing updates and the
+                           back-transformation on the bf16 matrix cores: each
+                           FP32 operand split into two bf16 parts, three
+                           products per real product (x_hi y_hi + x_hi y_lo +
+                           x_lo y_hi), FP32 accumulation; ~2^-16 relative error
+                           per product instead of FP32's 2^-24. Accuracy is
+                           stated, not assumed: be_eigh_batched (BE_C64 input)
+                           and the spin paths' eigensolver of the projected
+                           spin operator accept it                          */
 
 /* ---- overlap mode ---- */
 #define BE_OVL_POLAR 0 /* each overlap replaced by its unitary polar factor */
@@ -258,9 +267,9 @@ int be_nested_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t l
  *   (PSO_GAP if min |mu| < 1e-6 or the count of mu < 0 varies).
  * precision selects the eigensolver of A: BE_FP64, or BE_MIXED_FP32 (A
  * rounded to c64, FP32 reduction and back-transformation, FP64 tridiagonal
- * solve and orthonormalization); BE_MIXED_FP32_REFINED (for U from the
- * refined eigensolver) takes the FP64 solver; A, U and everything after are
- * FP64.
+ * solve and orthonormalization), BE_MIXED_BF16X (the same with split-bf16
+ * products in its GEMMs); BE_MIXED_FP32_REFINED (for U from the refined
+ * eigensolver) takes the FP64 solver; A, U and everything after are FP64.
  * Synchronizes the stream: the sector sizes are read back, and the
  * eigensolver and the polar steps read back their convergence. */
 int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t ldu, int64_t u_stride,

@@ -18,7 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libberryhip.so")
 
 BE_OK, BE_EINVAL, BE_ENOMEM, BE_EHIP, BE_ENOTIMPL = 0, -1, -2, -3, -4
 BE_C128, BE_C64 = 0, 1
-BE_FP64, BE_MIXED_FP32, BE_MIXED_FP32_REFINED = 0, 1, 2
+BE_FP64, BE_MIXED_FP32, BE_MIXED_FP32_REFINED, BE_MIXED_BF16X = 0, 1, 2, 3
+
+
+def c64_input(precision: int) -> bool:
+    """The eigensolver takes c64 Hamiltonians for this precision (the mixed
+    paths that reduce in FP32 from an FP32 input), else c128."""
+    return precision in (BE_MIXED_FP32, BE_MIXED_BF16X)
 BE_OVL_POLAR, BE_OVL_RAW = 0, 1
 ST_GAP_CLOSED, ST_OVERLAP_SINGULAR, ST_WINDING_UNRESOLVED = 1, 2, 4
 ST_PSO_GAP, ST_WANNIER_GAP, ST_NONCONVERGED, ST_NAN_INF = 8, 16, 32, 64

@@ -277,6 +277,9 @@ struct CGemm {
   bool herm = false;  // as in ZGemm
   bool herm_mirror = true;
   const int *act = nullptr;  // as in ZGemm
+  // products on the bf16 matrix cores with each FP32 operand split into two
+  // bf16 parts (three products per real product, ~2^-16 relative error)
+  bool bf16x3 = false;
 };
 int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream);
 
@@ -313,6 +316,7 @@ int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_
               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream,
               double clu_rel = 1e-12);
 int eigh_mixed(be_ctx *ctx, float2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
-               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream);
+               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream,
+               bool bf16x3 = false);
 
 }  // namespace be

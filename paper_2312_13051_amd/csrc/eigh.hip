@@ -1493,10 +1493,12 @@ struct GemmOf<float> {
 // Householder reduction and back-transformation (double: FP64 path, float:
 // mixed path); the tridiagonal solve and the re-orthonormalization are FP64.
 // Hin: nb_mat matrices of CT<T>::c; U: c128 output.
+// bf16x3 (T = float only): the trailing update and the back-transformation
+// take the split-bf16 products of the complex GEMM.
 template <typename T>
 static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ms, int64_t nb_mat, int lo, int hi,
                       double *evals, double2 *U, int ldu, int64_t us, uint32_t *status, hipStream_t stream,
-                      double clu_rel = kCluRel) {
+                      double clu_rel = kCluRel, bool bf16x3 = false) {
   typedef typename CT<T>::c C;
   typedef typename GemmOf<T>::type G;
   const int m = hi - lo;
@@ -1579,6 +1581,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
       g.tag = "her2k";
       g.herm = true;
       g.herm_mirror = false;  // the panel reads the lower triangle only
+      if constexpr (std::is_same<G, CGemm>::value) g.bf16x3 = bf16x3;
       BE_RET_IF(GemmOf<T>::run(ctx, g, stream));
     }
   }
@@ -1725,6 +1728,7 @@ static int eigh_chunk(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t 
     g.beta = mk<C>(beta, 0.0);
     g.batch = nb_mat;
     g.tag = "unmtr";
+    if constexpr (std::is_same<G, CGemm>::value) g.bf16x3 = bf16x3;
     return GemmOf<T>::run(ctx, g, stream);
   };
   const int64_t sXY = int64_t(NB2) * std::max(m, 1);
@@ -1849,7 +1853,7 @@ static int64_t eigh_sub_batch(be_ctx *ctx, int N, size_t per, size_t reusable, i
 template <typename T>
 static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo,
                     int band_hi, double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status,
-                    hipStream_t stream, double clu_rel = kCluRel) {
+                    hipStream_t stream, double clu_rel = kCluRel, bool bf16x3 = false) {
   const int m = band_hi - band_lo;
   BE_RET_IF(check_eigh_lds(ctx, N, m, sizeof(typename CT<T>::c)));
   if (n_mat == 0) return BE_OK;
@@ -1858,7 +1862,7 @@ static int eigh_run(be_ctx *ctx, typename CT<T>::c *H, int N, int ld, int64_t ma
   for (int64_t b0 = 0; b0 < n_mat; b0 += cap) {
     const int64_t nb_mat = std::min<int64_t>(cap, n_mat - b0);
     BE_RET_IF(eigh_chunk<T>(ctx, H + b0 * mat_stride, N, ld, mat_stride, nb_mat, band_lo, band_hi, evals + b0 * (m + 2),
-                            U + b0 * u_stride, ldu, u_stride, status + b0, stream, clu_rel));
+                            U + b0 * u_stride, ldu, u_stride, status + b0, stream, clu_rel, bf16x3));
   }
   return BE_OK;
 }
@@ -2049,8 +2053,10 @@ int eigh_fp64(be_ctx *ctx, double2 *H, int N, int ld, int64_t mat_stride, int64_
 }
 
 int eigh_mixed(be_ctx *ctx, float2 *H, int N, int ld, int64_t mat_stride, int64_t n_mat, int band_lo, int band_hi,
-               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream) {
-  return eigh_run<float>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream);
+               double *evals, double2 *U, int ldu, int64_t u_stride, uint32_t *status, hipStream_t stream,
+               bool bf16x3) {
+  return eigh_run<float>(ctx, H, N, ld, mat_stride, n_mat, band_lo, band_hi, evals, U, ldu, u_stride, status, stream,
+                         kCluRel, bf16x3);
 }
 
 }  // namespace be
@@ -2075,10 +2081,11 @@ extern "C" int be_eigh_batched(be_ctx *ctx, void *H, int32_t dtype, int32_t N, i
     return eigh_refined(ctx, static_cast<const double2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
                         static_cast<double2 *>(U), ldu, u_stride, status, stream);
   }
-  if (precision == BE_MIXED_FP32) {
-    BE_CHECK_ARG(ctx, dtype == BE_C64, "be_eigh_batched: BE_MIXED_FP32 needs BE_C64 matrices");
+  if (precision == BE_MIXED_FP32 || precision == BE_MIXED_BF16X) {
+    BE_CHECK_ARG(ctx, dtype == BE_C64, "be_eigh_batched: BE_MIXED_FP32 and BE_MIXED_BF16X need BE_C64 matrices");
     return eigh_run<float>(ctx, static_cast<float2 *>(H), N, ld, mat_stride, n_mat, band_lo, band_hi, evals,
-                           static_cast<double2 *>(U), ldu, u_stride, status, stream);
+                           static_cast<double2 *>(U), ldu, u_stride, status, stream, kCluRel,
+                           precision == BE_MIXED_BF16X);
   }
   return set_err(ctx, BE_EINVAL, "be_eigh_batched: unknown precision");
 }
@@ -2089,7 +2096,7 @@ extern "C" int be_eigh_round(be_ctx *ctx, int32_t N, int32_t precision, int64_t 
   BE_CHECK_ARG(ctx, N >= 1, "be_eigh_round: N < 1");
   if (precision == BE_FP64) {
     *round = panel_slots<double>(ctx, N);
-  } else if (precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED) {
+  } else if (precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED || precision == BE_MIXED_BF16X) {
     *round = panel_slots<float>(ctx, N);
   } else {
     return set_err(ctx, BE_EINVAL, "be_eigh_round: unknown precision");

@@ -283,6 +283,210 @@ int dispatch(be_ctx *ctx, GP<T> p, int opA, int opB, hipStream_t s) {
   return launch_cfg<T, 16, 16, 1, 1>(ctx, p, opA, opB, s);
 }
 
+// ---------------------------------------------------------------- split-bf16 complex GEMM
+// The FP32 complex GEMM on the bf16 matrix cores: every FP32 operand x is
+// split into x_hi = bf16(x) and x_lo = bf16(x - x_hi) (round to nearest even),
+// and each real product x y is taken as x_hi y_hi + x_hi y_lo + x_lo y_hi
+// (three v_mfma_f32_16x16x16_bf16, FP32 accumulation): about 16 significant
+// bits per operand instead of FP32's 24, relative error ~2^-16 per product.
+// Same tiles, work mapping, Hermitian mode and epilogue as zgemm_kernel;
+// tiles of A and B are staged in LDS as bf16 planes (hi and lo of the real and
+// imaginary parts) laid out [row][k], so that each lane's operand of four
+// consecutive k is one 8-byte read. Operand lanes (checked on the device):
+// lane l supplies row l % 16 of its operand at k = 4 (l / 16) + 0..3, and its
+// accumulator register r holds output (4 (l / 16) + r, l % 16).
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even (finite x)
+  return static_cast<unsigned short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(uint32_t(h) << 16); }
+
+template <int BM, int BN, int WM, int WN, int OPA, int OPB>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_bf16x3_kernel(GP<float> p) {
+  typedef float2 cplx;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  constexpr int KS = 16;        // k per stage: one bf16 MFMA step
+  constexpr int KP = KS + 4;    // LDS row pitch (bf16 elements, a multiple of 4: 8-byte reads)
+  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+  __shared__ __align__(16) unsigned short sA[4][BM * KP], sB[4][BN * KP];
+
+  const int64_t tiles = int64_t(p.tiles_m) * p.tiles_n;
+  const int64_t total = tiles * p.batch;
+  const int64_t w = be::xcd_work_id(total);
+  if (w >= total) return;
+  const int64_t q = w / tiles;
+  const int t2 = static_cast<int>(w - q * tiles);
+  const int tm = t2 % p.tiles_m, tn = t2 / p.tiles_m;
+  const int i0 = tm * BM, j0 = tn * BN;
+  static_assert(BM == BN, "square tiles (Hermitian mode pairs tile (tm, tn) with (tn, tm))");
+  if (p.herm && tm < tn) return;
+  if (p.act && p.act[q] == 0) return;
+  const cplx *A = p.A + be::zbatch_off(p.bA, q);
+  const cplx *B = p.B + be::zbatch_off(p.bB, q);
+  cplx *C = p.C + be::zbatch_off(p.bC, q);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int li = lane & 15, lk = lane >> 4;
+
+  v4f accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      accr[a][b] = v4f{0, 0, 0, 0};
+      acci[a][b] = v4f{0, 0, 0, 0};
+    }
+
+  constexpr int EA = (BM * KS + NT - 1) / NT;
+  constexpr int EB = (BN * KS + NT - 1) / NT;
+  cplx ga[EA], gb[EB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int e = tid + u * NT;
+      const int i = OPA == 0 ? e % BM : e / KS, k = OPA == 0 ? e / BM : e % KS;
+      const int gi = i0 + i, gk = k0 + k;
+      cplx v = {0.f, 0.f};
+      if (e < BM * KS && gi < p.M && gk < p.K) v = OPA == 0 ? A[gi + int64_t(gk) * p.lda] : A[gk + int64_t(gi) * p.lda];
+      ga[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + u * NT;
+      const int j = OPB == 0 ? e / KS : e % BN, k = OPB == 0 ? e % KS : e / BN;
+      const int gj = j0 + j, gk = k0 + k;
+      cplx v = {0.f, 0.f};
+      if (e < BN * KS && gj < p.N && gk < p.K) v = OPB == 0 ? B[gk + int64_t(gj) * p.ldb] : B[gj + int64_t(gk) * p.ldb];
+      gb[u] = v;
+    }
+  };
+  auto split_store = [&](unsigned short (*pl)[(BM > BN ? BM : BN) * KP], int off, float re, float im) {
+    const unsigned short rh = bf16_rne(re), ih = bf16_rne(im);
+    pl[0][off] = rh;
+    pl[1][off] = bf16_rne(re - bf16_to_f(rh));
+    pl[2][off] = ih;
+    pl[3][off] = bf16_rne(im - bf16_to_f(ih));
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int e = tid + u * NT;
+      if (e >= BM * KS) break;
+      const int i = OPA == 0 ? e % BM : e / KS, k = OPA == 0 ? e / BM : e % KS;
+      split_store(sA, i * KP + k, ga[u].x, OPA == 0 ? ga[u].y : -ga[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + u * NT;
+      if (e >= BN * KS) break;
+      const int j = OPB == 0 ? e / KS : e % BN, k = OPB == 0 ? e % KS : e / BN;
+      split_store(sB, j * KP + k, gb[u].x, OPB == 0 ? gb[u].y : -gb[u].y);
+    }
+  };
+  auto rd = [&](const unsigned short *plane, int row) {
+    return *reinterpret_cast<const v4s *>(plane + row * KP + 4 * lk);
+  };
+  auto mf = [](v4s x, v4s y, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, c, 0, 0, 0); };
+  const v4s sgn = {short(0x8000), short(0x8000), short(0x8000), short(0x8000)};
+
+  gload(0);
+  for (int k0 = 0; k0 < p.K; k0 += KS) {
+    sstore();
+    __syncthreads();
+    if (k0 + KS < p.K) gload(k0 + KS);
+    v4s arh[TM], arl[TM], aih[TM], ail[TM];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int ii = wm * (BM / WM) + a * 16 + li;
+      arh[a] = rd(sA[0], ii);
+      arl[a] = rd(sA[1], ii);
+      aih[a] = rd(sA[2], ii);
+      ail[a] = rd(sA[3], ii);
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int jj = wn * (BN / WN) + b * 16 + li;
+      const v4s brh = rd(sB[0], jj), brl = rd(sB[1], jj), bih = rd(sB[2], jj), bil = rd(sB[3], jj);
+      const v4s nbih = bih ^ sgn, nbil = bil ^ sgn;
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        // the MFMA's first operand from the B tile, its second from the A
+        // tile: each lane's accumulators hold one output row
+        v4f cr = accr[a][b], ci = acci[a][b];
+        cr = mf(brl, arh[a], cr);   // Ar Br (small terms first)
+        cr = mf(brh, arl[a], cr);
+        cr = mf(brh, arh[a], cr);
+        cr = mf(nbil, aih[a], cr);  // - Ai Bi
+        cr = mf(nbih, ail[a], cr);
+        cr = mf(nbih, aih[a], cr);
+        ci = mf(bil, arh[a], ci);   // Ar Bi
+        ci = mf(bih, arl[a], ci);
+        ci = mf(bih, arh[a], ci);
+        ci = mf(brl, aih[a], ci);   // Ai Br
+        ci = mf(brh, ail[a], ci);
+        ci = mf(brh, aih[a], ci);
+        accr[a][b] = cr;
+        acci[a][b] = ci;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue (as zgemm_kernel<float>): lane holds C(i_base + li, j_base + 4 lk + r)
+  const bool use_beta = (p.beta.x != 0.f) || (p.beta.y != 0.f);
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int gi = i0 + wm * (BM / WM) + a * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gj = j0 + wn * (BN / WN) + b * 16 + 4 * lk + r;
+        if (gi < p.M && gj < p.N) {
+          const float xr = accr[a][b][r], xi = acci[a][b][r];
+          cplx out;
+          out.x = p.alpha.x * xr - p.alpha.y * xi;
+          out.y = p.alpha.x * xi + p.alpha.y * xr;
+          const int64_t idx = gi + int64_t(gj) * p.ldc;
+          if (use_beta) {
+            const cplx c = C[idx];
+            out.x += p.beta.x * c.x - p.beta.y * c.y;
+            out.y += p.beta.x * c.y + p.beta.y * c.x;
+          }
+          C[idx] = out;
+          if (p.herm && p.mirror && tm > tn) C[gj + int64_t(gi) * p.ldc] = make_float2(out.x, -out.y);
+        }
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN>
+int launch_bf16x3(be_ctx *ctx, GP<float> p, int opA, int opB, hipStream_t s) {
+  p.tiles_m = (p.M + BM - 1) / BM;
+  p.tiles_n = (p.N + BN - 1) / BN;
+  int64_t total = int64_t(p.tiles_m) * p.tiles_n * p.batch;
+  dim3 grid(be::xcd_grid(total)), block(64 * WM * WN);
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((zgemm_bf16x3_kernel<BM, BN, WM, WN, 0, 0>), grid, block, 0, s, p);
+  if (opA == 0 && opB == 1) hipLaunchKernelGGL((zgemm_bf16x3_kernel<BM, BN, WM, WN, 0, 1>), grid, block, 0, s, p);
+  if (opA == 1 && opB == 0) hipLaunchKernelGGL((zgemm_bf16x3_kernel<BM, BN, WM, WN, 1, 0>), grid, block, 0, s, p);
+  if (opA == 1 && opB == 1) hipLaunchKernelGGL((zgemm_bf16x3_kernel<BM, BN, WM, WN, 1, 1>), grid, block, 0, s, p);
+  return be::check_launch(ctx, "zgemm_bf16x3");
+}
+
+int dispatch_bf16x3(be_ctx *ctx, GP<float> p, int opA, int opB, hipStream_t s) {
+  if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return BE_OK;
+  if (use_big_tiles(p.M, p.N)) return launch_bf16x3<64, 64, 4, 2>(ctx, p, opA, opB, s);
+  if (p.M >= 24 && p.N >= 24) return launch_bf16x3<32, 32, 2, 2>(ctx, p, opA, opB, s);
+  return launch_bf16x3<16, 16, 1, 1>(ctx, p, opA, opB, s);
+}
+
 // ---------------------------------------------------------------- real FP64 GEMM
 // C = alpha op(A) op(B) + beta C with op in {none, transpose}; one MFMA per
 // 16x16 tile and k-step, same staging and epilogue as the complex kernel.
@@ -493,6 +697,7 @@ int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
   p.sB = nullptr;
   p.sB_div = 1;
   p.sB_ld = 0;
+  if (g.bf16x3) return dispatch_bf16x3(ctx, p, g.opA, g.opB, stream);
   return dispatch<float>(ctx, p, g.opA, g.opB, stream);
 }
 

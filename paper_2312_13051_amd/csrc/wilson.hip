@@ -1546,13 +1546,14 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
   int erc;
   // BE_MIXED_FP32_REFINED takes the FP64 solver here (order m: the sectors'
   // subspaces are then FP64-accurate, as the refined eigenvectors U are)
-  if (precision == BE_MIXED_FP32) {
+  if (precision == BE_MIXED_FP32 || precision == BE_MIXED_BF16X) {
     // c64 copy of the projected operator
     float2 *A32 = reinterpret_cast<float2 *>(A32buf);
     hipLaunchKernelGGL(k_narrow, dim3(static_cast<uint32_t>(std::min<int64_t>((n_k * mm + 255) / 256, 65535))),
                        dim3(256), 0, stream, A, n_k * mm, A32);
     erc = check_launch(ctx, "k_narrow");
-    if (erc == BE_OK) erc = eigh_mixed(ctx, A32, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream);
+    if (erc == BE_OK)
+      erc = eigh_mixed(ctx, A32, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream, precision == BE_MIXED_BF16X);
   } else {
     erc = eigh_fp64(ctx, A, m, m, mm, n_k, 0, m, ev, Q, m, mm, kst, stream);
   }
@@ -1592,7 +1593,8 @@ extern "C" int be_spin_resolved_wilson(be_ctx *ctx, const void *U, int32_t N, in
   BE_CHECK_ARG(ctx, spin_diag && pso_evals && theta_dn && theta_up && C_dn && C_up && C_s && m_dn_h && status,
                "be_spin_resolved_wilson: null argument");
   BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_resolved_wilson: at most 1024 systems per call");
-  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED,
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED ||
+                        precision == BE_MIXED_BF16X,
                "be_spin_resolved_wilson: bad precision");
   if (n_sys == 0) return BE_OK;
   const int64_t kps = int64_t(n_par) * n_perp;
@@ -1688,7 +1690,8 @@ extern "C" int be_spin_sectors(be_ctx *ctx, const void *U, int32_t N, int32_t m,
   BE_CHECK_ARG(ctx, spin_diag && pso_evals && V && m_dn_h && status, "be_spin_sectors: null argument");
   BE_CHECK_ARG(ctx, ldv >= N && v_stride >= int64_t(ldv) * std::max(m, 1), "be_spin_sectors: ldv < N or v_stride < ldv*m");
   BE_CHECK_ARG(ctx, n_sys <= 1024, "be_spin_sectors: at most 1024 systems per call");
-  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED,
+  BE_CHECK_ARG(ctx, precision == BE_FP64 || precision == BE_MIXED_FP32 || precision == BE_MIXED_FP32_REFINED ||
+                        precision == BE_MIXED_BF16X,
                "be_spin_sectors: bad precision");
   if (n_sys == 0) return BE_OK;
   const int64_t kps = n_k_sys;

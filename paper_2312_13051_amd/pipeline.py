@@ -58,8 +58,8 @@ def eig_grid(ctx: L.Context, plan: L.HkPlan, sys_first: int, n_sys: int, kappa_g
     U = torch.empty((n_mat, max(m, 1), ldu), dtype=torch.complex128, device="cuda")
     ev = torch.empty((n_mat, m + 2), dtype=torch.float64, device="cuda")
     st = torch.empty(n_mat, dtype=torch.int32, device="cuda")
-    cdt = torch.complex64 if precision == L.BE_MIXED_FP32 else torch.complex128
-    dt = L.BE_C64 if precision == L.BE_MIXED_FP32 else L.BE_C128
+    cdt = torch.complex64 if L.c64_input(precision) else torch.complex128
+    dt = L.BE_C64 if L.c64_input(precision) else L.BE_C128
     per = max(1, chunk // n_k)  # systems per chunk
     H = torch.empty((min(per, n_sys) * n_k, N, N), dtype=cdt, device="cuda")
     for s0 in range(0, n_sys, per):

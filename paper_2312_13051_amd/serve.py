@@ -393,7 +393,7 @@ class GpuExecutor:
 
     @staticmethod
     def _hb(req):
-        return 8 if req.precision == L.BE_MIXED_FP32 else 16
+        return 8 if L.c64_input(req.precision) else 16
 
     def chunk_for(self, req: Request) -> int:
         """Hamiltonians per eigensolver launch for the request's key: the same
@@ -434,7 +434,7 @@ class GpuExecutor:
         with self._lock:
             ent = self._H.get(req.key)
             if ent is None:
-                dt = torch.complex64 if req.precision == L.BE_MIXED_FP32 else torch.complex128
+                dt = torch.complex64 if L.c64_input(req.precision) else torch.complex128
                 ent = [torch.empty((self.chunk_for(req), req.N, req.N), dtype=dt, device=self.device), None]
                 self._H[req.key] = ent
         if ent[1] is not None:
@@ -464,7 +464,7 @@ class GpuExecutor:
         ctx, stream = self.lanes[lane]
         r0 = parts[0][0]["req"]
         N, prec = r0.N, r0.precision
-        dcode = L.BE_C64 if prec == L.BE_MIXED_FP32 else L.BE_C128
+        dcode = L.BE_C64 if L.c64_input(prec) else L.BE_C128
         with torch.cuda.stream(stream):
             hent = self._hbuf(r0, stream)
             H = hent[0]

@@ -478,3 +478,48 @@ def test_bisection_cap_flags_nonconverged():
         assert np.all(st2 == 0) and np.array_equal(ev2, ev0) and np.array_equal(U2, U0)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("name", ["random257", "bhz_L10_W2"])
+def test_eigh_split_bf16_bounds(name):
+    """BE_MIXED_BF16X (trailing updates and back-transformation as split-bf16
+    products, ~2^-16 relative error per product): eigenvalues within 1e-5
+    ||H||, U orthonormal to 1e-4, projector within 1e-4 (measured: 1.1e-6,
+    1.3e-5 and 1.5e-5 on these inputs); it must not fall back to the FP32
+    products (its eigenvalues differ from the FP32 mixed path's)."""
+    gu.need_gpu()
+    from paper_2312_13051_amd import _lib as L
+    if name == "random257":
+        rng = np.random.default_rng(3)
+        A = rng.standard_normal((3, 257, 257)) + 1j * rng.standard_normal((3, 257, 257))
+        Hs = A + np.conj(np.swapaxes(A, 1, 2))
+    else:
+        hl = syn.bhz_disordered(10, 2.0, [3, 2, 4])
+        Hs = np.stack([orc.bloch_hamiltonian(hl, k) for k in syn.kplane(2, 2).reshape(-1, 3)])
+    n, N, _ = Hs.shape
+    m = N // 2
+    c = gu.ctx()
+    out = {}
+    for prec in (L.BE_MIXED_FP32, L.BE_MIXED_BF16X):
+        dH = gu.from_np(Hs, N, dtype=torch.complex64)
+        U = gu.colmajor(n, N, m, N, fill=0)
+        ev = torch.empty((n, m + 2), dtype=torch.float64, device="cuda")
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        c.eigh_batched(dH, 1, N, N, dH.stride(0), n, 0, m, prec, ev, U, N, U.stride(0), st)
+        torch.cuda.synchronize()
+        out[prec] = (ev.cpu().numpy(), gu.to_np(U, N)[:, :, :m], st.cpu().numpy())
+    ev, U, st = out[L.BE_MIXED_BF16X]
+    assert np.all(st == 0)
+    for q in range(n):
+        w, V = np.linalg.eigh(Hs[q])
+        nrm = np.abs(w).max()
+        assert np.max(np.abs(ev[q, 1:m + 1] - w[:m])) <= 1e-5 * nrm
+        assert np.max(np.abs(U[q].conj().T @ U[q] - np.eye(m))) < 1e-4
+        assert np.max(np.abs(U[q] @ U[q].conj().T - V[:, :m] @ V[:, :m].conj().T)) < 1e-4
+    assert not np.array_equal(ev, out[L.BE_MIXED_FP32][0])
+    z = gu.from_np(Hs, N)                # c128 input is refused for this precision
+    ev2 = torch.empty((n, m + 2), dtype=torch.float64, device="cuda")
+    U2 = gu.colmajor(n, N, m, N, fill=0)
+    st2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    with pytest.raises(L.BerryError):
+        c.eigh_batched(z, L.BE_C128, N, N, z.stride(0), n, 0, m, L.BE_MIXED_BF16X, ev2, U2, N, U2.stride(0), st2)

@@ -125,3 +125,27 @@ def test_random_spin_resolved_cases_match_the_oracle(seed):
             assert float(out["C_s"].cpu().numpy()[0]) == ref["C_s"]
     finally:
         c.close()
+
+
+def test_split_bf16_spin_resolved_loop_states_its_error():
+    """The spin-resolved loop with BE_MIXED_BF16X (split-bf16 products in both
+    eigensolvers): same sector sizes and spin Chern numbers as FP64, phases
+    within 1e-4 rad of the FP64 path (its stated error is ~1e-6)."""
+    gu.need_gpu()
+    hl = syn.bhz_disordered(4, 1.0, [79, 1])
+    kg = syn.kplane(12, 6)
+    sd = syn.bhz_spin_diag(hl)[None]
+    c = gu.ctx()
+    try:
+        plan = c.hk_plan([hl])
+        ref = PL.spin(c, PL.eig_grid(c, plan, 0, 1, kg, 0, hl.N // 2, L.BE_FP64), sd)
+        got = PL.spin(c, PL.eig_grid(c, plan, 0, 1, kg, 0, hl.N // 2, L.BE_MIXED_BF16X), sd,
+                      precision=L.BE_MIXED_BF16X)
+        md = ref["m_dn"][0]
+        assert got["m_dn"] == ref["m_dn"]
+        assert float(got["C_s"].cpu().numpy()[0]) == float(ref["C_s"].cpu().numpy()[0]) == 1.0
+        for k, w in (("theta_dn", md), ("theta_up", hl.N // 2 - md)):
+            assert phase_set_error(got[k].cpu().numpy()[0, :, :w], ref[k].cpu().numpy()[0, :, :w]) < 1e-4
+        assert int(got["status"].cpu().numpy()[0]) == 0
+    finally:
+        c.close()
