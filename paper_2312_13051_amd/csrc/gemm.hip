@@ -2,8 +2,9 @@
 //
 //   C_q = alpha op(A_q) op(B_q) + beta C_q,  op in {none, conjugate transpose}
 //
-// Complex products use four real MFMAs per 16x16 tile and k-step
-// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br). Tiles of A and B are staged
+// Complex products use four real MFMAs per 16x16 tile and k-step in FP64
+// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br) and three in FP32 (Gauss:
+// Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) accumulated apart, combined at the end). Tiles of A and B are staged
 // through LDS as separate real and imaginary planes laid out [k][row], so
 // every MFMA operand fetch is one conflict-free 8-byte (4-byte) LDS read per
 // lane. The MFMA's "A" operand is taken from the B tile and its "B" operand
@@ -102,13 +103,16 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   const int wm = wave % WM, wn = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
 
-  acc_t accr[TM][TN], acci[TM][TN];
+  // FP32: complex products by three real MFMAs (Gauss), else four
+  constexpr bool M3 = sizeof(T) == 4;
+  acc_t accr[TM][TN], acci[TM][TN], acc2[M3 ? TM : 1][M3 ? TN : 1];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
       accr[a][b] = acc_t{0, 0, 0, 0};
       acci[a][b] = acc_t{0, 0, 0, 0};
+      if constexpr (M3) acc2[a][b] = acc_t{0, 0, 0, 0};
     }
 
   // Software pipeline: the global loads of k-tile t+1 are issued into
@@ -201,17 +205,40 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
         bi[b] = sBi[(kk + lk) * PB + jj];
         nbi[b] = -bi[b];
       }
+      if constexpr (M3) {
+        // three real products per complex one: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
-      for (int a = 0; a < TM; ++a)
+        for (int a = 0; a < TM; ++a) {
+          const T as = ar[a] + ai[a];
 #pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          accr[a][b] = MF<T>::mfma(br[b], ar[a], accr[a][b]);
-          accr[a][b] = MF<T>::mfma(nbi[b], ai[a], accr[a][b]);
-          acci[a][b] = MF<T>::mfma(bi[b], ar[a], acci[a][b]);
-          acci[a][b] = MF<T>::mfma(br[b], ai[a], acci[a][b]);
+          for (int b = 0; b < TN; ++b) {
+            accr[a][b] = MF<T>::mfma(br[b], ar[a], accr[a][b]);
+            acc2[a][b] = MF<T>::mfma(bi[b], ai[a], acc2[a][b]);
+            acci[a][b] = MF<T>::mfma(br[b] + bi[b], as, acci[a][b]);
+          }
         }
+      } else {
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b) {
+            accr[a][b] = MF<T>::mfma(br[b], ar[a], accr[a][b]);
+            accr[a][b] = MF<T>::mfma(nbi[b], ai[a], accr[a][b]);
+            acci[a][b] = MF<T>::mfma(bi[b], ar[a], acci[a][b]);
+            acci[a][b] = MF<T>::mfma(br[b], ai[a], acci[a][b]);
+          }
+      }
     }
     __syncthreads();
+  }
+  if constexpr (M3) {  // Cr = Ar Br - Ai Bi, Ci = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        acci[a][b] = acci[a][b] - accr[a][b] - acc2[a][b];
+        accr[a][b] = accr[a][b] - acc2[a][b];
+      }
   }
 
   // ---- epilogue: lane holds C(i = i_base + li, j = j_base + row(lk, r))
