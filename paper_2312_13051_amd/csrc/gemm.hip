@@ -2,9 +2,10 @@
 //
 //   C_q = alpha op(A_q) op(B_q) + beta C_q,  op in {none, conjugate transpose}
 //
-// Complex products use four real MFMAs per 16x16 tile and k-step in FP64
-// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br) and three in FP32 (Gauss:
-// Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) accumulated apart, combined at the end). Tiles of A and B are staged
+// Complex products use three real MFMAs per 16x16 tile and k-step (Gauss:
+// Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) accumulated apart; at the end
+// Cr = Ar Br - Ai Bi and Ci = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi), a quarter
+// less matrix-core work than the four products of the textbook form. Tiles of A and B are staged
 // through LDS as separate real and imaginary planes laid out [k][row], so
 // every MFMA operand fetch is one conflict-free 8-byte (4-byte) LDS read per
 // lane. The MFMA's "A" operand is taken from the B tile and its "B" operand
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   const int wm = wave % WM, wn = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
 
-  // FP32: complex products by three real MFMAs (Gauss), else four
-  constexpr bool M3 = sizeof(T) == 4;
+  // complex products by three real MFMAs (Gauss); false: the four-product form
+  constexpr bool M3 = true;
   acc_t accr[TM][TN], acci[TM][TN], acc2[M3 ? TM : 1][M3 ? TN : 1];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
