@@ -246,6 +246,10 @@ struct ZGemm {
   // read), unless herm_mirror is false (callers that read the lower triangle only)
   bool herm = false;
   bool herm_mirror = true;
+  // complex products in the four-product form instead of three real products
+  // (Gauss): for Hermitian outputs that feed an eigensolver, whose diagonal
+  // tiles it keeps bitwise Hermitian with exactly real diagonals
+  bool four_mult = false;
   // optional per-item predicate: items with act[q] == 0 are skipped (C left as it is)
   const int *act = nullptr;
   // optional real row scaling of B (opB = 'N' only): op(B_q) = diag(s_q) B_q
@@ -276,6 +280,7 @@ struct CGemm {
   const char *tag = "cgemm";
   bool herm = false;  // as in ZGemm
   bool herm_mirror = true;
+  bool four_mult = false;  // as in ZGemm
   const int *act = nullptr;  // as in ZGemm
   // products on the bf16 matrix cores with each FP32 operand split into two
   // bf16 parts (three products per real product, ~2^-16 relative error)

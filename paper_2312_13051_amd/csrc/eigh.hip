@@ -1118,7 +1118,10 @@ __global__ __launch_bounds__(PT) void tri_gs(int N, int m, const double *lamg, d
               nr = fma(v, v, nr);
             }
             nr = wave_sum(nr);
-            const double inv = 1.0 / sqrt(nr);
+            // a vector in the span of the earlier ones is left at zero (the
+            // orthonormalization that follows then flags the matrix) rather
+            // than divided by zero
+            const double inv = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
             for (int i = lane; i < N; i += 64) X[int64_t(i) * mp + t] *= inv;
           }
         }
@@ -1154,7 +1157,10 @@ __global__ __launch_bounds__(PT) void ns_prep_real(double *G, int m, double *err
     for (int w = 1; w < PT / 64; ++w) t = fmax(t, red[w]);
     if (!(t == t)) t = INFINITY;
     err[q] = t;
-    act[q] = t <= tol ? 0 : t < 1e-8 ? 2 : 1;
+    // beyond 1 (columns of unit norm cannot differ from orthonormal by more
+    // elementwise) the iteration is outside its basin and would grow without
+    // bound: stop, the error stays and flags the matrix
+    act[q] = t <= tol ? 0 : t < 1e-8 ? 2 : t > 1.0 ? 0 : 1;
   }
 }
 
@@ -1452,7 +1458,7 @@ __global__ __launch_bounds__(PT) void ns_prep_cplx(double2 *G, int m, double *er
     for (int w = 1; w < PT / 64; ++w) t = fmax(t, red[w]);
     if (!(t == t)) t = INFINITY;
     err[q] = t;
-    act[q] = t <= tol ? 0 : t < last ? 2 : 1;
+    act[q] = t <= tol ? 0 : t < last ? 2 : t > 1.0 ? 0 : 1;  // beyond 1: outside the basin (as in ns_prep_real)
   }
 }
 
@@ -1987,6 +1993,7 @@ static int eigh_refined_chunk(be_ctx *ctx, const double2 *H, int N, int ld, int6
     g.batch = nb;
     g.tag = "refine_orth";
     g.herm = true;
+    g.four_mult = true;  // the Gram matrix's small off-diagonal entries to full relative accuracy
     g.act = act;
     BE_RET_IF(zgemm(ctx, g, stream));
     hipLaunchKernelGGL(ns_prep_cplx, dim3(static_cast<uint32_t>(nb)), dim3(PT), 0, stream, Gm, m, err, act, 1e-14,

@@ -5,7 +5,9 @@
 // Complex products use three real MFMAs per 16x16 tile and k-step (Gauss:
 // Ar Br, Ai Bi and (Ar + Ai)(Br + Bi) accumulated apart; at the end
 // Cr = Ar Br - Ai Bi and Ci = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi), a quarter
-// less matrix-core work than the four products of the textbook form. Tiles of A and B are staged
+// less matrix-core work than the four products of the textbook form, which
+// callers can ask for (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br) where a
+// Hermitian product must come out bitwise Hermitian. Tiles of A and B are staged
 // through LDS as separate real and imaginary planes laid out [k][row], so
 // every MFMA operand fetch is one conflict-free 8-byte (4-byte) LDS read per
 // lane. The MFMA's "A" operand is taken from the B tile and its "B" operand
@@ -66,13 +68,14 @@ struct GP {
   int tiles_m, tiles_n;
   int herm;  // Hermitian C: lower tiles only, strictly lower tiles mirrored into the upper triangle (if mirror)
   int mirror;
+  int four_mult;  // complex products in the four-product form
   const int *act;  // per batch item: 0 skips the item (its C is left untouched), or null
   const double *sB;  // row scales of B (OPB == 0), or null: s_q = sB + (q / sB_div) * sB_ld
   int64_t sB_div, sB_ld;
 };
 
 // BM x BN block tile, WM x WN waves, each wave (BM/WM) x (BN/WN).
-template <typename T, int BM, int BN, int WM, int WN, int OPA, int OPB>
+template <typename T, int BM, int BN, int WM, int WN, int OPA, int OPB, bool M3>
 __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   typedef typename MF<T>::cplx cplx;
   typedef typename MF<T>::acc_t acc_t;
@@ -104,8 +107,10 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GP<T> p) {
   const int wm = wave % WM, wn = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
 
-  // complex products by three real MFMAs (Gauss); false: the four-product form
-  constexpr bool M3 = true;
+  // M3: complex products by three real MFMAs (Gauss); else the four-product
+  // form, which callers ask for where it matters that the Gauss form takes Ci
+  // as a difference of large terms: the (i, j) and (j, i) entries of a
+  // Hermitian product are then not exact conjugates, nor its diagonal real
   acc_t accr[TM][TN], acci[TM][TN], acc2[M3 ? TM : 1][M3 ? TN : 1];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -280,10 +285,17 @@ int launch_cfg(be_ctx *ctx, GP<T> p, int opA, int opB, hipStream_t s) {
   p.tiles_n = (p.N + BN - 1) / BN;
   int64_t total = int64_t(p.tiles_m) * p.tiles_n * p.batch;
   dim3 grid(be::xcd_grid(total)), block(64 * WM * WN);
-  if (opA == 0 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 0>), grid, block, 0, s, p);
-  if (opA == 0 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 1>), grid, block, 0, s, p);
-  if (opA == 1 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 0>), grid, block, 0, s, p);
-  if (opA == 1 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 1>), grid, block, 0, s, p);
+  if (p.four_mult) {
+    if (opA == 0 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 0, false>), grid, block, 0, s, p);
+    if (opA == 0 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 1, false>), grid, block, 0, s, p);
+    if (opA == 1 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 0, false>), grid, block, 0, s, p);
+    if (opA == 1 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 1, false>), grid, block, 0, s, p);
+  } else {
+    if (opA == 0 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 0, true>), grid, block, 0, s, p);
+    if (opA == 0 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 0, 1, true>), grid, block, 0, s, p);
+    if (opA == 1 && opB == 0) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 0, true>), grid, block, 0, s, p);
+    if (opA == 1 && opB == 1) hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN, 1, 1, true>), grid, block, 0, s, p);
+  }
   return be::check_launch(ctx, "zgemm");
 }
 
@@ -693,6 +705,7 @@ int zgemm(be_ctx *ctx, const ZGemm &g, hipStream_t stream) {
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
   p.mirror = g.herm_mirror ? 1 : 0;
+  p.four_mult = g.four_mult ? 1 : 0;
   p.act = g.act;
   BE_CHECK_ARG(ctx, !g.scaleB || (g.opB == 0 && g.scaleB_div >= 1), "zgemm: row scaling of B needs opB = 'N'");
   p.sB = g.scaleB;
@@ -721,6 +734,7 @@ int cgemm(be_ctx *ctx, const CGemm &g, hipStream_t stream) {
   p.batch = g.batch;
   p.herm = g.herm ? 1 : 0;
   p.mirror = g.herm_mirror ? 1 : 0;
+  p.four_mult = g.four_mult ? 1 : 0;
   p.act = g.act;
   p.sB = nullptr;
   p.sB_div = 1;

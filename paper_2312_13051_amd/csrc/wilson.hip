@@ -12,9 +12,12 @@
 //   chain         W_line = F_{n-1} ... F_0 as a binary tree of batched GEMMs
 //                 that keeps the left-to-right order
 //   eigenphases   one wave per W: Householder reduction to Hessenberg form,
-//                 then single-shift complex QR with Wilkinson shifts; for
-//                 unitary W all entries are bounded by one, so deflation uses
-//                 an absolute threshold
+//                 then single-shift complex QR with Wilkinson shifts; a
+//                 subdiagonal entry is negligible below 32 eps times its two
+//                 diagonal neighbours (the level to which a product of polar
+//                 factors is unitary: phases that close are not separated
+//                 further, and deflating changes W's eigenvalues, W being
+//                 normal, by no more than that)
 //   winding       Phi_i = sum theta mod 2pi, C = (1/2pi) sum wrap(dPhi)
 #include <algorithm>
 #include <cfloat>
@@ -255,13 +258,14 @@ __global__ __launch_bounds__(64) void k_unitary_eig(const double2 *W, int m, int
     __syncthreads();
   }
   // ---- single-shift QR on the Hessenberg matrix
-  const double tol = 4.0 * eps;
+  const double tol = 32.0 * eps;  // relative to the two diagonal neighbours
   int ihi = m - 1, its = 0, total = 0;
   bool failed = false;
   while (ihi >= 0) {
     int l = 0;
     for (int k = ihi; k >= 1; --k) {
-      if (cabs1(H[k + int64_t(k - 1) * m]) <= tol) {
+      if (cabs1(H[k + int64_t(k - 1) * m]) <=
+          fmax(tol * (cabs1(H[(k - 1) + int64_t(k - 1) * m]) + cabs1(H[k + int64_t(k) * m])), DBL_MIN)) {
         l = k;
         break;
       }
@@ -280,8 +284,15 @@ __global__ __launch_bounds__(64) void k_unitary_eig(const double2 *W, int m, int
     if (l > 0 && lane == 0) H[l + int64_t(l - 1) * m] = make_double2(0.0, 0.0);
     double2 mu;
     const double2 dd = H[ihi + int64_t(ihi) * m];
-    if (its == 10 || its == 20) {
+    // exceptional shifts every 10 steps without a deflation, alternately from
+    // the bottom and from the top of the active block (a Wilkinson shift can
+    // cycle without converging, e.g. for eigenvalues placed symmetrically
+    // about it, which a unitary W can have)
+    if (its > 0 && its % 20 == 10) {
       mu = make_double2(dd.x + 0.75 * cabs1(H[ihi + int64_t(ihi - 1) * m]), dd.y);
+    } else if (its > 0 && its % 20 == 0) {
+      const double2 dl = H[l + int64_t(l) * m];
+      mu = make_double2(dl.x + 0.75 * cabs1(H[(l + 1) + int64_t(l) * m]), dl.y);
     } else {
       const double2 a = H[(ihi - 1) + int64_t(ihi - 1) * m], b = H[(ihi - 1) + int64_t(ihi) * m],
                     c = H[ihi + int64_t(ihi - 1) * m];
@@ -514,14 +525,14 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
     __syncthreads();
   }
   // ---- single-shift QR on the Hessenberg matrix
-  const double tol = 4.0 * DBL_EPSILON;
+  const double tol = 32.0 * DBL_EPSILON;  // relative to the two diagonal neighbours (as in k_unitary_eig)
   int ihi = m - 1, its = 0, total = 0;
   bool failed = false;
   while (ihi >= 0) {
     // deflation: the largest k <= ihi with a negligible subdiagonal (block max)
     int lk = 0;
     for (int k = 1 + tid; k <= ihi; k += NT)
-      if (cabs1(at(k, k - 1)) <= tol) lk = max(lk, k);
+      if (cabs1(at(k, k - 1)) <= fmax(tol * (cabs1(at(k - 1, k - 1)) + cabs1(at(k, k))), DBL_MIN)) lk = max(lk, k);
     for (int o = 32; o > 0; o >>= 1) lk = max(lk, __shfl_xor(lk, o, 64));
     if (lane == 0) redi[wave] = lk;
     __syncthreads();
@@ -542,8 +553,12 @@ __global__ __launch_bounds__(NT) void k_unitary_eig_wg(const double2 *W, int m, 
     if (l > 0 && tid == 0) at(l, l - 1) = make_double2(0.0, 0.0);
     double2 mu;
     const double2 dd = at(ihi, ihi);
-    if (its == 10 || its == 20) {
+    // exceptional shifts every 10 steps without a deflation (as in k_unitary_eig)
+    if (its > 0 && its % 20 == 10) {
       mu = make_double2(dd.x + 0.75 * cabs1(at(ihi, ihi - 1)), dd.y);
+    } else if (its > 0 && its % 20 == 0) {
+      const double2 dl = at(l, l);
+      mu = make_double2(dl.x + 0.75 * cabs1(at(l + 1, l)), dl.y);
     } else {
       const double2 a = at(ihi - 1, ihi - 1), b = at(ihi - 1, ihi), c = at(ihi, ihi - 1);
       const double2 t = make_double2(0.5 * (a.x - dd.x), 0.5 * (a.y - dd.y));
@@ -1539,6 +1554,7 @@ int spin_operator_eig(be_ctx *ctx, const void *U, int32_t N, int32_t m, int32_t 
     g.batch = n_k;
     g.tag = "pso";
     g.herm = true;  // U^H S U is Hermitian: lower tiles computed, mirrored (bitwise Hermitian for the eigensolver)
+    g.four_mult = true;  // diagonal tiles bitwise Hermitian too
     BE_RET_IF(zgemm(ctx, g, stream));
   }
   // ---- eigh of the m x m projected spin operator (all bands)
