@@ -973,6 +973,11 @@ def main_served(args):
         "phase_err_vs_fp64_rad": gate, "phase_gate_1e-6_ok": None if max_err is None else bool(max_err <= 1e-6),
         "valid_requests": int(sum(1 for r in reqs if int(np.asarray(r.result["status"]).max()) == 0
                                   and not r.result["eig_status"])),
+        # OR of the status words per request type (4 = WINDING_UNRESOLVED: the
+        # phases stand, the grid does not resolve an integer winding)
+        "status_by_type": {k: int(np.bitwise_or.reduce([int(np.bitwise_or.reduce(
+            np.asarray(r.result["status"], dtype=np.int64).ravel())) for r in reqs if r.tag == k]))
+            for k in syn.SERVED_TYPES if any(r.tag == k for r in reqs)},
         "kernels": kernels,
     }
     print(json.dumps(out))
