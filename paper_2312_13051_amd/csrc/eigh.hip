@@ -1961,8 +1961,12 @@ static int eigh_refined_chunk(be_ctx *ctx, const double2 *H, int N, int ld, int6
       BE_RET_IF(zg(N, m, N - hi, 0, Uall + int64_t(hi) * N, N, NN, S2 + lo, nc, sS2, U, ldu, us, 1.0, "refine_corr"));
   }
   // Newton-Schulz orthonormalization in FP64, ping-pong between U (buffer 0)
-  // and the left half of GU (buffer 1); a matrix whose error is below 1e-6
-  // takes its last step, which leaves about 1e-12
+  // and the left half of GU (buffer 1); a matrix whose error is below 1e-8
+  // takes its last step, which leaves rounding (a last step from 1e-6 left
+  // about 1e-12, enough to spread the +-1 eigenvalues of a projected spin
+  // operator formed from these vectors over 1e-12, where the eigensolver's
+  // cluster tolerance splits them into nearly parallel inverse-iteration
+  // vectors)
   struct Buf {
     double2 *p;
     int ld;
@@ -1997,7 +2001,7 @@ static int eigh_refined_chunk(be_ctx *ctx, const double2 *H, int N, int ld, int6
     g.act = act;
     BE_RET_IF(zgemm(ctx, g, stream));
     hipLaunchKernelGGL(ns_prep_cplx, dim3(static_cast<uint32_t>(nb)), dim3(PT), 0, stream, Gm, m, err, act, 1e-14,
-                       1e-6);
+                       1e-8);
     BE_RET_IF(check_launch(ctx, "ns_prep_cplx"));
     ZGemm h;  // Y = X (3 I - Gm) / 2
     h.M = N;
