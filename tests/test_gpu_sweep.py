@@ -149,3 +149,26 @@ def test_split_bf16_spin_resolved_loop_states_its_error():
         assert int(got["status"].cpu().numpy()[0]) == 0
     finally:
         c.close()
+
+
+def test_refined_spin_operator_keeps_its_clusters():
+    """Refined path on a spin-conserving BHZ 10x10 supercell: the window's
+    vectors are orthonormal to rounding, so the projected spin operator's
+    eigenvalues are +-1 within 1e-12 (one cluster each for its eigensolver;
+    vectors orthonormal only to ~1e-12 spread them over ~5e-12, where the
+    cluster tolerance cut them into nearly parallel inverse-iteration
+    vectors), and the loop is unflagged with C_s = 1."""
+    gu.need_gpu()
+    hl = syn.bhz_disordered(10, 1.0, [80, 1])
+    kg = syn.kplane(6, 4)
+    sd = syn.bhz_spin_diag(hl)[None]
+    c = gu.ctx()
+    try:
+        g = PL.eig_grid(c, c.hk_plan([hl]), 0, 1, kg, 0, hl.N // 2, L.BE_MIXED_FP32_REFINED)
+        out = PL.spin(c, g, sd, precision=L.BE_MIXED_FP32_REFINED)
+        mu = out["mu"].cpu().numpy()
+        assert float(np.max(np.abs(np.abs(mu) - 1.0))) < 1e-12
+        assert int(out["status"].cpu().numpy()[0]) == 0
+        assert float(out["C_s"].cpu().numpy()[0]) == 1.0
+    finally:
+        c.close()
